@@ -1,0 +1,227 @@
+"""Throughput benchmark: DPA-1 energy + forces + virial steps on one MI355X.
+
+Workload: the protein-shaped periodic system (15,668 atoms in a 53.9 A cube,
+H/C/N/O/S = 0.64/0.10/0.03/0.22/0.01, jittered lattice at 0.1 atoms/A^3), the
+seeded random-init DPA-1 model (type embedding 8, embedding 25/50/100,
+axis 16, 2 attention layers of width 128, fitting 240/240/240), rcut 6 A,
+sel 120.  100 frames of a cumulative N(0, 0.01 A) random walk are generated
+on the host and uploaded before timing; step k evaluates frame k mod 100.
+One step = neighbour-list rebuild + forward + input-gradient adjoint + forces
++ virial (dp_compute_device on device-resident inputs).
+
+Prints one JSON line on stdout; a per-kernel table goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+RCUT = 6.0
+SEL = 120
+N_FRAMES = 100
+FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+METRIC = "atom-steps/s E+F at 15,668 atoms: FP32 vs BF16 vs student, at force RMSE"
+
+
+def flop_model(nnei: np.ndarray, shape) -> dict:
+    """Algorithmic FLOPs per step of each kernel, at the actual neighbour counts.
+
+    Multiply-adds count 2 FLOPs; forward plus input-gradient adjoint only;
+    neither padding nor the recomputation of the logits in the attention
+    backward is counted.  Returns {kernel: (flops per step, launches per step)}.
+    """
+    P = float(nnei.sum())
+    n2 = float((nnei.astype(np.float64) ** 2).sum())
+    nloc = float(len(nnei))
+    M, d, L = shape["M"], shape["dattn"], shape["n_attn"]
+    emb = shape["emb"]
+    fin0 = M * shape["axis"] + shape["tebd"]
+    f = shape["fit"]
+    fit = 2.0 * (fin0 * f[0] + sum(f[i] * f[i + 1] for i in range(len(f) - 1)) + f[-1]) * nloc
+    emb_gemm = 2.0 * sum(emb[i] * emb[i + 1] for i in range(len(emb) - 1)) * P
+    return {
+        "env_embed1": (2.0 * (1 + 2 * shape["tebd"]) * emb[0] * P, 1),
+        "emb_fwd": (emb_gemm, len(emb) - 1),
+        "qkv_fwd": (L * 2.0 * M * 3 * d * P, L),
+        "attn_fwd": (L * 2.0 * 2 * d * n2, L),
+        "oproj_ln_fwd": (L * 2.0 * d * M * P, L),
+        "desc_fwd": (2.0 * 4 * M * P + 2.0 * 4 * M * shape["axis"] * nloc, 1),
+        "fit_fwd": (fit, len(f)),
+        "fit_bwd": (fit, len(f)),
+        "desc_bwd": (2.0 * 2 * 4 * M * P + 2.0 * 2 * 4 * M * shape["axis"] * nloc, 1),
+        "oproj_bwd": (L * 2.0 * d * M * P, L),
+        "attn_bwd": (L * 2.0 * 4 * d * n2, L),
+        "qkv_bwd": (L * 2.0 * M * 3 * d * P, L),
+        "emb_bwd": (emb_gemm, len(emb) - 1),
+    }
+
+
+def cpu_baseline(weights_path, sysm, budget_s: float) -> dict:
+    """The FP64 CPU oracle on a bounded sample of the same frame."""
+    import torch
+
+    from oracle import dpa1_oracle as orc
+    om = orc.load_model(weights_path)
+    n = len(sysm.coords)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(n)
+    done = 0
+    t0 = time.perf_counter()
+    chunk = 128
+    while time.perf_counter() - t0 < budget_s and done < n:
+        cs = np.sort(order[done:done + chunk])
+        orc.evaluate_centers(om, sysm.coords, sysm.types, sysm.box, RCUT, SEL, cs)
+        done += len(cs)
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "atom-steps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{done} random centres of the 15,668-atom frame, each with a "
+                      f"brute-force neighbour search, FP64 energy and autograd pair "
+                      f"gradients ({dt:.1f} s); the rate is centres per second"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the DPA-1 step of one domain is measured on "
+              "one MI355X; multi-GPU runs are not part of this benchmark.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_07276_amd import binding, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    tmpdir = tempfile.mkdtemp()
+    wpath = os.path.join(tmpdir, "dpa1_seed0.bin")
+    shp = synth.make_weights(wpath, seed=0)
+    model = binding.Model(wpath, RCUT, SEL)
+
+    sysm = synth.protein_system(0)
+    n = len(sysm.coords)
+    frames = synth.perturbed_frames(sysm, N_FRAMES, 0.01)
+    d_frames = torch.tensor(frames, device=dev)
+    d_types = torch.tensor(sysm.types, device=dev)
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    f = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    v = torch.zeros(9, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    box = sysm.box
+
+    def step(k):
+        model.compute_device(d_frames[k % N_FRAMES], d_types, box, n, 0, e, f, v, None, stream)
+
+    for k in range(args.warmup):
+        step(k)
+    model.sync()
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(k)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    model.sync()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    value = n * args.steps / (ms_total / 1e3)
+    E_last = float(e.cpu()[0])
+    F_last = f.cpu().numpy()
+    assert np.isfinite(E_last) and np.all(np.isfinite(F_last))
+
+    # neighbour statistics of frame 0 for the FLOP model
+    step(0)
+    model.sync()
+    _, nnei = model.debug_nlist(n)
+    shape = {"M": shp.emb[-1], "dattn": shp.attn_dim, "emb": shp.emb, "axis": shp.axis,
+             "tebd": shp.tebd_dim, "fit": shp.fit, "n_attn": shp.n_attn}
+    flops = flop_model(nnei, shape)
+    step_flops = sum(fl for fl, _ in flops.values())
+
+    roofline = None
+    if not args.no_kernel_timing:
+        # second pass over the same frames with a HIP event pair around every launch
+        model.set_timing(True)
+        for k in range(args.steps):
+            step(k)
+        model.sync()
+        ktimes = model.kernel_times()
+        model.set_timing(False)
+        tot = sum(ms for _, ms in ktimes.values())
+        print(f"{'kernel':<16}{'launches':>9}{'avg ms':>10}{'share':>8}{'TFLOP/s':>9}",
+              file=sys.stderr)
+        for name, (cnt, ms) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
+            tf = ""
+            if name in flops:
+                tf = f"{flops[name][0] * args.steps / (ms * 1e-3) / 1e12:9.1f}"
+            print(f"{name:<16}{cnt:>9}{ms / cnt:>10.4f}{ms / tot:>8.1%}{tf:>9}", file=sys.stderr)
+        print(f"step: {ms_step:.3f} ms, {step_flops / 1e12:.4f} TFLOP algorithmic, "
+              f"sum of kernel times {tot / args.steps:.3f} ms", file=sys.stderr)
+        dom = max((k for k in ktimes if k in flops), key=lambda k: ktimes[k][1])
+        cnt, ms = ktimes[dom]
+        avg_s = ms / cnt * 1e-3
+        per_launch = flops[dom][0] / flops[dom][1]
+        achieved = per_launch / avg_s / 1e12
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
+                    "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                    "avg_launch_ms": round(ms / cnt, 4),
+                    "flop_per_launch": per_launch,
+                    "step_algorithmic_tflop": round(step_flops / 1e12, 4),
+                    "step_frac": round(step_flops / (ms_step * 1e-3) / 1e12
+                                       / FP32_MFMA_PEAK_TFLOPS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wpath, sysm, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "protein-shaped periodic box, 15,668 atoms, 53.9 A cube, "
+                               "FP32 DPA-1 E+F+virial",
+                   "atoms": n, "rcut": RCUT, "sel": SEL, "mean_neighbours":
+                       round(float(nnei.mean()), 2), "frames": N_FRAMES,
+                   "model": "DPA-1 random-init seed 0: tebd 8, emb 25/50/100, axis 16, "
+                            "2 attention layers x 128, fitting 240x3",
+                   "precision": "fp32"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    model.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * dpa1.h - C ABI of the MI355X DPA-1 inference library.
+ *
+ * One call evaluates a DPA-1 deep potential for one MD step on one domain:
+ * the energy of the local atoms, the forces on local and ghost atoms and the
+ * virial.  This mirrors the per-step inference call of a DeePMD-style model
+ * inside a domain-decomposed MD engine: the caller flags which atoms are
+ * local and which are ghosts, energies are summed over local atoms only and
+ * ghost forces are returned for the caller to reduce onto their owners
+ * (Sec. II-C, Eq. (7)).  The library is not MPI-aware; it sees one domain.
+ *
+ * Units: Angstrom and eV.  Arrays are row-major, atoms are ordered locals
+ * first, then ghosts: atom k is local iff k < nloc.
+ *
+ * Model: energy E = sum_{i<nloc} e_i with e_i = Phi(D^i) (Sec. II-B and
+ * Eq. (5)); descriptor D^i = G^T R~ R~^T G_< over the full neighbour list
+ * of i within rcut (Sec. II-B; Sec. II-C full lists); G from a type-embedded
+ * embedding net refined by gated self-attention inside the neighbour set
+ * (Sec. II-B, DPA-1); forces F = -dE/dx (Eq. (2)).
+ *
+ * Precision: neighbour search and minimum-image pair vectors in FP64; the
+ * network in FP32 (FP32 MFMA); energy, force and virial reductions in FP64.
+ * Results are deterministic: the same inputs give bit-identical outputs.
+ *
+ * Ownership: the caller owns every array it passes.  A dp_model owns its
+ * device weights and workspace.  A handle is not thread-safe and must not be
+ * used by two calls at once (one handle per stream).
+ *
+ * Errors: every function returns DP_OK (0) or a negative dp_status;
+ * dp_last_error() gives a message for the calling thread.  Argument checks
+ * run before any device work; on error no output is written.
+ */
+#ifndef DPA1_H
+#define DPA1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dp_model dp_model;
+
+enum dp_status {
+  DP_OK = 0,
+  DP_ERR_ARG = -1,           /* NULL pointer, negative count, rcut/sel out of range */
+  DP_ERR_TYPE = -2,          /* atom type outside [0, ntypes) */
+  DP_ERR_BOX = -3,           /* non-orthorhombic box or a box length <= 2 rcut */
+  DP_ERR_SEL_OVERFLOW = -4,  /* an atom has more than sel neighbours within rcut */
+  DP_ERR_WEIGHTS = -5,       /* weights file missing, malformed or unsupported */
+  DP_ERR_DEVICE = -6,        /* HIP runtime error */
+  DP_ERR_OOM = -7            /* device allocation failed */
+};
+
+/* Largest supported neighbour capacity. */
+#define DP_MAX_SEL 128
+
+/*
+ * Load a weights file and upload the model to the current HIP device.
+ *   weights_path  file in the DPA-1 weights format (magic "DPA1WTS"), FP64
+ *                 tensors; they are rounded to FP32 once here.
+ *   rcut          cutoff radius in Angstrom, > rcut_smth of the file.
+ *   sel           neighbour capacity, 1 <= sel <= DP_MAX_SEL.  It also sets
+ *                 the attention normalisation, which adds (sel - n_i) e^{-S}
+ *                 so that energies stay smooth when a neighbour crosses rcut.
+ *   out           receives the handle; release with dp_destroy.
+ */
+int dp_create(const char *weights_path, double rcut, int sel, dp_model **out);
+
+/*
+ * Host-memory step: copies inputs to the device, runs the step on the
+ * handle's own stream, copies results back and waits.
+ *   coords       [(nloc+nghost)*3] FP64 positions.
+ *   types        [nloc+nghost], each in [0, ntypes).
+ *   box          [9] FP64, rows are the cell vectors (orthorhombic only, each
+ *                length > 2 rcut; minimum image is applied to every pair), or
+ *                NULL for open boundaries (the caller supplies image ghosts).
+ *   nloc, nghost counts, >= 0.
+ *   energy       out: sum of e_i over local atoms.
+ *   forces       out: [(nloc+nghost)*3]; ghost atoms receive
+ *                -sum_{i local} de_i/dx_ghost (Eq. (7)).
+ *   virial       out: [9], Xi_ab = -sum_{i<nloc} sum_j d_ij,a de_i/dd_ij,b
+ *                with d_ij = x_j - x_i (equals sum_k x_k,a F_k,b when open).
+ *   atom_energy  optional out [nloc] (e_i), or NULL.
+ * Returns DP_ERR_SEL_OVERFLOW when some atom (local, or ghost counting its
+ * local neighbours) has more than sel neighbours; nothing is written then.
+ */
+int dp_compute(dp_model *m, const double *coords, const int32_t *types, const double *box,
+               int nloc, int nghost, double *energy, double *forces, double *virial,
+               double *atom_energy);
+
+/*
+ * Device-memory step, asynchronous on the caller's stream (hipStream_t, NULL
+ * for the default stream).  d_coords, d_types, d_energy [1], d_forces, d_virial
+ * [9] and d_atom_energy (optional) are device pointers with the layouts of
+ * dp_compute; box is a host pointer as above.  The call returns after
+ * enqueueing; conditions found on the device (an out-of-range type, a
+ * neighbour overflow) are reported by dp_sync, and the outputs of such a step
+ * are not meaningful.
+ */
+int dp_compute_device(dp_model *m, const double *d_coords, const int32_t *d_types,
+                      const double *box, int nloc, int nghost, double *d_energy,
+                      double *d_forces, double *d_virial, double *d_atom_energy,
+                      void *hip_stream);
+
+/* Wait for the handle's last step and return its device-side status. */
+int dp_sync(dp_model *m);
+
+/*
+ * Neighbour list of the last completed step: nlist [nloc*sel] with the
+ * neighbours of local atom i in ascending index order, padded with -1, and
+ * nnei [nloc].  Host pointers; waits for the step.
+ */
+int dp_debug_nlist(dp_model *m, int32_t *nlist, int32_t *nnei);
+
+/*
+ * Per-kernel timing.  When enabled, every launch of a step is bracketed by
+ * HIP events on its stream.  dp_kernel_times fills, for up to max entries,
+ * the kernel name (NUL-terminated, 48 bytes each), the launch count and the
+ * summed duration in milliseconds since the last reset; it returns the number
+ * of distinct kernels.
+ */
+int dp_set_timing(dp_model *m, int enable);
+int dp_kernel_times(dp_model *m, char *names, int64_t *counts, double *total_ms, int max);
+
+/* Model hyper-parameters: ints[8] = ntypes, tebd_dim, axis, n_attn, attn_dim,
+ * embedding width M, fitting width, sel; dbls[3] = rcut, rcut_smth, attn_shift. */
+int dp_model_info(const dp_model *m, int32_t *ints, double *dbls);
+
+void dp_destroy(dp_model *m);
+
+/* Message for the last nonzero return on the calling thread ("" if none). */
+const char *dp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPA1_H */

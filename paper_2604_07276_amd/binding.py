@@ -1,0 +1,165 @@
+"""Python binding of the DPA-1 C ABI (include/dpa1.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Torch tensors are accepted as device buffers (their data pointers
+are passed through) and torch's current HIP stream is used for the
+device-memory entry point.  There is no fallback: if the library is not
+built or cannot be loaded, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpa1.so")
+
+DP_OK = 0
+STATUS_NAMES = {
+    -1: "DP_ERR_ARG", -2: "DP_ERR_TYPE", -3: "DP_ERR_BOX", -4: "DP_ERR_SEL_OVERFLOW",
+    -5: "DP_ERR_WEIGHTS", -6: "DP_ERR_DEVICE", -7: "DP_ERR_OOM",
+}
+EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_sync", "dp_debug_nlist",
+            "dp_set_timing", "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error")
+
+_lib = None
+
+
+class DPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdpa1.so (built in-tree) and declare the signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2604_07276_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    lib.dp_create.argtypes = [ctypes.c_char_p, D, I, ctypes.POINTER(P)]
+    lib.dp_compute.argtypes = [P, P, P, P, I, I, P, P, P, P]
+    lib.dp_compute_device.argtypes = [P, P, P, P, I, I, P, P, P, P, P]
+    lib.dp_sync.argtypes = [P]
+    lib.dp_debug_nlist.argtypes = [P, P, P]
+    lib.dp_set_timing.argtypes = [P, I]
+    lib.dp_kernel_times.argtypes = [P, P, P, P, I]
+    lib.dp_model_info.argtypes = [P, P, P]
+    lib.dp_destroy.argtypes = [P]
+    lib.dp_destroy.restype = None
+    lib.dp_last_error.argtypes = []
+    lib.dp_last_error.restype = ctypes.c_char_p
+    for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_sync", "dp_debug_nlist",
+                 "dp_set_timing", "dp_kernel_times", "dp_model_info"):
+        getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise DPError(rc, _lib.dp_last_error().decode())
+    return rc
+
+
+def _ptr(a) -> int | None:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class Model:
+    """A loaded DPA-1 model on the current HIP device (dp_create / dp_destroy)."""
+
+    def __init__(self, weights_path: str, rcut: float, sel: int):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.dp_create(weights_path.encode(), float(rcut), int(sel), ctypes.byref(h)))
+        self._h = h
+        self.rcut = float(rcut)
+        self.sel = int(sel)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        ints = np.zeros(8, dtype=np.int32)
+        dbls = np.zeros(3)
+        _check(_lib.dp_model_info(self._h, ints.ctypes.data, dbls.ctypes.data))
+        return ints, dbls
+
+    def compute(self, coords, types, box, nloc: int, nghost: int, atom_energy: bool = False):
+        """Host-memory step (dp_compute).  Returns (E, F [N,3], virial [3,3], e_i or None)."""
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        types = np.ascontiguousarray(types, dtype=np.int32)
+        boxa = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        nall = nloc + nghost
+        E = np.zeros(1)
+        F = np.zeros((nall, 3))
+        V = np.zeros(9)
+        AE = np.zeros(max(nloc, 1)) if atom_energy else None
+        _check(_lib.dp_compute(self._h, _ptr(coords) if nall else None,
+                               _ptr(types) if nall else None, _ptr(boxa), nloc, nghost,
+                               E.ctypes.data, F.ctypes.data if nall else None, V.ctypes.data,
+                               _ptr(AE)))
+        return float(E[0]), F, V.reshape(3, 3), (AE[:nloc] if atom_energy else None)
+
+    def compute_device(self, coords, types, box, nloc: int, nghost: int, energy, forces, virial,
+                       atom_energy=None, stream=None):
+        """Device-memory step (dp_compute_device), asynchronous on ``stream``.
+
+        coords (float64 [N,3]), types (int32 [N]), energy (float64 [1]), forces
+        (float64 [N,3]), virial (float64 [9]) and atom_energy (float64 [nloc] or
+        None) are torch CUDA tensors; box is host data or None.
+        """
+        import torch
+        boxa = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(_lib.dp_compute_device(self._h, _ptr(coords), _ptr(types), _ptr(boxa), nloc,
+                                      nghost, _ptr(energy), _ptr(forces), _ptr(virial),
+                                      _ptr(atom_energy), sp))
+
+    def sync(self):
+        """Wait for the last step; raises on a device-side error (overflow, bad type)."""
+        _check(_lib.dp_sync(self._h))
+
+    def debug_nlist(self, nloc: int):
+        nl = np.zeros((max(nloc, 1), self.sel), dtype=np.int32)
+        nn = np.zeros(max(nloc, 1), dtype=np.int32)
+        _check(_lib.dp_debug_nlist(self._h, nl.ctypes.data, nn.ctypes.data))
+        return nl[:nloc], nn[:nloc]
+
+    def set_timing(self, enable: bool):
+        _check(_lib.dp_set_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self) -> dict:
+        n = _check(_lib.dp_kernel_times(self._h, None, None, None, 0))
+        names = ctypes.create_string_buffer(48 * max(n, 1))
+        counts = np.zeros(max(n, 1), dtype=np.int64)
+        ms = np.zeros(max(n, 1))
+        _check(_lib.dp_kernel_times(self._h, names, counts.ctypes.data, ms.ctypes.data, n))
+        out = {}
+        for k in range(n):
+            nm = names.raw[48 * k:48 * (k + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (int(counts[k]), float(ms[k]))
+        return out

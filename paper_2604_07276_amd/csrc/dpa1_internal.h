@@ -1,0 +1,150 @@
+// Internal declarations shared by the host orchestration and the HIP kernels
+// of the DPA-1 library.  Not part of the public ABI (that is include/dpa1.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpa1 {
+
+// ---------------------------------------------------------------------------
+// Padded widths.  Activations are stored row-major with a row stride that is
+// the width rounded up to 16 (one MFMA k-chunk); the pad columns hold zeros.
+// ---------------------------------------------------------------------------
+constexpr int kPad = 16;
+inline int pad16(int x) { return (x + kPad - 1) / kPad * kPad; }
+
+// Geometry record of one neighbour pair (8 floats):
+//   s = sw/r, rhat (3), sw, r, dsw/dr, unused.
+enum GeomField { G_S = 0, G_RX = 1, G_RY = 2, G_RZ = 3, G_SW = 4, G_R = 5, G_DSW = 6 };
+constexpr int kGeom = 8;
+
+// Cell grid used for the O(N) neighbour search.
+struct CellGrid {
+  int periodic;
+  int nc[3];
+  int ncell;
+  double lo[3];        // origin of the grid (0 when periodic)
+  double L[3];         // box lengths (periodic only)
+  double inv_edge[3];  // cells per Angstrom
+};
+
+// Device status flags of one step.
+struct DevFlags {
+  int overflow_atom;   // smallest atom index with more than sel neighbours, INT_MAX if none
+  int overflow_count;  // its neighbour count
+  int bad_type_atom;   // smallest atom index with an invalid type, INT_MAX if none
+  int pad_;
+};
+
+// ---------------------------------------------------------------------------
+// neighbour search (nlist.hip)
+// ---------------------------------------------------------------------------
+void launch_check_types(const int32_t *types, int nall, int ntypes, DevFlags *flags,
+                        int32_t *safe, hipStream_t s);
+void launch_cell_bin(const double *coords, int nall, CellGrid grid, int *atom_cell,
+                     int *cell_count, hipStream_t s);
+void launch_scan(const int *in, int n, int *out_excl, hipStream_t s);  // out[n] = total
+void launch_cell_fill(const int *atom_cell, int nall, const int *cell_start, int *cell_fill,
+                      int *cell_atoms, hipStream_t s);
+void launch_nlist(const double *coords, int nloc, int nall, CellGrid grid, double rcut,
+                  int sel, const int *atom_cell, const int *cell_start, const int *cell_atoms,
+                  int *nlist, int *nnei, DevFlags *flags, hipStream_t s);
+// Per pair: geometry record and the first embedding layer
+// h1 = tanh(type_table[t_j][t_i] + ws * s), 25 -> stride 32.
+void launch_env_embed1(const double *coords, const int32_t *types, CellGrid grid, int nloc,
+                       int sel, double rcut, double rcut_smth, const int *nlist, const int *nnei,
+                       const int *pair_off, const float *type_table, const float *ws, int ntypes,
+                       int n1, int ld1, float *geom, float *h1, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// row-batched FP32 MFMA GEMMs with fused epilogues (gemm.hip)
+//   Y[M x N] = X[M x K] W[K x N], W passed transposed as Wt[Npad x K].
+//   M is read from device memory (*Mptr) when Mptr != nullptr.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  const float *X;
+  int ldx;
+  const float *Wt;
+  int K;          // multiple of 16
+  int Npad;       // multiple of 16
+  int Nreal;
+  const int *Mptr;
+  int Mmax;       // grid sizing bound
+};
+
+enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_FOLD = 4 };
+
+// y = tanh(acc + b) + res ; optionally also stores the tanh output.
+// Per-row bias: bias + row_type[row] * bias_ld when row_type != nullptr.
+void gemm_tanh_res(const GemmArgs &a, const float *bias, const int32_t *row_type, int bias_ld,
+                   const float *res, int ldr, int res_mode, int res_fin, float *y, int ldy,
+                   float *tout, int ldt, hipStream_t s);
+// y = acc + b (b may be null)
+void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s);
+// Attention output projection with layer norm and residual:
+//   yv = acc + b; xhat = (yv - mean) * rstd; gout = gin + gamma*xhat + beta.
+void gemm_ln_res(const GemmArgs &a, const float *bias, const float *gamma, const float *beta,
+                 float eps, const float *gin, int ldg, float *gout, float *xhat, float *rstd,
+                 hipStream_t s);
+// Backward through a tanh layer: d = acc + res; a = d * (1 - t^2).
+void gemm_bwd_tanh(const GemmArgs &a, const float *res, int ldr, int res_mode, int res_fin,
+                   const float *t, int ldt, float *d, int ldd, float *aout, int lda,
+                   hipStream_t s);
+// Backward of the attention input projections:
+//   dgin = acc + dgout; then either the layer-norm backward of the previous
+//   layer (mode 0: dy = rstd*(gamma*dgin - mean(.) - xhat*mean(gamma*dgin*xhat)))
+//   or the embedding tanh backward (mode 1: du = dgin * (1 - t^2)).
+void gemm_qkv_bwd(const GemmArgs &a, const float *dgout, int mode, const float *gamma,
+                  const float *xhat, const float *rstd, const float *t, float *dgin,
+                  float *dnext, hipStream_t s);
+// First embedding layer backward: dh1 = acc + residual(dh2) (RES_NONE, RES_IDENT or
+// RES_FOLD); du1 = dh1 * (1 - h1^2); gs[row] = sum_o du1[o] * ws[o].
+void gemm_emb1_bwd(const GemmArgs &a, const float *dh2, int ldd2, int res_mode, int fin,
+                   const float *h1, int ldh1, const float *ws, float *gs, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// per-centre kernels (attn.hip)
+// ---------------------------------------------------------------------------
+// Gated neighbour self-attention core, forward: O = (P o H) V per centre.
+void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, const int *nnei,
+                     int nloc, int sel, int dattn, float shift, float *out, hipStream_t s);
+// Backward of the core: dQKV, and accumulation of dE/dsw and dE/drhat per pair.
+size_t attn_bwd_lds_bytes();
+hipError_t set_attn_bwd_lds_limit();
+void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
+                     const int *pair_off, const int *nnei, int nloc, int sel, int dattn,
+                     float shift, float *dqkv, float *gw, float *gr, int accumulate,
+                     hipStream_t s);
+// Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].
+void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,
+                     const int *nnei, int nloc, int sel, int M, int axis, float *T, float *dmat,
+                     hipStream_t s);
+// Descriptor backward and the layer-norm backward of the last attention layer.
+void launch_desc_bwd(const float *geom, const float *G, int ldg, const float *T,
+                     const float *dD, const int *pair_off, const int *nnei, int nloc, int sel,
+                     int M, int axis, int ln_mode, const float *gamma, const float *xhat,
+                     const float *rstd, const float *t_emb, float *dG, float *dnext,
+                     float *dRt, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// energies, pair gradients, forces, virial (misc.hip)
+// ---------------------------------------------------------------------------
+// e_i = z3 . w_out + b_out + ebias[type_i]; a3 = w_out * (1 - t3^2).
+void launch_energy(const float *z3, const float *t3, int ld, int nfit, const float *w_out,
+                   float b_out, const float *ebias, const int32_t *types, int nloc, float *e,
+                   float *a3, hipStream_t s);
+// g_ij = de_i/dd_ij from the per-pair upstream gradients.
+void launch_env_bwd(const float *geom, const float *gs, const float *dRt, const float *gw,
+                    const float *gr, const int *Mptr, int Mmax, float sel_inv_unused,
+                    float *g, hipStream_t s);
+// Forces by a deterministic gather over the full neighbour lists, per-centre
+// virial partials and FP64 outputs.
+void launch_forces(const double *coords, CellGrid grid, int nloc, int nall, int sel,
+                   const int *nlist, const int *nnei, const int *pair_off, const float *g,
+                   double *forces, double *vir_part, hipStream_t s);
+// E = sum e_i, Xi = sum of partials (fixed-order FP64 reductions); atom_energy.
+void launch_reduce(const float *e, const double *vir_part, int nloc, double *energy,
+                   double *virial, double *atom_energy, hipStream_t s);
+
+}  // namespace dpa1

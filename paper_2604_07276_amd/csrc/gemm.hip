@@ -1,0 +1,475 @@
+// Row-batched FP32 GEMMs on the CDNA matrix cores, with fused epilogues.
+//
+// Every multilayer-perceptron layer of the model (the embedding net, the
+// attention input/output projections and the fitting net, Sec. II-B) and its
+// input-gradient adjoint is a product Y[M x N] = X[M x K] W[K x N] with a
+// small weight matrix shared by all rows (neighbour pairs or centres).
+//
+// Tiling: one wavefront owns 16*MT rows and NT tiles of 16 output columns.
+// The kernel computes the transposed product Y^T = W^T X^T with
+// v_mfma_f32_16x16x4_f32 so that the accumulator layout gives each lane four
+// consecutive output columns of one row: lane l holds row (l % 16) and
+// columns 4*(l / 16) + {0..3} of every 16x16 tile, which makes the epilogue
+// stores 16-byte vector stores and the per-row reductions of the layer norm
+// a register sum plus two cross-lane steps.  Both operands are read as
+// 16-byte vectors along k straight from global memory (W is stored
+// transposed, Wt[n][k]); the k index of a 16-wide chunk is permuted
+// identically on both operands, which leaves the contraction unchanged.
+#include "dpa1_internal.h"
+
+namespace dpa1 {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float row_sum16(float v) {
+  // sum over the four lane groups that share (lane % 16)
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+template <int MT, int NT, class Epi>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a, Epi epi) {
+  const int M = a.Mptr ? *a.Mptr : a.Mmax;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  if (row0 >= M) return;
+  const int nt0 = blockIdx.y * NT;
+  const int ntt = a.Npad / 16;
+  const int r = lane & 15;
+  const int g = lane >> 4;
+
+  floatx4 acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const float *xrow[MT];
+  bool xok[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = row0 + mt * 16 + r;
+    xok[mt] = row < M;
+    xrow[mt] = a.X + (size_t)(xok[mt] ? row : 0) * a.ldx + 4 * g;
+  }
+  const float *wrow[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+    wrow[nt] = a.Wt + (size_t)(tile * 16 + r) * a.K + 4 * g;
+  }
+
+  for (int k0 = 0; k0 < a.K; k0 += 16) {
+    floatx4 xv[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      xv[mt] = xok[mt] ? *(const floatx4 *)(xrow[mt] + k0) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (nt0 + nt >= ntt) continue;
+      const floatx4 wv = *(const floatx4 *)(wrow[nt] + k0);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        acc[mt][nt] = mfma4(wv[0], xv[mt][0], acc[mt][nt]);
+        acc[mt][nt] = mfma4(wv[1], xv[mt][1], acc[mt][nt]);
+        acc[mt][nt] = mfma4(wv[2], xv[mt][2], acc[mt][nt]);
+        acc[mt][nt] = mfma4(wv[3], xv[mt][3], acc[mt][nt]);
+      }
+    }
+  }
+  epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
+}
+
+// ------------------------------------------------------------------ epilogues
+
+struct EpiLinear {
+  const float *bias;
+  float *y;
+  int ldy;
+  int Nreal;
+  template <int MT, int NT>
+  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+                        int M) const {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      if (row >= M) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt0 + nt >= ntt) continue;
+        const int n0 = (nt0 + nt) * 16 + 4 * g;
+        floatx4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + v;
+          o[v] = n < Nreal ? acc[mt][nt][v] + (bias ? bias[n] : 0.f) : 0.f;
+        }
+        *(floatx4 *)(y + (size_t)row * ldy + n0) = o;
+      }
+    }
+  }
+};
+
+struct EpiTanhRes {
+  const float *bias;
+  const int32_t *row_type;
+  int bias_ld;
+  const float *res;
+  int ldr;
+  int res_mode;
+  int res_fin;
+  float *y;
+  int ldy;
+  float *tout;
+  int ldt;
+  int Nreal;
+  template <int MT, int NT>
+  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+                        int M) const {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      if (row >= M) continue;
+      const float *b = bias + (row_type ? (size_t)row_type[row] * bias_ld : 0);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt0 + nt >= ntt) continue;
+        const int n0 = (nt0 + nt) * 16 + 4 * g;
+        floatx4 o, tv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + v;
+          if (n < Nreal) {
+            const float t = tanhf(acc[mt][nt][v] + b[n]);
+            float rr = 0.f;
+            if (res_mode == RES_IDENT) rr = res[(size_t)row * ldr + n];
+            else if (res_mode == RES_DOUBLE) rr = res[(size_t)row * ldr + n % res_fin];
+            o[v] = t + rr;
+            tv[v] = t;
+          } else {
+            o[v] = 0.f;
+            tv[v] = 0.f;
+          }
+        }
+        *(floatx4 *)(y + (size_t)row * ldy + n0) = o;
+        if (tout) *(floatx4 *)(tout + (size_t)row * ldt + n0) = tv;
+      }
+    }
+  }
+};
+
+// Output projection + layer norm + residual (all output columns in one wave).
+struct EpiLNRes {
+  const float *bias, *gamma, *beta;
+  float eps;
+  const float *gin;
+  int ld;  // row stride of gin, gout, xhat (= Npad)
+  float *gout, *xhat, *rstd;
+  int Nreal;
+  template <int MT, int NT>
+  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+                        int M) const {
+    const int r = lane & 15, g = lane >> 4;
+    const float invn = 1.0f / (float)Nreal;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      const bool ok = row < M;
+      float s1 = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          if (nt < ntt && n < Nreal) {
+            acc[mt][nt][v] += bias[n];
+            s1 += acc[mt][nt][v];
+          }
+        }
+      }
+      const float mean = row_sum16(s1) * invn;
+      float s2 = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          if (nt < ntt && n < Nreal) {
+            const float c = acc[mt][nt][v] - mean;
+            s2 += c * c;
+          }
+        }
+      }
+      const float var = row_sum16(s2) * invn;
+      const float rs = 1.0f / sqrtf(var + eps);
+      if (!ok) continue;
+      if (g == 0) rstd[row] = rs;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt >= ntt) continue;
+        const int n0 = nt * 16 + 4 * g;
+        const floatx4 gi = *(const floatx4 *)(gin + (size_t)row * ld + n0);
+        floatx4 go, xh;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + v;
+          if (n < Nreal) {
+            const float x = (acc[mt][nt][v] - mean) * rs;
+            xh[v] = x;
+            go[v] = gi[v] + gamma[n] * x + beta[n];
+          } else {
+            xh[v] = 0.f;
+            go[v] = 0.f;
+          }
+        }
+        *(floatx4 *)(gout + (size_t)row * ld + n0) = go;
+        *(floatx4 *)(xhat + (size_t)row * ld + n0) = xh;
+      }
+    }
+  }
+};
+
+// d = acc + residual gradient ; a = d * (1 - t^2)
+struct EpiBwdTanh {
+  const float *res;
+  int ldr;
+  int res_mode;
+  int res_fin;
+  const float *t;
+  int ldt;
+  float *d;
+  int ldd;
+  float *aout;
+  int lda;
+  int Nreal;
+  template <int MT, int NT>
+  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+                        int M) const {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      if (row >= M) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt0 + nt >= ntt) continue;
+        const int n0 = (nt0 + nt) * 16 + 4 * g;
+        floatx4 dv, av;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + v;
+          if (n < Nreal) {
+            float x = acc[mt][nt][v];
+            if (res_mode == RES_IDENT) x += res[(size_t)row * ldr + n];
+            else if (res_mode == RES_BCAST) x += res[n];
+            else if (res_mode == RES_FOLD)
+              x += res[(size_t)row * ldr + n] + res[(size_t)row * ldr + n + res_fin];
+            const float tt = t[(size_t)row * ldt + n];
+            dv[v] = x;
+            av[v] = x * (1.0f - tt * tt);
+          } else {
+            dv[v] = 0.f;
+            av[v] = 0.f;
+          }
+        }
+        if (d) *(floatx4 *)(d + (size_t)row * ldd + n0) = dv;
+        *(floatx4 *)(aout + (size_t)row * lda + n0) = av;
+      }
+    }
+  }
+};
+
+// dgin = acc + dgout ; then layer-norm backward (mode 0) or tanh backward (mode 1).
+struct EpiQKVBwd {
+  const float *dgout;
+  int mode;
+  const float *gamma, *xhat, *rstd, *t;
+  int ld;
+  float *dgin, *dnext;
+  int Nreal;
+  template <int MT, int NT>
+  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+                        int M) const {
+    const int r = lane & 15, g = lane >> 4;
+    const float invn = 1.0f / (float)Nreal;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      const bool ok = row < M;
+      const size_t rb = (size_t)(ok ? row : 0) * ld;
+      float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt >= ntt) continue;
+        const int n0 = nt * 16 + 4 * g;
+        const floatx4 go = *(const floatx4 *)(dgout + rb + n0);
+        floatx4 xh = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (mode == 0) xh = *(const floatx4 *)(xhat + rb + n0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = n0 + v;
+          if (n < Nreal) {
+            acc[mt][nt][v] += go[v];
+            if (mode == 0) {
+              const float dx = gamma[n] * acc[mt][nt][v];
+              s1 += dx;
+              s2 += dx * xh[v];
+            }
+          } else {
+            acc[mt][nt][v] = 0.f;
+          }
+        }
+      }
+      float m1 = 0.f, m2 = 0.f, rs = 0.f;
+      if (mode == 0) {
+        m1 = row_sum16(s1) * invn;
+        m2 = row_sum16(s2) * invn;
+        rs = ok ? rstd[row] : 0.f;
+      }
+      if (!ok) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt >= ntt) continue;
+        const int n0 = nt * 16 + 4 * g;
+        floatx4 dn;
+        if (mode == 0) {
+          const floatx4 xh = *(const floatx4 *)(xhat + rb + n0);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = n0 + v;
+            dn[v] = n < Nreal ? rs * (gamma[n] * acc[mt][nt][v] - m1 - xh[v] * m2) : 0.f;
+          }
+        } else {
+          const floatx4 tt = *(const floatx4 *)(t + rb + n0);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dn[v] = acc[mt][nt][v] * (1.0f - tt[v] * tt[v]);
+        }
+        *(floatx4 *)(dgin + rb + n0) = acc[mt][nt];
+        *(floatx4 *)(dnext + rb + n0) = dn;
+      }
+    }
+  }
+};
+
+// dh1 = acc + residual(dh2); du1 = dh1 * (1 - h1^2); gs = sum_o du1[o] * ws[o]
+struct EpiEmb1Bwd {
+  const float *dh2;
+  int ldd2, res_mode, fin;
+  const float *h1;
+  int ldh1;
+  const float *ws;
+  float *gs;
+  int Nreal;
+  template <int MT, int NT>
+  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+                        int M) const {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      const bool ok = row < M;
+      const size_t rr = (size_t)(ok ? row : 0);
+      float s = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt >= ntt) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          if (n < Nreal) {
+            float d = acc[mt][nt][v];
+            if (res_mode == RES_IDENT) d += dh2[rr * ldd2 + n];
+            else if (res_mode == RES_FOLD) d += dh2[rr * ldd2 + n] + dh2[rr * ldd2 + n + fin];
+            const float h = h1[rr * ldh1 + n];
+            s += d * (1.0f - h * h) * ws[n];
+          }
+        }
+      }
+      s = row_sum16(s);
+      if (ok && g == 0) gs[row] = s;
+    }
+  }
+};
+
+template <class Epi, int MT>
+void dispatch_nt(const GemmArgs &a, const Epi &e, int nt, hipStream_t s) {
+  const int ntt = a.Npad / 16;
+  const unsigned gx = (unsigned)((a.Mmax + 64 * MT - 1) / (64 * MT));
+  const unsigned gy = (unsigned)((ntt + nt - 1) / nt);
+  if (gx == 0) return;
+  dim3 grid(gx, gy), block(256);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((k_gemm<MT, 1, Epi>), grid, block, 0, s, a, e); break;
+    case 2: hipLaunchKernelGGL((k_gemm<MT, 2, Epi>), grid, block, 0, s, a, e); break;
+    case 3: hipLaunchKernelGGL((k_gemm<MT, 3, Epi>), grid, block, 0, s, a, e); break;
+    case 4: hipLaunchKernelGGL((k_gemm<MT, 4, Epi>), grid, block, 0, s, a, e); break;
+    case 5: hipLaunchKernelGGL((k_gemm<MT, 5, Epi>), grid, block, 0, s, a, e); break;
+    case 6: hipLaunchKernelGGL((k_gemm<MT, 6, Epi>), grid, block, 0, s, a, e); break;
+    case 7: hipLaunchKernelGGL((k_gemm<MT, 7, Epi>), grid, block, 0, s, a, e); break;
+    default: hipLaunchKernelGGL((k_gemm<MT, 8, Epi>), grid, block, 0, s, a, e); break;
+  }
+}
+
+// Rows per wave: two 16-row tiles for the large pair-batched products,
+// one for the centre-batched fitting net (more blocks for fewer rows).
+template <class Epi>
+void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
+  const int ntt = a.Npad / 16;
+  int nt = ntt < 8 ? ntt : 8;
+  if (full_rows && ntt > 8) nt = ntt;  // callers guarantee ntt <= 8 for row reductions
+  if (a.Mmax >= 65536) dispatch_nt<Epi, 2>(a, e, nt, s);
+  else dispatch_nt<Epi, 1>(a, e, nt, s);
+}
+
+}  // namespace
+
+void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s) {
+  EpiLinear e{bias, y, ldy, a.Nreal};
+  run(a, e, false, s);
+}
+
+void gemm_tanh_res(const GemmArgs &a, const float *bias, const int32_t *row_type, int bias_ld,
+                   const float *res, int ldr, int res_mode, int res_fin, float *y, int ldy,
+                   float *tout, int ldt, hipStream_t s) {
+  EpiTanhRes e{bias, row_type, bias_ld, res, ldr, res_mode, res_fin, y, ldy, tout, ldt, a.Nreal};
+  run(a, e, false, s);
+}
+
+void gemm_ln_res(const GemmArgs &a, const float *bias, const float *gamma, const float *beta,
+                 float eps, const float *gin, int ldg, float *gout, float *xhat, float *rstd,
+                 hipStream_t s) {
+  EpiLNRes e{bias, gamma, beta, eps, gin, ldg, gout, xhat, rstd, a.Nreal};
+  run(a, e, true, s);
+}
+
+void gemm_bwd_tanh(const GemmArgs &a, const float *res, int ldr, int res_mode, int res_fin,
+                   const float *t, int ldt, float *d, int ldd, float *aout, int lda,
+                   hipStream_t s) {
+  EpiBwdTanh e{res, ldr, res_mode, res_fin, t, ldt, d, ldd, aout, lda, a.Nreal};
+  run(a, e, false, s);
+}
+
+void gemm_qkv_bwd(const GemmArgs &a, const float *dgout, int mode, const float *gamma,
+                  const float *xhat, const float *rstd, const float *t, float *dgin,
+                  float *dnext, hipStream_t s) {
+  EpiQKVBwd e{dgout, mode, gamma, xhat, rstd, t, a.Npad, dgin, dnext, a.Nreal};
+  run(a, e, true, s);
+}
+
+void gemm_emb1_bwd(const GemmArgs &a, const float *dh2, int ldd2, int res_mode, int fin,
+                   const float *h1, int ldh1, const float *ws, float *gs, hipStream_t s) {
+  EpiEmb1Bwd e{dh2, ldd2, res_mode, fin, h1, ldh1, ws, gs, a.Nreal};
+  run(a, e, true, s);
+}
+
+}  // namespace dpa1

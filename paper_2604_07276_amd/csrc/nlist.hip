@@ -1,0 +1,312 @@
+// Neighbour search and per-pair geometry for DPA-1 inference on gfx950.
+//
+// Full neighbour lists within the cutoff (Sec. II-A: cutoff lists make the
+// cost O(N); Sec. II-C: a DP descriptor needs the full list of every centre).
+// A cell grid with edge >= rcut bins the atoms; one wavefront per centre
+// scans the 27 surrounding cells, tests candidates in FP64 and compacts hits
+// with a ballot.  Lists are sorted by atom index so that every later stage
+// sees a deterministic neighbour order.
+//
+// Pair vectors follow one fixed FP64 recipe, with contraction disabled so
+// the result does not depend on FMA formation:
+//   d = x_j - x_i;  with a box d -= L * rint(d / L);
+//   r2 = (dx*dx + dy*dy) + dz*dz;  neighbour iff r2 < rcut*rcut.
+#include <climits>
+
+#include "dpa1_internal.h"
+
+namespace dpa1 {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kNlistWaves = 4;     // waves per block in the neighbour kernel
+constexpr int kListCap = 128;      // == DP_MAX_SEL
+
+__device__ __forceinline__ void pair_vec(const double *__restrict__ x, int i, int j,
+                                         const CellGrid &g, double d[3]) {
+#pragma clang fp contract(off)
+  for (int c = 0; c < 3; ++c) {
+    double v = x[3 * j + c] - x[3 * i + c];
+    if (g.periodic) v = v - g.L[c] * rint(v / g.L[c]);
+    d[c] = v;
+  }
+}
+
+__device__ __forceinline__ double norm2(const double d[3]) {
+#pragma clang fp contract(off)
+  return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+__device__ __forceinline__ int cell_coord(double x, int c, const CellGrid &g) {
+  double u;
+  if (g.periodic) {
+    double w = x - g.L[c] * floor(x / g.L[c]);
+    u = w * g.inv_edge[c];
+  } else {
+    u = (x - g.lo[c]) * g.inv_edge[c];
+  }
+  int k = (int)floor(u);
+  k = k < 0 ? 0 : k;
+  k = k >= g.nc[c] ? g.nc[c] - 1 : k;
+  return k;
+}
+
+// Flags out-of-range types and writes a clamped copy that every later kernel
+// indexes tables with, so a bad input can never address outside them.
+__global__ void k_check_types(const int32_t *__restrict__ types, int nall, int ntypes,
+                              DevFlags *flags, int32_t *__restrict__ safe) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nall) return;
+  int t = types[k];
+  if (t < 0 || t >= ntypes) {
+    atomicMin(&flags->bad_type_atom, k);
+    t = t < 0 ? 0 : ntypes - 1;
+  }
+  safe[k] = t;
+}
+
+__global__ void k_cell_bin(const double *__restrict__ x, int nall, CellGrid g,
+                           int *__restrict__ atom_cell, int *__restrict__ cell_count) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nall) return;
+  int cx = cell_coord(x[3 * k + 0], 0, g);
+  int cy = cell_coord(x[3 * k + 1], 1, g);
+  int cz = cell_coord(x[3 * k + 2], 2, g);
+  int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+  atom_cell[k] = c;
+  atomicAdd(&cell_count[c], 1);
+}
+
+// Single-block exclusive scan: out[0..n) exclusive prefix sums, out[n] total.
+__global__ __launch_bounds__(1024) void k_scan(const int *__restrict__ in, int n,
+                                               int *__restrict__ out) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b = t * per;
+  const int e = min(b + per, n);
+  int s = 0;
+  for (int k = b; k < e; ++k) s += in[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;  // exclusive prefix of this chunk
+  for (int k = b; k < e; ++k) {
+    out[k] = run;
+    run += in[k];
+  }
+  if (t == 1023) out[n] = part[1023];
+}
+
+__global__ void k_cell_fill(const int *__restrict__ atom_cell, int nall,
+                            const int *__restrict__ cell_start, int *__restrict__ cell_fill,
+                            int *__restrict__ cell_atoms) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nall) return;
+  int c = atom_cell[k];
+  int pos = atomicAdd(&cell_fill[c], 1);
+  cell_atoms[cell_start[c] + pos] = k;
+}
+
+// Distinct cell offsets along one dimension.
+__device__ __forceinline__ int dim_offsets(const CellGrid &g, int dim, int c, int out[3]) {
+  int n = 0;
+  const int nc = g.nc[dim];
+  if (g.periodic) {
+    if (nc >= 3) {
+      out[n++] = (c + nc - 1) % nc;
+      out[n++] = c;
+      out[n++] = (c + 1) % nc;
+    } else if (nc == 2) {
+      out[n++] = 0;
+      out[n++] = 1;
+    } else {
+      out[n++] = 0;
+    }
+  } else {
+    for (int o = -1; o <= 1; ++o) {
+      int q = c + o;
+      if (q >= 0 && q < nc) out[n++] = q;
+    }
+  }
+  return n;
+}
+
+// One wavefront per centre atom k.  Local centres collect every atom within
+// rcut; ghost centres collect local atoms only (they are needed by the force
+// gather, never as energy centres).
+__global__ __launch_bounds__(kWave *kNlistWaves) void k_nlist(
+    const double *__restrict__ x, int nloc, int nall, CellGrid g, double rc2, int sel,
+    const int *__restrict__ atom_cell, const int *__restrict__ cell_start,
+    const int *__restrict__ cell_atoms, int *__restrict__ nlist, int *__restrict__ nnei,
+    DevFlags *flags) {
+  __shared__ int list[kNlistWaves][kListCap];
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int k = blockIdx.x * kNlistWaves + wave;
+  if (k >= nall) return;
+  const bool ghost = k >= nloc;
+  const int ck = atom_cell[k];
+  const int cx = ck % g.nc[0];
+  const int cy = (ck / g.nc[0]) % g.nc[1];
+  const int cz = ck / (g.nc[0] * g.nc[1]);
+  int ox[3], oy[3], oz[3];
+  const int nx = dim_offsets(g, 0, cx, ox);
+  const int ny = dim_offsets(g, 1, cy, oy);
+  const int nz = dim_offsets(g, 2, cz, oz);
+  int count = 0;
+  for (int a = 0; a < nz; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nx; ++c) {
+        const int cell = (oz[a] * g.nc[1] + oy[b]) * g.nc[0] + ox[c];
+        const int beg = cell_start[cell];
+        const int end = cell_start[cell + 1];
+        for (int base = beg; base < end; base += kWave) {
+          const int idx = base + lane;
+          bool hit = false;
+          int j = -1;
+          if (idx < end) {
+            j = cell_atoms[idx];
+            if (j != k && (!ghost || j < nloc)) {
+              double d[3];
+              pair_vec(x, k, j, g, d);
+              hit = norm2(d) < rc2;
+            }
+          }
+          const unsigned long long m = __ballot(hit);
+          const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+          if (hit && pos < kListCap) list[wave][pos] = j;
+          count += __popcll(m);
+        }
+      }
+  const int n = count < sel ? count : sel;
+  if (count > sel) {
+    if (lane == 0) {
+      int old = atomicMin(&flags->overflow_atom, k);
+      if (old > k) atomicExch(&flags->overflow_count, count);
+    }
+  }
+  // rank sort of the (distinct) indices
+  int vals[2], ranks[2];
+  for (int h = 0; h < 2; ++h) {
+    const int p = lane + h * kWave;
+    vals[h] = p < n ? list[wave][p] : INT_MAX;
+    ranks[h] = 0;
+  }
+  for (int q = 0; q < n; ++q) {
+    const int v = list[wave][q];
+    ranks[0] += v < vals[0];
+    ranks[1] += v < vals[1];
+  }
+  int *row = nlist + (size_t)k * sel;
+  for (int h = 0; h < 2; ++h) {
+    const int p = lane + h * kWave;
+    if (p < n) row[ranks[h]] = vals[h];
+    else if (p < sel) row[p] = -1;
+  }
+  if (lane == 0) nnei[k] = n;
+}
+
+// One thread per (centre, slot).  Geometry in FP64, stored as FP32.
+__global__ void k_env_embed1(const double *__restrict__ x, const int32_t *__restrict__ types,
+                             CellGrid g, int nloc, int sel, double rcut, double rs,
+                             const int *__restrict__ nlist, const int *__restrict__ nnei,
+                             const int *__restrict__ pair_off,
+                             const float *__restrict__ type_table,
+                             const float *__restrict__ ws, int ntypes, int n1, int ld1,
+                             float *__restrict__ geom, float *__restrict__ h1) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nloc * sel) return;
+  const int i = (int)(t / sel);
+  const int s = (int)(t % sel);
+  if (s >= nnei[i]) return;
+  const int j = nlist[(size_t)i * sel + s];
+  const int p = pair_off[i] + s;
+  double d[3];
+  pair_vec(x, i, j, g, d);
+  const double r = sqrt(norm2(d));
+  double sw, dsw;
+  if (r < rs) {
+    sw = 1.0;
+    dsw = 0.0;
+  } else if (r < rcut) {
+    const double inv = 1.0 / (rcut - rs);
+    const double u = (r - rs) * inv;
+    // sw = u^3 (-6u^2 + 15u - 10) + 1 ; dsw/dr = -30 u^2 (u - 1)^2 / (rcut - rs)
+    sw = u * u * u * (-6.0 * u * u + 15.0 * u - 10.0) + 1.0;
+    dsw = -30.0 * u * u * (u - 1.0) * (u - 1.0) * inv;
+  } else {
+    sw = 0.0;
+    dsw = 0.0;
+  }
+  const double sv = sw / r;
+  float *gp = geom + (size_t)p * kGeom;
+  gp[G_S] = (float)sv;
+  gp[G_RX] = (float)(d[0] / r);
+  gp[G_RY] = (float)(d[1] / r);
+  gp[G_RZ] = (float)(d[2] / r);
+  gp[G_SW] = (float)sw;
+  gp[G_R] = (float)r;
+  gp[G_DSW] = (float)dsw;
+  gp[7] = 0.0f;
+  const float s32 = (float)sv;
+  const float *tt = type_table + ((size_t)types[j] * ntypes + types[i]) * ld1;
+  float *hp = h1 + (size_t)p * ld1;
+  for (int o = 0; o < ld1; ++o) hp[o] = o < n1 ? tanhf(tt[o] + ws[o] * s32) : 0.0f;
+}
+
+}  // namespace
+
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_check_types(const int32_t *types, int nall, int ntypes, DevFlags *flags,
+                        int32_t *safe, hipStream_t s) {
+  if (nall <= 0) return;
+  hipLaunchKernelGGL(k_check_types, dim3(nblk(nall, 256)), dim3(256), 0, s, types, nall, ntypes,
+                     flags, safe);
+}
+
+void launch_cell_bin(const double *coords, int nall, CellGrid grid, int *atom_cell,
+                     int *cell_count, hipStream_t s) {
+  if (nall <= 0) return;
+  hipLaunchKernelGGL(k_cell_bin, dim3(nblk(nall, 256)), dim3(256), 0, s, coords, nall, grid,
+                     atom_cell, cell_count);
+}
+
+void launch_scan(const int *in, int n, int *out_excl, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, n, out_excl);
+}
+
+void launch_cell_fill(const int *atom_cell, int nall, const int *cell_start, int *cell_fill,
+                      int *cell_atoms, hipStream_t s) {
+  if (nall <= 0) return;
+  hipLaunchKernelGGL(k_cell_fill, dim3(nblk(nall, 256)), dim3(256), 0, s, atom_cell, nall,
+                     cell_start, cell_fill, cell_atoms);
+}
+
+void launch_nlist(const double *coords, int nloc, int nall, CellGrid grid, double rcut, int sel,
+                  const int *atom_cell, const int *cell_start, const int *cell_atoms, int *nlist,
+                  int *nnei, DevFlags *flags, hipStream_t s) {
+  if (nall <= 0) return;
+  hipLaunchKernelGGL(k_nlist, dim3(nblk(nall, kNlistWaves)), dim3(kWave * kNlistWaves), 0, s,
+                     coords, nloc, nall, grid, rcut * rcut, sel, atom_cell, cell_start,
+                     cell_atoms, nlist, nnei, flags);
+}
+
+void launch_env_embed1(const double *coords, const int32_t *types, CellGrid grid, int nloc,
+                       int sel, double rcut, double rcut_smth, const int *nlist, const int *nnei,
+                       const int *pair_off, const float *type_table, const float *ws, int ntypes,
+                       int n1, int ld1, float *geom, float *h1, hipStream_t s) {
+  if (nloc <= 0) return;
+  hipLaunchKernelGGL(k_env_embed1, dim3(nblk((long)nloc * sel, 256)), dim3(256), 0, s, coords,
+                     types, grid, nloc, sel, rcut, rcut_smth, nlist, nnei, pair_off, type_table,
+                     ws, ntypes, n1, ld1, geom, h1);
+}
+
+}  // namespace dpa1

@@ -1,0 +1,71 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/dpa1.h, and rejects bad arguments before touching a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_07276_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "dpa1.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dp_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_lists_the_abi():
+    names = _declared_functions()
+    assert set(names) == set(binding.EXPORTED), names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load_library()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _create(path, rcut=6.0, sel=120):
+    lib = binding.load_library()
+    h = ctypes.c_void_p()
+    rc = lib.dp_create(path.encode() if path is not None else None, rcut, sel, ctypes.byref(h))
+    return rc, lib.dp_last_error().decode()
+
+
+def test_create_rejects_missing_file(tmp_path):
+    rc, msg = _create(str(tmp_path / "nope.bin"))
+    assert rc == -5 and "cannot open" in msg
+
+
+def test_create_rejects_foreign_file(tmp_path):
+    p = tmp_path / "junk.bin"
+    p.write_bytes(b"not a weights file at all")
+    rc, msg = _create(str(p))
+    assert rc == -5
+
+
+def test_create_rejects_bad_sel_and_rcut(weights_path):
+    assert _create(weights_path, sel=0)[0] == -1
+    assert _create(weights_path, sel=129)[0] == -1
+    assert _create(weights_path, rcut=-1.0)[0] == -1
+    assert _create(None)[0] == -1
+
+
+def test_calls_with_null_handle_fail_cleanly():
+    lib = binding.load_library()
+    assert lib.dp_compute(None, None, None, None, 0, 0, None, None, None, None) == -1
+    assert lib.dp_sync(None) == -1
+    assert lib.dp_debug_nlist(None, None, None) == -1
+    lib.dp_destroy(None)
+
+
+def test_create_without_device_reports_device_error(weights_path):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, msg = _create(weights_path)
+    assert rc == -6, msg
