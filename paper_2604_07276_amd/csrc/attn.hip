@@ -55,39 +55,6 @@ __device__ __forceinline__ float sum_rows(float v) {  // over the 16 lanes of a 
   return v;
 }
 
-// Per-neighbour gate data staged in LDS: (rhat_x, rhat_y, rhat_z, sw), zero
-// for slots beyond n.
-__device__ __forceinline__ void stage_keys(const float *__restrict__ geom, int base, int n,
-                                           float4 *kg) {
-  for (int t = threadIdx.x; t < kMaxTiles * 16; t += blockDim.x) {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < n) {
-      const float *gp = geom + (size_t)(base + t) * kGeom;
-      v = make_float4(gp[G_RX], gp[G_RY], gp[G_RZ], gp[G_SW]);
-    }
-    kg[t] = v;
-  }
-}
-
-// S^T tile for key tile kt and the wave's query registers qv.
-// dattn = 128 = 8 chunks of 16 features.
-__device__ __forceinline__ floatx4 qk_tile(const float *__restrict__ rows, int ld, int base,
-                                           int n, int kt, int r, int g, const floatx4 (&qv)[8]) {
-  floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int key = kt * 16 + r;
-  const bool ok = key < n;
-  const float *kr = rows + (size_t)(base + (ok ? key : 0)) * ld + 4 * g;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const floatx4 kv = ok ? *(const floatx4 *)(kr + 16 * c) : floatx4{0.f, 0.f, 0.f, 0.f};
-    acc = mfma4(kv[0], qv[c][0], acc);
-    acc = mfma4(kv[1], qv[c][1], acc);
-    acc = mfma4(kv[2], qv[c][2], acc);
-    acc = mfma4(kv[3], qv[c][3], acc);
-  }
-  return acc;
-}
-
 // Load one 16x128 row tile as the MFMA B operand: lane holds row r,
 // features 16c + 4g + {0..3}.
 __device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld, int base,
@@ -99,65 +66,165 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld
     v[c] = ok ? *(const floatx4 *)(p + 16 * c) : floatx4{0.f, 0.f, 0.f, 0.f};
 }
 
-// acc[ft] += X^T B for one 16-row tile of X (rows 'tile*16 + 4g + t', all 128
-// features) and a 16x16 B tile held as bt (lane: column r, rows 4g + t).
-__device__ __forceinline__ void accum_xt_b(const float *__restrict__ rows, int ld, int base,
-                                           int n, int tile, int r, int g, const floatx4 &bt,
-                                           floatx4 (&acc)[8]) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int row = tile * 16 + 4 * g + t;
-    const bool ok = row < n;
-    const float *p = rows + (size_t)(base + (ok ? row : 0)) * ld + r;
-#pragma unroll
-    for (int ft = 0; ft < 8; ++ft) {
-      const float x = ok ? p[16 * ft] : 0.f;
-      acc[ft] = mfma4(x, bt[t], acc[ft]);
-    }
+// Stage rows [base, base + n) x 128 features of src (row stride ld) into LDS
+// transposed, XT[f][k] with row stride NPAD + 4; rows n..NPAD-1 are zero.
+// Products that contract over neighbours read it with one 16-byte LDS load
+// per lane per four MFMA steps.
+template <int NPAD>
+__device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, int base, int n,
+                                        float *XT) {
+  constexpr int LDT = NPAD + 4;
+  for (int idx = threadIdx.x; idx < NPAD * 32; idx += blockDim.x) {
+    const int row = idx >> 5, c4 = idx & 31;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < n) v = *(const float4 *)(src + (size_t)(base + row) * ld + 4 * c4);
+    float *d = XT + (4 * c4) * LDT + row;
+    d[0] = v.x;
+    d[LDT] = v.y;
+    d[2 * LDT] = v.z;
+    d[3 * LDT] = v.w;
   }
 }
 
-// --------------------------------------------------------------------- forward
+template <int NPAD>
+__device__ __forceinline__ void stage_gate(const float *__restrict__ geom, int base, int n,
+                                           float4 *kg) {
+  for (int t = threadIdx.x; t < NPAD; t += blockDim.x) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < n) {
+      const float *gp = geom + (size_t)(base + t) * kGeom;
+      v = make_float4(gp[G_RX], gp[G_RY], gp[G_RZ], gp[G_SW]);
+    }
+    kg[t] = v;
+  }
+}
 
-__global__ __launch_bounds__(512) void k_attn_fwd(const float *__restrict__ qkv,
-                                                  const float *__restrict__ geom,
-                                                  const int *__restrict__ pair_off,
-                                                  const int *__restrict__ nnei, int sel,
-                                                  float shift, float *__restrict__ out) {
-  __shared__ float4 kg[kMaxTiles * 16];
+// acc[ft] += XT^T-tile x bt : contraction over the 16 rows of tile 'tile',
+// XT in LDS (feature-major), bt a 16x16 B operand held in registers.
+template <int NPAD>
+__device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int g,
+                                          const floatx4 &bt, floatx4 (&acc)[8]) {
+  constexpr int LDT = NPAD + 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    floatx4 x[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      x[f] = *(const floatx4 *)(XT + ((4 * h + f) * 16 + r) * LDT + tile * 16 + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+  }
+}
+
+// Keeps the compiler from hoisting the loads of later iterations (which
+// would hold many more registers live than the pipeline needs).
+#define SCHED_FENCE() asm volatile("" ::: "memory")
+
+// S^T tiles for every key tile: st[kt] (lane: query r, keys 4g + v) from the
+// wave's 16 query rows qv and the key rows read from global memory.  The key
+// rows of feature chunk c+1 are loaded while chunk c is multiplied.
+template <int NT>
+__device__ __forceinline__ void qk_tiles(const float *__restrict__ krows, int ld, int base, int n,
+                                         int ntile, int r, int g, const floatx4 (&qv)[8],
+                                         floatx4 (&st)[NT]) {
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) st[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float *kp = krows + (size_t)base * ld + (size_t)r * ld + 4 * g;
+  auto load = [&](int c, floatx4 (&kv)[NT]) {
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt)
+      kv[kt] = kt * 16 + r < n ? *(const floatx4 *)(kp + (size_t)kt * 16 * ld + 16 * c)
+                               : floatx4{0.f, 0.f, 0.f, 0.f};
+  };
+  floatx4 cur[NT], nxt[NT];
+  load(0, cur);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (c + 1 < 8) load(c + 1, nxt);
+    SCHED_FENCE();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma4(cur[kt][t], qv[c][t], st[kt]);
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) cur[kt] = nxt[kt];
+  }
+}
+
+// One 16x16 tile of rows x kreg^T: lane (row r of the 16-row tile at 'row0',
+// lane group g) supplies the A operand from global memory, breg the B operand.
+__device__ __forceinline__ floatx4 rows_times(const float *__restrict__ rows, int ld, int base,
+                                              int n, int row0, int r, int g,
+                                              const floatx4 (&breg)[8]) {
+  const int row = row0 + r;
+  const bool ok = row < n;
+  const float *p = rows + (size_t)(base + (ok ? row : 0)) * ld + 4 * g;
+  floatx4 a0 = floatx4{0.f, 0.f, 0.f, 0.f}, a1 = a0;
+  floatx4 x0 = ok ? *(const floatx4 *)(p) : a0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    floatx4 x1 = a0;
+    if (c + 1 < 8 && ok) x1 = *(const floatx4 *)(p + 16 * (c + 1));
+    SCHED_FENCE();
+    if (c & 1) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a1 = mfma4(x0[t], breg[c][t], a1);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a0 = mfma4(x0[t], breg[c][t], a0);
+    }
+    x0 = x1;
+  }
+  return a0 + a1;
+}
+
+// --------------------------------------------------------------------- forward
+//
+// One workgroup per centre whose neighbour count lies in (nlo, NPAD]; one
+// wavefront per 16-query tile.  V is staged transposed in LDS for A V.
+
+template <int NPAD>
+__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) void k_attn_fwd(
+    const float *__restrict__ qkv, const float *__restrict__ geom,
+    const int *__restrict__ pair_off, const int *__restrict__ nnei, int sel, float shift,
+    float *__restrict__ out, int nlo) {
+  constexpr int NT = NPAD / 16;
+  extern __shared__ float4 smem[];
+  float4 *kg = smem;
+  float *VT = (float *)(smem + NPAD);
   const int i = blockIdx.x;
   const int n = nnei[i];
+  if (n <= nlo || n > NPAD) return;  // uniform over the block
   const int base = pair_off[i];
-  stage_keys(geom, base, n, kg);
+  const int ntile = (n + 15) >> 4;
+  const int ld = kQKV * 128;
+  stage_gate<NPAD>(geom, base, n, kg);
+  stage_t<NPAD>(qkv + 256, ld, base, n, VT);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int ntile = (n + 15) >> 4;
   if (wave >= ntile) return;
   const int r = lane & 15, g = lane >> 4;
   const int q = wave * 16 + r;
   const bool qok = q < n;
-  const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;  // 1/sqrt(128)
 
   floatx4 qv[8];
   load_rows(qkv, ld, base, n, q, g, qv);
-  floatx4 st[kMaxTiles];
-#pragma unroll
-  for (int kt = 0; kt < kMaxTiles; ++kt)
-    if (kt < ntile) st[kt] = qk_tile(qkv + 128, ld, base, n, kt, r, g, qv);
+  floatx4 st[NT];
+  qk_tiles<NT>(qkv + 128, ld, base, n, ntile, r, g, qv, st);
 
   const float4 gq = kg[q];
   const float wq = qok ? gq.w : 0.f;
   float mx = -FLT_MAX;
 #pragma unroll
-  for (int kt = 0; kt < kMaxTiles; ++kt) {
-    if (kt >= ntile) continue;
+  for (int kt = 0; kt < NT; ++kt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int k = kt * 16 + 4 * g + v;
-      const float wk = kg[k].w;
-      float l = (st[kt][v] * inv_sqrt_d + shift) * wq * wk - shift;
+      float l = (st[kt][v] * inv_sqrt_d + shift) * wq * kg[k].w - shift;
       l = k < n ? l : -INFINITY;
       st[kt][v] = l;
       mx = fmaxf(mx, l);
@@ -166,8 +233,7 @@ __global__ __launch_bounds__(512) void k_attn_fwd(const float *__restrict__ qkv,
   const float m = fmaxf(max_groups(mx), -shift);
   float z = 0.f;
 #pragma unroll
-  for (int kt = 0; kt < kMaxTiles; ++kt) {
-    if (kt >= ntile) continue;
+  for (int kt = 0; kt < NT; ++kt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const float e = expf(st[kt][v] - m);
@@ -182,8 +248,7 @@ __global__ __launch_bounds__(512) void k_attn_fwd(const float *__restrict__ qkv,
 #pragma unroll
   for (int ft = 0; ft < 8; ++ft) oacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kt = 0; kt < kMaxTiles; ++kt) {
-    if (kt >= ntile) continue;
+  for (int kt = 0; kt < NT; ++kt) {
     floatx4 at;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -191,7 +256,7 @@ __global__ __launch_bounds__(512) void k_attn_fwd(const float *__restrict__ qkv,
       const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
       at[v] = st[kt][v] * invz * wq * gk.w * c;
     }
-    accum_xt_b(qkv + 256, ld, base, n, kt, r, g, at, oacc);
+    accum_lds<NPAD>(VT, kt, r, g, at, oacc);
   }
   if (!qok) return;
   float *op = out + (size_t)(base + q) * 128 + 4 * g;
@@ -207,115 +272,108 @@ __global__ __launch_bounds__(512) void k_attn_fwd(const float *__restrict__ qkv,
 //   dS = dL w_q w_k / sqrt(d) ; dQ = dS K ; dK = dS^T Q
 //   X = dL (lam + S) + dH c  -> dw_q += sum_k X w_k, dw_k += sum_q X w_q
 //   Y = dH w_q w_k           -> drhat_q += sum_k Y rhat_k, drhat_k += sum_q Y rhat_q
-// Pass 1 (wave = query tile): P, dA, dL, dQ, query-side sums; A and dS go to
-// LDS.  Pass 2 (wave = key tile): dK, dV from the LDS tiles, key-side sums.
+// Phase A (wave = query tile): logits, softmax statistics, dA, dS, dQ and the
+// query-side sums (K^T in LDS).  Phase B1 (wave = key tile): logits and dA
+// recomputed in the key-major layout, dK and the key-side sums (Q^T in LDS);
+// the tile of A is kept in registers for phase B2: dV (dO^T in LDS).
 
-__global__ __launch_bounds__(512) void k_attn_bwd(
+template <int NPAD>
+__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd(
     const float *__restrict__ qkv, const float *__restrict__ o, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
     const int *__restrict__ nnei, int sel, float shift, float *__restrict__ dqkv,
-    float *__restrict__ gw, float *__restrict__ gr, int accumulate) {
-  extern __shared__ float lds[];
-  float4 *kg = (float4 *)lds;                               // [128]
-  float4 *qside = kg + kMaxTiles * 16;                      // [128] query-side (dw, dr)
-  float4 *kpart = qside + kMaxTiles * 16;                   // [8 waves][128] key-side
-  float *tA = (float *)(kpart + kMaxTiles * kMaxTiles * 16);  // [64 tiles][256]
-  float *tS = tA + kMaxTiles * kMaxTiles * 256;              // [64 tiles][256]
-
+    float *__restrict__ gw, float *__restrict__ gr, int accumulate, int nlo) {
+  constexpr int NT = NPAD / 16;
+  extern __shared__ float4 smem[];
+  float4 *kg = smem;                 // [NPAD] rhat, sw
+  float4 *stats = kg + NPAD;         // [NPAD] m, 1/Z, D_q
+  float4 *qside = stats + NPAD;      // [NPAD] query-side dE/dsw, dE/drhat
+  float *XT = (float *)(qside + NPAD);  // [128][NPAD + 4]
   const int i = blockIdx.x;
   const int n = nnei[i];
+  if (n <= nlo || n > NPAD) return;  // uniform over the block
   const int base = pair_off[i];
-  stage_keys(geom, base, n, kg);
-  __syncthreads();
+  const int ntile = (n + 15) >> 4;
+  const int ld = kQKV * 128;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int ntile = (n + 15) >> 4;
   const int r = lane & 15, g = lane >> 4;
-  const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
 
+  stage_gate<NPAD>(geom, base, n, kg);
+  stage_t<NPAD>(qkv + 128, ld, base, n, XT);  // K^T
+  __syncthreads();
+
+  // ---------------- phase A: wave = query tile
   if (wave < ntile) {
-    const int qt = wave;
-    const int q = qt * 16 + r;
+    const int q = wave * 16 + r;
     const bool qok = q < n;
     const float4 gq = kg[q];
     const float wq = qok ? gq.w : 0.f;
-
-    floatx4 qv[8];
-    load_rows(qkv, ld, base, n, q, g, qv);
-    floatx4 st[kMaxTiles];  // lam, then probabilities
-#pragma unroll
-    for (int kt = 0; kt < kMaxTiles; ++kt)
-      if (kt < ntile) st[kt] = qk_tile(qkv + 128, ld, base, n, kt, r, g, qv);
-
-    floatx4 dov[8];
-    load_rows(dO, 128, base, n, q, g, dov);
-    // D_q = dO_q . o_q
-    float dq = 0.f;
+    floatx4 lam[NT];
     {
-      floatx4 ov[8];
-      load_rows(o, 128, base, n, q, g, ov);
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
-              dov[c][3] * ov[c][3];
-      dq = sum_groups(dq);
+      floatx4 qv[8];
+      load_rows(qkv, ld, base, n, q, g, qv);
+      qk_tiles<NT>(qkv + 128, ld, base, n, ntile, r, g, qv, lam);
     }
-
-    floatx4 lam[kMaxTiles];
     float mx = -FLT_MAX;
 #pragma unroll
-    for (int kt = 0; kt < kMaxTiles; ++kt) {
-      if (kt >= ntile) continue;
-#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+  #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int k = kt * 16 + 4 * g + v;
-        const float wk = kg[k].w;
-        const float lm = st[kt][v] * inv_sqrt_d;
-        lam[kt][v] = lm;
-        float l = (lm + shift) * wq * wk - shift;
-        l = k < n ? l : -INFINITY;
-        st[kt][v] = l;
+        lam[kt][v] *= inv_sqrt_d;
+        const float l = k < n ? (lam[kt][v] + shift) * wq * kg[k].w - shift : -INFINITY;
         mx = fmaxf(mx, l);
       }
     }
     const float m = fmaxf(max_groups(mx), -shift);
     float z = 0.f;
 #pragma unroll
-    for (int kt = 0; kt < kMaxTiles; ++kt) {
-      if (kt >= ntile) continue;
-#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+  #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float e = expf(st[kt][v] - m);
-        st[kt][v] = e;
-        z += e;
+        const int k = kt * 16 + 4 * g + v;
+        if (k < n) z += expf((lam[kt][v] + shift) * wq * kg[k].w - shift - m);
       }
     }
     z = sum_groups(z) + (float)(sel - n) * expf(-shift - m);
     const float invz = 1.0f / z;
 
+    floatx4 da[NT];
+    float dq;
+    {
+      floatx4 dov[8], ov[8];
+      load_rows(dO, 128, base, n, q, g, dov);
+      load_rows(o, 128, base, n, q, g, ov);
+      dq = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
+              dov[c][3] * ov[c][3];
+      dq = sum_groups(dq);
+      qk_tiles<NT>(qkv + 256, ld, base, n, ntile, r, g, dov, da);  // dA^T tiles
+    }
+    if (g == 0) stats[q] = make_float4(m, invz, dq, 0.f);
+
     floatx4 dqacc[8];
 #pragma unroll
     for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
     float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
-
 #pragma unroll
-    for (int kt = 0; kt < kMaxTiles; ++kt) {
-      if (kt >= ntile) continue;
-      const floatx4 da = qk_tile(qkv + 256, ld, base, n, kt, r, g, dov);  // dA^T tile
-      floatx4 at, ds;
+    for (int kt = 0; kt < NT; ++kt) {
+        floatx4 ds;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int k = kt * 16 + 4 * g + v;
         const float4 gk = kg[k];
         const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
         const float ww = wq * gk.w;
-        const float p = qok ? st[kt][v] * invz : 0.f;
+        const float l = (lam[kt][v] + shift) * ww - shift;
+        const float p = (qok && k < n) ? expf(l - m) * invz : 0.f;
         const float h = ww * c;
-        const float dP = da[v] * h;
-        const float dH = da[v] * p;
-        const float dL = p * (dP - dq);
-        at[v] = p * h;
+        const float dH = da[kt][v] * p;
+        const float dL = p * (da[kt][v] * h - dq);
         ds[v] = dL * ww * inv_sqrt_d;
         const float X = dL * (lam[kt][v] + shift) + dH * c;
         const float Y = dH * ww;
@@ -323,18 +381,8 @@ __global__ __launch_bounds__(512) void k_attn_bwd(
         drqx += Y * gk.x;
         drqy += Y * gk.y;
         drqz += Y * gk.z;
-        // key side: sum over the 16 queries of this wave
-        float kx = sum_rows(X * wq);
-        float ky0 = sum_rows(Y * gq.x);
-        float ky1 = sum_rows(Y * gq.y);
-        float ky2 = sum_rows(Y * gq.z);
-        if (r == 0) kpart[qt * (kMaxTiles * 16) + k] = make_float4(kx, ky0, ky1, ky2);
       }
-      accum_xt_b(qkv + 128, ld, base, n, kt, r, g, ds, dqacc);
-      // A and dS tiles, element (q_local = r, k_local = 4g + v)
-      const int tix = (qt * kMaxTiles + kt) * 256 + r * 16 + 4 * g;
-      *(floatx4 *)(tA + tix) = at;
-      *(floatx4 *)(tS + tix) = ds;
+      accum_lds<NPAD>(XT, kt, r, g, ds, dqacc);
     }
     dwq = sum_groups(dwq);
     drqx = sum_groups(drqx);
@@ -348,56 +396,110 @@ __global__ __launch_bounds__(512) void k_attn_bwd(
     }
   }
   __syncthreads();
-  if (wave >= ntile) return;
+  stage_t<NPAD>(qkv, ld, base, n, XT);  // Q^T
+  __syncthreads();
 
-  // pass 2: wave owns key tile kt
-  const int kt = wave;
-  floatx4 dkacc[8], dvacc[8];
+  // ---------------- phase B1: wave = key tile
+  const int kk = wave * 16 + r;
+  const bool kok = kk < n;
+  floatx4 at[NT];
+  float dwk = 0.f, drkx = 0.f, drky = 0.f, drkz = 0.f;
+  if (wave < ntile) {
+    const float4 gk = kg[kk];
+    const float wk = kok ? gk.w : 0.f;
+    // logits and dA for this key tile against every query tile, key-major
+    floatx4 sk[NT], dk[NT];
+    {
+      floatx4 kreg[8];
+      load_rows(qkv + 128, ld, base, n, kk, g, kreg);
 #pragma unroll
-  for (int ft = 0; ft < 8; ++ft) {
-    dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
-    dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
-  }
-  for (int qt = 0; qt < ntile; ++qt) {
-    floatx4 bs, ba;
-    const int tb = (qt * kMaxTiles + kt) * 256;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      bs[t] = tS[tb + (4 * g + t) * 16 + r];
-      ba[t] = tA[tb + (4 * g + t) * 16 + r];
+      for (int qt = 0; qt < NT; ++qt)
+        sk[qt] = qt < ntile ? rows_times(qkv, ld, base, n, qt * 16, r, g, kreg)
+                            : floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    accum_xt_b(qkv, ld, base, n, qt, r, g, bs, dkacc);
-    accum_xt_b(dO, 128, base, n, qt, r, g, ba, dvacc);
-  }
-  const int key = kt * 16 + r;
-  if (key < n) {
-    float *dp = dqkv + (size_t)(base + key) * ld + 4 * g;
+    {
+      floatx4 vreg[8];
+      load_rows(qkv + 256, ld, base, n, kk, g, vreg);
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) {
-      *(floatx4 *)(dp + 128 + 16 * ft) = dkacc[ft];
-      *(floatx4 *)(dp + 256 + 16 * ft) = dvacc[ft];
+      for (int qt = 0; qt < NT; ++qt)
+        dk[qt] = qt < ntile ? rows_times(dO, 128, base, n, qt * 16, r, g, vreg)
+                            : floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    if (g == 0) {
-      float4 tot = qside[key];
-      for (int w = 0; w < ntile; ++w) {
-        const float4 kp = kpart[w * (kMaxTiles * 16) + key];
-        tot.x += kp.x;
-        tot.y += kp.y;
-        tot.z += kp.z;
-        tot.w += kp.w;
+    floatx4 dkacc[8];
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int qt = 0; qt < NT; ++qt) {
+      at[qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (qt >= ntile) continue;
+      floatx4 ds;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int qq = qt * 16 + 4 * g + v;
+        const float4 sq = stats[qq];
+        const float4 gq = kg[qq];
+        const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
+        const float ww = gq.w * wk;
+        const float lm = sk[qt][v] * inv_sqrt_d;
+        const float l = (lm + shift) * ww - shift;
+        const float p = (kok && qq < n) ? expf(l - sq.x) * sq.y : 0.f;
+        const float h = ww * c;
+        const float dav = dk[qt][v];
+        const float dH = dav * p;
+        const float dL = p * (dav * h - sq.z);
+        at[qt][v] = p * h;
+        ds[v] = dL * ww * inv_sqrt_d;
+        const float X = dL * (lm + shift) + dH * c;
+        const float Y = dH * ww;
+        dwk += X * gq.w;
+        drkx += Y * gq.x;
+        drky += Y * gq.y;
+        drkz += Y * gq.z;
       }
-      const size_t p = (size_t)(base + key);
-      if (accumulate) {
-        gw[p] += tot.x;
-        gr[4 * p + 0] += tot.y;
-        gr[4 * p + 1] += tot.z;
-        gr[4 * p + 2] += tot.w;
-      } else {
-        gw[p] = tot.x;
-        gr[4 * p + 0] = tot.y;
-        gr[4 * p + 1] = tot.z;
-        gr[4 * p + 2] = tot.w;
-        gr[4 * p + 3] = 0.f;
+      accum_lds<NPAD>(XT, qt, r, g, ds, dkacc);
+    }
+    if (kok) {
+      float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+#pragma unroll
+      for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+    }
+    dwk = sum_groups(dwk);
+    drkx = sum_groups(drkx);
+    drky = sum_groups(drky);
+    drkz = sum_groups(drkz);
+  }
+  __syncthreads();
+  stage_t<NPAD>(dO, 128, base, n, XT);  // dO^T
+  __syncthreads();
+
+  // ---------------- phase B2: dV = A^T dO
+  if (wave < ntile) {
+    floatx4 dvacc[8];
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int qt = 0; qt < NT; ++qt)
+      if (qt < ntile) accum_lds<NPAD>(XT, qt, r, g, at[qt], dvacc);
+    if (kok) {
+      float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
+#pragma unroll
+      for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
+      if (g == 0) {
+        const float4 qs = qside[kk];
+        const size_t p = (size_t)(base + kk);
+        const float tw = qs.x + dwk, tx = qs.y + drkx, ty = qs.z + drky, tz = qs.w + drkz;
+        if (accumulate) {
+          gw[p] += tw;
+          gr[4 * p + 0] += tx;
+          gr[4 * p + 1] += ty;
+          gr[4 * p + 2] += tz;
+        } else {
+          gw[p] = tw;
+          gr[4 * p + 0] = tx;
+          gr[4 * p + 1] = ty;
+          gr[4 * p + 2] = tz;
+          gr[4 * p + 3] = 0.f;
+        }
       }
     }
   }
@@ -566,25 +668,52 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
   }
 }
 
+// Centres are grouped by neighbour count into classes of 32, 64, 96 and 128
+// slots; each class runs a kernel sized for it (blocks of the other classes
+// exit at once), so the common case does not pay for the largest LDS size.
+template <int NPAD>
+size_t fwd_lds() {
+  return sizeof(float4) * NPAD + sizeof(float) * 128 * (NPAD + 4);
+}
+template <int NPAD>
+size_t bwd_lds() {
+  return sizeof(float4) * 3 * NPAD + sizeof(float) * 128 * (NPAD + 4);
+}
+
+template <int NPAD>
+void fwd_one(const float *qkv, const float *geom, const int *pair_off, const int *nnei, int nloc,
+             int sel, float shift, float *out, int nlo, hipStream_t s) {
+  hipLaunchKernelGGL(k_attn_fwd<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), fwd_lds<NPAD>(), s, qkv,
+                     geom, pair_off, nnei, sel, shift, out, nlo);
+}
+template <int NPAD>
+void bwd_one(const float *qkv, const float *o, const float *dO, const float *geom,
+             const int *pair_off, const int *nnei, int nloc, int sel, float shift, float *dqkv,
+             float *gw, float *gr, int accumulate, int nlo, hipStream_t s) {
+  hipLaunchKernelGGL(k_attn_bwd<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), bwd_lds<NPAD>(), s, qkv,
+                     o, dO, geom, pair_off, nnei, sel, shift, dqkv, gw, gr, accumulate, nlo);
+}
+
 }  // namespace
 
 void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, const int *nnei,
                      int nloc, int sel, int dattn, float shift, float *out, hipStream_t s) {
   (void)dattn;
   if (nloc <= 0) return;
-  hipLaunchKernelGGL(k_attn_fwd, dim3(nloc), dim3(512), 0, s, qkv, geom, pair_off, nnei, sel,
-                     shift, out);
-}
-
-size_t attn_bwd_lds_bytes() {
-  return sizeof(float4) * (kMaxTiles * 16 * 2 + kMaxTiles * kMaxTiles * 16) +
-         sizeof(float) * 2 * kMaxTiles * kMaxTiles * 256;
+  fwd_one<32>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 0, s);
+  if (sel > 32) fwd_one<64>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 32, s);
+  if (sel > 64) fwd_one<96>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 64, s);
+  if (sel > 96) fwd_one<128>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 96, s);
 }
 
 hipError_t set_attn_bwd_lds_limit() {
-  return hipFuncSetAttribute((const void *)k_attn_bwd,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)attn_bwd_lds_bytes());
+  hipError_t e = hipFuncSetAttribute((const void *)k_attn_bwd<128>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bwd_lds<128>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_attn_fwd<128>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<128>());
+  return e;
 }
 
 void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
@@ -593,8 +722,14 @@ void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const fl
                      hipStream_t s) {
   (void)dattn;
   if (nloc <= 0) return;
-  hipLaunchKernelGGL(k_attn_bwd, dim3(nloc), dim3(512), attn_bwd_lds_bytes(), s, qkv, o, dO,
-                     geom, pair_off, nnei, sel, shift, dqkv, gw, gr, accumulate);
+  bwd_one<32>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 0, s);
+  if (sel > 32)
+    bwd_one<64>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 32, s);
+  if (sel > 64)
+    bwd_one<96>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 64, s);
+  if (sel > 96)
+    bwd_one<128>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 96,
+                 s);
 }
 
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,

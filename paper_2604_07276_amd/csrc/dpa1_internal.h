@@ -110,7 +110,6 @@ void gemm_emb1_bwd(const GemmArgs &a, const float *dh2, int ldd2, int res_mode, 
 void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, const int *nnei,
                      int nloc, int sel, int dattn, float shift, float *out, hipStream_t s);
 // Backward of the core: dQKV, and accumulation of dE/dsw and dE/drhat per pair.
-size_t attn_bwd_lds_bytes();
 hipError_t set_attn_bwd_lds_limit();
 void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
                      const int *pair_off, const int *nnei, int nloc, int sel, int dattn,

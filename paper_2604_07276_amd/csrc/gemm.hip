@@ -35,7 +35,7 @@ __device__ __forceinline__ float row_sum16(float v) {
 }
 
 template <int MT, int NT, class Epi>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a, Epi epi) {
+__global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -67,23 +67,38 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, Epi epi) {
     wrow[nt] = a.Wt + (size_t)(tile * 16 + r) * a.K + 4 * g;
   }
 
+  // Double-buffered k loop: the operands of chunk k0 + 16 are loaded while
+  // chunk k0 is multiplied; the MFMAs of one k step go to independent
+  // accumulators back to back.
+  floatx4 xv[MT], wv[NT], xn[MT], wn[NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+    xv[mt] = xok[mt] ? *(const floatx4 *)(xrow[mt]) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+    wv[nt] = *(const floatx4 *)(wrow[nt]);
+#pragma unroll 1
   for (int k0 = 0; k0 < a.K; k0 += 16) {
-    floatx4 xv[MT];
+    const int kn = k0 + 16 < a.K ? k0 + 16 : k0;  // last chunk reloads itself (unused)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
-      xv[mt] = xok[mt] ? *(const floatx4 *)(xrow[mt] + k0) : floatx4{0.f, 0.f, 0.f, 0.f};
+      xn[mt] = xok[mt] ? *(const floatx4 *)(xrow[mt] + kn) : floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      if (nt0 + nt >= ntt) continue;
-      const floatx4 wv = *(const floatx4 *)(wrow[nt] + k0);
+    for (int nt = 0; nt < NT; ++nt)
+      wn[nt] = *(const floatx4 *)(wrow[nt] + kn);
+    asm volatile("" ::: "memory");
+    // Tiles past the last column tile (nt0 + nt >= ntt) multiply a duplicate of
+    // tile 0 and are never stored: no branch inside the MFMA sequence.
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        acc[mt][nt] = mfma4(wv[0], xv[mt][0], acc[mt][nt]);
-        acc[mt][nt] = mfma4(wv[1], xv[mt][1], acc[mt][nt]);
-        acc[mt][nt] = mfma4(wv[2], xv[mt][2], acc[mt][nt]);
-        acc[mt][nt] = mfma4(wv[3], xv[mt][3], acc[mt][nt]);
-      }
-    }
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) wv[nt] = wn[nt];
   }
   epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
 }
@@ -96,7 +111,7 @@ struct EpiLinear {
   int ldy;
   int Nreal;
   template <int MT, int NT>
-  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
                         int M) const {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -133,7 +148,7 @@ struct EpiTanhRes {
   int ldt;
   int Nreal;
   template <int MT, int NT>
-  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
                         int M) const {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -177,7 +192,7 @@ struct EpiLNRes {
   float *gout, *xhat, *rstd;
   int Nreal;
   template <int MT, int NT>
-  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
                         int M) const {
     const int r = lane & 15, g = lane >> 4;
     const float invn = 1.0f / (float)Nreal;
@@ -253,7 +268,7 @@ struct EpiBwdTanh {
   int lda;
   int Nreal;
   template <int MT, int NT>
-  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
                         int M) const {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -298,7 +313,7 @@ struct EpiQKVBwd {
   float *dgin, *dnext;
   int Nreal;
   template <int MT, int NT>
-  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
                         int M) const {
     const int r = lane & 15, g = lane >> 4;
     const float invn = 1.0f / (float)Nreal;
@@ -371,7 +386,7 @@ struct EpiEmb1Bwd {
   float *gs;
   int Nreal;
   template <int MT, int NT>
-  __device__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
                         int M) const {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
