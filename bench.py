@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one device-to-device copy of this many MiB (calibrates "
+                         "hardware byte counters against a known transfer) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the DPA-1 step of one domain is measured on "
@@ -112,6 +115,15 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nb}), flush=True)
+        return
     tmpdir = tempfile.mkdtemp()
     wpath = os.path.join(tmpdir, "dpa1_seed0.bin")
     shp = synth.make_weights(wpath, seed=0)

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpa1.so")
-SOURCES = ["dpa1.cpp", "nlist.hip", "gemm.hip", "attn.hip", "misc.hip"]
+SOURCES = ["dpa1.cpp", "nlist.hip", "gemm.hip", "attn.hip", "embed.hip", "misc.hip"]
 
 
 def hipcc():

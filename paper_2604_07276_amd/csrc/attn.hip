@@ -60,10 +60,13 @@ __device__ __forceinline__ float sum_rows(float v) {  // over the 16 lanes of a 
 __device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld, int base,
                                           int n, int row, int g, floatx4 (&v)[8]) {
   const bool ok = row < n;
-  const float *p = rows + (size_t)(base + (ok ? row : 0)) * ld + 4 * g;
+  const float *rb = rows + (size_t)base * ld;
+  const int off = (ok ? row : 0) * ld + 4 * g;
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
-    v[c] = ok ? *(const floatx4 *)(p + 16 * c) : floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < 8; ++c) {
+    const floatx4 x = *(const floatx4 *)(rb + off + 16 * c);
+    v[c] = ok ? x : floatx4{0.f, 0.f, 0.f, 0.f};
+  }
 }
 
 // Stage rows [base, base + n) x 128 features of src (row stride ld) into LDS
@@ -74,15 +77,26 @@ template <int NPAD>
 __device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, int base, int n,
                                         float *XT) {
   constexpr int LDT = NPAD + 4;
-  for (int idx = threadIdx.x; idx < NPAD * 32; idx += blockDim.x) {
+  constexpr int THREADS = NPAD / 16 * 64;
+  constexpr int ITER = NPAD * 32 / THREADS;  // = 8
+  float4 v[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int idx = threadIdx.x + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (row < n) v = *(const float4 *)(src + (size_t)(base + row) * ld + 4 * c4);
+    const int rr = row < n ? row : 0;
+    v[it] = *(const float4 *)(src + (size_t)(base + rr) * ld + 4 * c4);
+    if (row >= n) v[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int idx = threadIdx.x + it * THREADS;
+    const int row = idx >> 5, c4 = idx & 31;
     float *d = XT + (4 * c4) * LDT + row;
-    d[0] = v.x;
-    d[LDT] = v.y;
-    d[2 * LDT] = v.z;
-    d[3 * LDT] = v.w;
+    d[0] = v[it].x;
+    d[LDT] = v[it].y;
+    d[2 * LDT] = v[it].z;
+    d[3 * LDT] = v[it].w;
   }
 }
 
@@ -105,22 +119,19 @@ template <int NPAD>
 __device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int g,
                                           const floatx4 &bt, floatx4 (&acc)[8]) {
   constexpr int LDT = NPAD + 4;
+  floatx4 x[8];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    floatx4 x[4];
+  for (int ft = 0; ft < 8; ++ft)
+    x[ft] = *(const floatx4 *)(XT + (ft * 16 + r) * LDT + tile * 16 + 4 * g);
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-      x[f] = *(const floatx4 *)(XT + ((4 * h + f) * 16 + r) * LDT + tile * 16 + 4 * g);
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
-  }
+    for (int ft = 0; ft < 8; ++ft) acc[ft] = mfma4(x[ft][t], bt[t], acc[ft]);
 }
 
 // Keeps the compiler from hoisting the loads of later iterations (which
 // would hold many more registers live than the pipeline needs).
-#define SCHED_FENCE() asm volatile("" ::: "memory")
+#define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 
 // S^T tiles for every key tile: st[kt] (lane: query r, keys 4g + v) from the
 // wave's 16 query rows qv and the key rows read from global memory.  The key
@@ -131,12 +142,21 @@ __device__ __forceinline__ void qk_tiles(const float *__restrict__ krows, int ld
                                          floatx4 (&st)[NT]) {
 #pragma unroll
   for (int kt = 0; kt < NT; ++kt) st[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const float *kp = krows + (size_t)base * ld + (size_t)r * ld + 4 * g;
+  // rows past n read row 0 of the centre and are replaced by zeros; the row
+  // base is uniform, per-lane offsets are 32-bit
+  const float *kb = krows + (size_t)base * ld;
+  int ko[NT];
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    const int row = kt * 16 + r;
+    ko[kt] = (row < n ? row : 0) * ld + 4 * g;
+  }
   auto load = [&](int c, floatx4 (&kv)[NT]) {
 #pragma unroll
-    for (int kt = 0; kt < NT; ++kt)
-      kv[kt] = kt * 16 + r < n ? *(const floatx4 *)(kp + (size_t)kt * 16 * ld + 16 * c)
-                               : floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < NT; ++kt) {
+      const floatx4 x = *(const floatx4 *)(kb + ko[kt] + 16 * c);
+      kv[kt] = kt * 16 + r < n ? x : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
   };
   floatx4 cur[NT], nxt[NT];
   load(0, cur);
@@ -161,12 +181,17 @@ __device__ __forceinline__ floatx4 rows_times(const float *__restrict__ rows, in
   const int row = row0 + r;
   const bool ok = row < n;
   const float *p = rows + (size_t)(base + (ok ? row : 0)) * ld + 4 * g;
-  floatx4 a0 = floatx4{0.f, 0.f, 0.f, 0.f}, a1 = a0;
-  floatx4 x0 = ok ? *(const floatx4 *)(p) : a0;
+  const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
+  floatx4 a0 = zero, a1 = zero;
+  floatx4 x0 = *(const floatx4 *)(p);
+  x0 = ok ? x0 : zero;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    floatx4 x1 = a0;
-    if (c + 1 < 8 && ok) x1 = *(const floatx4 *)(p + 16 * (c + 1));
+    floatx4 x1 = zero;
+    if (c + 1 < 8) {
+      x1 = *(const floatx4 *)(p + 16 * (c + 1));
+      x1 = ok ? x1 : zero;
+    }
     SCHED_FENCE();
     if (c & 1) {
 #pragma unroll
@@ -277,18 +302,23 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
 // recomputed in the key-major layout, dK and the key-side sums (Q^T in LDS);
 // the tile of A is kept in registers for phase B2: dV (dO^T in LDS).
 
+// Backward, in two kernels per class.  k_attn_bwd_q (wave = query tile):
+// logits, softmax statistics, dA, dS, dQ and the query-side sums (K^T in
+// LDS); it writes the statistics (m, 1/Z, D_q) and the query-side sums per
+// pair.  k_attn_bwd_k (wave = key tile): logits and dA recomputed key-major,
+// dK and the key-side sums (Q^T in LDS), then dV from the tile of A kept in
+// registers (dO^T in LDS); it adds both sides into dE/dsw and dE/drhat.
+
 template <int NPAD>
-__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd(
+__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_q(
     const float *__restrict__ qkv, const float *__restrict__ o, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
     const int *__restrict__ nnei, int sel, float shift, float *__restrict__ dqkv,
-    float *__restrict__ gw, float *__restrict__ gr, int accumulate, int nlo) {
+    float4 *__restrict__ astat, float4 *__restrict__ qside, int nlo) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
-  float4 *kg = smem;                 // [NPAD] rhat, sw
-  float4 *stats = kg + NPAD;         // [NPAD] m, 1/Z, D_q
-  float4 *qside = stats + NPAD;      // [NPAD] query-side dE/dsw, dE/drhat
-  float *XT = (float *)(qside + NPAD);  // [128][NPAD + 4]
+  float4 *kg = smem;                // [NPAD] rhat, sw
+  float *XT = (float *)(kg + NPAD);  // [128][NPAD + 4]
   const int i = blockIdx.x;
   const int n = nnei[i];
   if (n <= nlo || n > NPAD) return;  // uniform over the block
@@ -354,7 +384,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       dq = sum_groups(dq);
       qk_tiles<NT>(qkv + 256, ld, base, n, ntile, r, g, dov, da);  // dA^T tiles
     }
-    if (g == 0) stats[q] = make_float4(m, invz, dq, 0.f);
+    if (g == 0 && qok) astat[base + q] = make_float4(m, invz, dq, 0.f);
 
     floatx4 dqacc[8];
 #pragma unroll
@@ -388,14 +418,40 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     drqx = sum_groups(drqx);
     drqy = sum_groups(drqy);
     drqz = sum_groups(drqz);
-    if (g == 0) qside[q] = make_float4(dwq, drqx, drqy, drqz);
+    if (g == 0 && qok) qside[base + q] = make_float4(dwq, drqx, drqy, drqz);
     if (qok) {
       float *dp = dqkv + (size_t)(base + q) * ld + 4 * g;
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dqacc[ft];
     }
   }
-  __syncthreads();
+}
+
+template <int NPAD>
+__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_k(
+    const float *__restrict__ qkv, const float *__restrict__ dO,
+    const float *__restrict__ geom, const int *__restrict__ pair_off,
+    const int *__restrict__ nnei, float shift, float *__restrict__ dqkv,
+    const float4 *__restrict__ astat, const float4 *__restrict__ qsbuf,
+    float *__restrict__ gw, float *__restrict__ gr, int accumulate, int nlo) {
+  constexpr int NT = NPAD / 16;
+  extern __shared__ float4 smem[];
+  float4 *kg = smem;                 // [NPAD] rhat, sw
+  float4 *stats = kg + NPAD;         // [NPAD] m, 1/Z, D_q of each query
+  float *XT = (float *)(stats + NPAD);  // [128][NPAD + 4]
+  const int i = blockIdx.x;
+  const int n = nnei[i];
+  if (n <= nlo || n > NPAD) return;  // uniform over the block
+  const int base = pair_off[i];
+  const int ntile = (n + 15) >> 4;
+  const int ld = kQKV * 128;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const float inv_sqrt_d = 0.08838834764831845f;
+  stage_gate<NPAD>(geom, base, n, kg);
+  for (int t = threadIdx.x; t < NPAD; t += blockDim.x)
+    stats[t] = t < n ? astat[base + t] : make_float4(0.f, 1.f, 0.f, 0.f);
   stage_t<NPAD>(qkv, ld, base, n, XT);  // Q^T
   __syncthreads();
 
@@ -407,23 +463,18 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
   if (wave < ntile) {
     const float4 gk = kg[kk];
     const float wk = kok ? gk.w : 0.f;
-    // logits and dA for this key tile against every query tile, key-major
+    // logits and dA for this key tile against every query tile, key-major:
+    // lane holds key r and queries 4g + v of each query tile
     floatx4 sk[NT], dk[NT];
     {
       floatx4 kreg[8];
       load_rows(qkv + 128, ld, base, n, kk, g, kreg);
-#pragma unroll
-      for (int qt = 0; qt < NT; ++qt)
-        sk[qt] = qt < ntile ? rows_times(qkv, ld, base, n, qt * 16, r, g, kreg)
-                            : floatx4{0.f, 0.f, 0.f, 0.f};
+      qk_tiles<NT>(qkv, ld, base, n, ntile, r, g, kreg, sk);
     }
     {
       floatx4 vreg[8];
       load_rows(qkv + 256, ld, base, n, kk, g, vreg);
-#pragma unroll
-      for (int qt = 0; qt < NT; ++qt)
-        dk[qt] = qt < ntile ? rows_times(dO, 128, base, n, qt * 16, r, g, vreg)
-                            : floatx4{0.f, 0.f, 0.f, 0.f};
+      qk_tiles<NT>(dO, 128, base, n, ntile, r, g, vreg, dk);
     }
     floatx4 dkacc[8];
 #pragma unroll
@@ -485,7 +536,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
       if (g == 0) {
-        const float4 qs = qside[kk];
+        const float4 qs = qsbuf[base + kk];
         const size_t p = (size_t)(base + kk);
         const float tw = qs.x + dwk, tx = qs.y + drkx, ty = qs.z + drky, tz = qs.w + drkz;
         if (accumulate) {
@@ -649,13 +700,13 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
         if (m < M) {
           if (ln_mode == 0) {
             nx = rs * (gamma[m] * dg[h] - s1 * invm - xh[h] * s2 * invm);
-          } else {
+          } else if (ln_mode == 1) {
             const float t = temb[p * ldg + m];
             nx = dg[h] * (1.0f - t * t);
           }
         }
         dG[p * ldg + m] = dg[h];
-        dnext[p * ldg + m] = nx;
+        if (ln_mode != 2) dnext[p * ldg + m] = nx;
       }
     }
     if (lane == 0) {
@@ -676,8 +727,12 @@ size_t fwd_lds() {
   return sizeof(float4) * NPAD + sizeof(float) * 128 * (NPAD + 4);
 }
 template <int NPAD>
-size_t bwd_lds() {
-  return sizeof(float4) * 3 * NPAD + sizeof(float) * 128 * (NPAD + 4);
+size_t bwdq_lds() {
+  return sizeof(float4) * NPAD + sizeof(float) * 128 * (NPAD + 4);
+}
+template <int NPAD>
+size_t bwdk_lds() {
+  return sizeof(float4) * 2 * NPAD + sizeof(float) * 128 * (NPAD + 4);
 }
 
 template <int NPAD>
@@ -687,11 +742,19 @@ void fwd_one(const float *qkv, const float *geom, const int *pair_off, const int
                      geom, pair_off, nnei, sel, shift, out, nlo);
 }
 template <int NPAD>
-void bwd_one(const float *qkv, const float *o, const float *dO, const float *geom,
-             const int *pair_off, const int *nnei, int nloc, int sel, float shift, float *dqkv,
-             float *gw, float *gr, int accumulate, int nlo, hipStream_t s) {
-  hipLaunchKernelGGL(k_attn_bwd<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), bwd_lds<NPAD>(), s, qkv,
-                     o, dO, geom, pair_off, nnei, sel, shift, dqkv, gw, gr, accumulate, nlo);
+void bwdq_one(const float *qkv, const float *o, const float *dO, const float *geom,
+              const int *pair_off, const int *nnei, int nloc, int sel, float shift, float *dqkv,
+              float4 *astat, float4 *qside, int nlo, hipStream_t s) {
+  hipLaunchKernelGGL(k_attn_bwd_q<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), bwdq_lds<NPAD>(), s,
+                     qkv, o, dO, geom, pair_off, nnei, sel, shift, dqkv, astat, qside, nlo);
+}
+template <int NPAD>
+void bwdk_one(const float *qkv, const float *dO, const float *geom, const int *pair_off,
+              const int *nnei, int nloc, float shift, float *dqkv, const float4 *astat,
+              const float4 *qside, float *gw, float *gr, int accumulate, int nlo, hipStream_t s) {
+  hipLaunchKernelGGL(k_attn_bwd_k<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), bwdk_lds<NPAD>(), s,
+                     qkv, dO, geom, pair_off, nnei, shift, dqkv, astat, qside, gw, gr, accumulate,
+                     nlo);
 }
 
 }  // namespace
@@ -707,9 +770,12 @@ void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, c
 }
 
 hipError_t set_attn_bwd_lds_limit() {
-  hipError_t e = hipFuncSetAttribute((const void *)k_attn_bwd<128>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_attn_bwd_q<128>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)bwd_lds<128>());
+                                     (int)bwdq_lds<128>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_attn_bwd_k<128>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdk_lds<128>());
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_attn_fwd<128>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<128>());
@@ -718,18 +784,29 @@ hipError_t set_attn_bwd_lds_limit() {
 
 void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
                      const int *pair_off, const int *nnei, int nloc, int sel, int dattn,
-                     float shift, float *dqkv, float *gw, float *gr, int accumulate,
-                     hipStream_t s) {
+                     float shift, float *dqkv, float *gw, float *gr, float *scratch4a,
+                     float *scratch4b, int accumulate, hipStream_t s) {
   (void)dattn;
   if (nloc <= 0) return;
-  bwd_one<32>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 0, s);
+  float4 *astat = (float4 *)scratch4a, *qside = (float4 *)scratch4b;
+  bwdq_one<32>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 0, s);
   if (sel > 32)
-    bwd_one<64>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 32, s);
+    bwdq_one<64>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 32, s);
   if (sel > 64)
-    bwd_one<96>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 64, s);
+    bwdq_one<96>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 64, s);
   if (sel > 96)
-    bwd_one<128>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, gw, gr, accumulate, 96,
-                 s);
+    bwdq_one<128>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 96, s);
+  bwdk_one<32>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr, accumulate,
+               0, s);
+  if (sel > 32)
+    bwdk_one<64>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr,
+                 accumulate, 32, s);
+  if (sel > 64)
+    bwdk_one<96>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr,
+                 accumulate, 64, s);
+  if (sel > 96)
+    bwdk_one<128>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr,
+                  accumulate, 96, s);
 }
 
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,

@@ -84,8 +84,8 @@ struct Timer {
   void collect() {
     for (auto &p : pending) {
       float ms = 0.f;
-      hipEventSynchronize(p.b);
-      hipEventElapsedTime(&ms, p.a, p.b);
+      (void)hipEventSynchronize(p.b);
+      (void)hipEventElapsedTime(&ms, p.a, p.b);
       auto &t = totals[p.name];
       t.first += 1;
       t.second += ms;
@@ -96,10 +96,10 @@ struct Timer {
   }
   ~Timer() {
     for (auto &p : pending) {
-      hipEventDestroy(p.a);
-      hipEventDestroy(p.b);
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
     }
-    for (auto e : pool) hipEventDestroy(e);
+    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -143,7 +143,7 @@ struct dp_model {
     float *T, *dmat, *e;
     std::vector<float *> z, tf;        // fitting outputs / tanh parts
     std::vector<float *> fa, fdz;      // fitting backward a_l and dz_l
-    float *dD, *dGa, *dGb, *dY, *dO, *dqkv, *dRt, *gw, *gr, *gs, *g;
+    float *dD, *dGa, *dGb, *dY, *dO, *dqkv, *dRt, *gw, *gr, *gs, *g, *astat, *qside;
     std::vector<float *> du, dh;       // embedding backward
   } w;
   DevFlags *flags = nullptr;       // device
@@ -156,12 +156,12 @@ struct dp_model {
   Timer timer;
 
   ~dp_model() {
-    if (arena) hipFree(arena);
-    for (void *p : weight_allocs) hipFree(p);
-    if (flags) hipFree(flags);
-    if (bbox) hipFree(bbox);
-    if (flags_host) hipHostFree(flags_host);
-    if (own) hipStreamDestroy(own);
+    if (arena) (void)hipFree(arena);
+    for (void *p : weight_allocs) (void)hipFree(p);
+    if (flags) (void)hipFree(flags);
+    if (bbox) (void)hipFree(bbox);
+    if (flags_host) (void)hipHostFree(flags_host);
+    if (own) (void)hipStreamDestroy(own);
   }
 };
 
@@ -492,6 +492,8 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
   w.gr = c.take<float>(P * 4);
   w.gs = c.take<float>(P);
   w.g = c.take<float>(P * 4);
+  w.astat = c.take<float>(P * 4);
+  w.qside = c.take<float>(P * 4);
   w.du.assign(ne, nullptr);
   w.dh.assign(ne, nullptr);
   for (int l = 0; l < ne; ++l) {
@@ -606,11 +608,11 @@ __global__ void k_bbox(const double *x, int n, double *out) {
     if (m->timer.enabled) {                                       \
       a_ = m->timer.get();                                        \
       b_ = m->timer.get();                                        \
-      if (a_) hipEventRecord(a_, s);                              \
+      if (a_) (void)hipEventRecord(a_, s);                        \
     }                                                             \
     call;                                                         \
     if (a_ && b_) {                                               \
-      hipEventRecord(b_, s);                                      \
+      (void)hipEventRecord(b_, s);                                \
       m->timer.pending.push_back({name, a_, b_});                 \
     }                                                             \
   } while (0)
@@ -644,11 +646,20 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
                         w.nnei, w.pair_off, m->type_table, m->ws, m->ntypes, m->emb[0],
                         m->lde[0], w.geom, w.h[0], s));
   // embedding layers
-  for (int l = 1; l < ne; ++l) {
-    const Linear &L = m->embl[l];
-    GemmArgs a{w.h[l - 1], L.ldin, L.Wt, L.ldin, L.ldout, L.fout, Pptr, Pmax};
-    RUN("emb_fwd", gemm_tanh_res(a, L.b, nullptr, 0, w.h[l - 1], L.ldin, L.res, L.fin, w.h[l],
-                                 L.ldout, w.te[l], L.ldout, s));
+  const bool emb_fused = ne == 3 && emb_fused_supported(m->lde[0], m->lde[1], m->lde[2]);
+  EmbLaunch el{};
+  if (emb_fused) {
+    el = EmbLaunch{w.h[0], m->embl[1].Wt, m->embl[1].b, m->embl[2].Wt, m->embl[2].b,
+                   m->embl[1].Wb, m->embl[2].Wb, m->ws, m->emb[0], m->emb[1], m->emb[2],
+                   m->embl[1].res, m->embl[2].res, Pptr, Pmax};
+    RUN("emb_fwd", launch_emb_fwd(el, w.h[2], s));
+  } else {
+    for (int l = 1; l < ne; ++l) {
+      const Linear &L = m->embl[l];
+      GemmArgs a{w.h[l - 1], L.ldin, L.Wt, L.ldin, L.ldout, L.fout, Pptr, Pmax};
+      RUN("emb_fwd", gemm_tanh_res(a, L.b, nullptr, 0, w.h[l - 1], L.ldin, L.res, L.fin, w.h[l],
+                                   L.ldout, w.te[l], L.ldout, s));
+    }
   }
   // attention layers
   const int D = m->dattn, ldM = m->ldM;
@@ -706,7 +717,7 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
   float *dG_cur = w.dGa, *dG_nxt = w.dGb;
   float *emb_du_top = w.du[ne - 1];
   {
-    const int ln_mode = na > 0 ? 0 : 1;
+    const int ln_mode = na > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = na > 0 ? m->attn[na - 1].gamma : nullptr;
     const float *xh = na > 0 ? w.xhat[na - 1] : nullptr;
     const float *rs = na > 0 ? w.rstd[na - 1] : nullptr;
@@ -717,8 +728,10 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
   }
   if (na == 0) {
     RUN("zero_attn_grads", {
-      hipMemsetAsync(w.gw, 0, sizeof(float) * (size_t)Pmax, s);
-      hipMemsetAsync(w.gr, 0, sizeof(float) * 4 * (size_t)Pmax, s);
+      hipLaunchKernelGGL(k_fill_int, dim3((Pmax + 255) / 256), dim3(256), 0, s, (int *)w.gw,
+                         Pmax, 0);
+      hipLaunchKernelGGL(k_fill_int, dim3((4 * Pmax + 255) / 256), dim3(256), 0, s,
+                         (int *)w.gr, 4 * Pmax, 0);
     });
   }
   for (int a = na - 1; a >= 0; --a) {
@@ -726,10 +739,10 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s));
     RUN("attn_bwd", launch_attn_bwd(w.qkv[a], w.o[a], w.dO, w.geom, w.pair_off, w.nnei, nloc,
-                                    sel, D, (float)m->shift, w.dqkv, w.gw, w.gr,
-                                    a != na - 1, s));
+                                    sel, D, (float)m->shift, w.dqkv, w.gw, w.gr, w.astat,
+                                    w.qside, a != na - 1, s));
     GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax};
-    const int mode = a > 0 ? 0 : 1;
+    const int mode = a > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = a > 0 ? m->attn[a - 1].gamma : nullptr;
     const float *xh = a > 0 ? w.xhat[a - 1] : nullptr;
     const float *rs = a > 0 ? w.rstd[a - 1] : nullptr;
@@ -738,8 +751,9 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
     std::swap(dG_cur, dG_nxt);
   }
   // embedding adjoint; dG_cur is dE/dG0 = dE/dh_{ne-1}
+  if (emb_fused) RUN("emb_bwd", launch_emb_bwd(el, dG_cur, w.gs, s));
   w.dh[ne - 1] = dG_cur;
-  for (int l = ne - 1; l >= 1; --l) {
+  for (int l = ne - 1; l >= 1 && !emb_fused; --l) {
     const Linear &L = m->embl[l];
     GemmArgs a{w.du[l], L.ldout, L.Wb, L.ldout, L.ldin, L.fin, Pptr, Pmax};
     const int mode = L.res == RES_IDENT ? RES_IDENT : (L.res == RES_DOUBLE ? RES_FOLD : RES_NONE);
@@ -846,8 +860,8 @@ int dp_create(const char *weights_path, double rcut, int sel, dp_model **out) {
 
 void dp_destroy(dp_model *m) {
   if (!m) return;
-  hipSetDevice(m->device);
-  if (m->last) hipStreamSynchronize(m->last);
+  (void)hipSetDevice(m->device);
+  if (m->last) (void)hipStreamSynchronize(m->last);
   delete m;
 }
 
@@ -979,7 +993,7 @@ int dp_debug_nlist(dp_model *m, int32_t *nlist, int32_t *nnei) {
 
 int dp_set_timing(dp_model *m, int enable) {
   if (!m) return fail(DP_ERR_ARG, "model handle is NULL");
-  if (m->last) hipStreamSynchronize(m->last);
+  if (m->last) (void)hipStreamSynchronize(m->last);
   m->timer.collect();
   m->timer.enabled = enable != 0;
   m->timer.totals.clear();
@@ -988,7 +1002,7 @@ int dp_set_timing(dp_model *m, int enable) {
 
 int dp_kernel_times(dp_model *m, char *names, int64_t *counts, double *total_ms, int max) {
   if (!m) return fail(DP_ERR_ARG, "model handle is NULL");
-  if (m->last) hipStreamSynchronize(m->last);
+  if (m->last) (void)hipStreamSynchronize(m->last);
   m->timer.collect();
   int k = 0;
   for (auto &kv : m->timer.totals) {

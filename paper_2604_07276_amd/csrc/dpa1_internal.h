@@ -93,8 +93,8 @@ void gemm_bwd_tanh(const GemmArgs &a, const float *res, int ldr, int res_mode, i
                    hipStream_t s);
 // Backward of the attention input projections:
 //   dgin = acc + dgout; then either the layer-norm backward of the previous
-//   layer (mode 0: dy = rstd*(gamma*dgin - mean(.) - xhat*mean(gamma*dgin*xhat)))
-//   or the embedding tanh backward (mode 1: du = dgin * (1 - t^2)).
+//   layer (mode 0: dy = rstd*(gamma*dgin - mean(.) - xhat*mean(gamma*dgin*xhat))),
+//   the embedding tanh backward (mode 1: du = dgin * (1 - t^2)) or nothing (mode 2).
 void gemm_qkv_bwd(const GemmArgs &a, const float *dgout, int mode, const float *gamma,
                   const float *xhat, const float *rstd, const float *t, float *dgin,
                   float *dnext, hipStream_t s);
@@ -104,6 +104,25 @@ void gemm_emb1_bwd(const GemmArgs &a, const float *dh2, int ldd2, int res_mode, 
                    const float *h1, int ldh1, const float *ws, float *gs, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// fused embedding layers 2..3 and their adjoint (embed.hip)
+// ---------------------------------------------------------------------------
+struct EmbLaunch {
+  const float *h1;        // [P][ld0] first-layer output
+  const float *W2t, *b2;  // layer 2, transposed weights [ld1][ld0], bias [ld1]
+  const float *W3t, *b3;  // layer 3 [ld2][ld1], [ld2]
+  const float *W2b, *W3b; // adjoint operands [ld0][ld1], [ld1][ld2]
+  const float *ws;        // first-layer weight of s [ld0]
+  int n0, n1, n2;         // real widths
+  int res2, res3;         // residual rules (RES_NONE / RES_IDENT / RES_DOUBLE)
+  const int *Pptr;        // number of pairs (device)
+  int Pmax;
+};
+bool emb_fused_supported(int ld0, int ld1, int ld2);
+void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s);
+// dE/ds per pair from dE/dG0, recomputing the forward of layers 2..3.
+void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // per-centre kernels (attn.hip)
 // ---------------------------------------------------------------------------
 // Gated neighbour self-attention core, forward: O = (P o H) V per centre.
@@ -111,15 +130,18 @@ void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, c
                      int nloc, int sel, int dattn, float shift, float *out, hipStream_t s);
 // Backward of the core: dQKV, and accumulation of dE/dsw and dE/drhat per pair.
 hipError_t set_attn_bwd_lds_limit();
+// scratch4a/scratch4b: two per-pair float4 buffers (softmax statistics and
+// query-side sums handed from the query-tile kernel to the key-tile kernel).
 void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
                      const int *pair_off, const int *nnei, int nloc, int sel, int dattn,
-                     float shift, float *dqkv, float *gw, float *gr, int accumulate,
-                     hipStream_t s);
+                     float shift, float *dqkv, float *gw, float *gr, float *scratch4a,
+                     float *scratch4b, int accumulate, hipStream_t s);
 // Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,
                      const int *nnei, int nloc, int sel, int M, int axis, float *T, float *dmat,
                      hipStream_t s);
-// Descriptor backward and the layer-norm backward of the last attention layer.
+// Descriptor backward and the layer-norm backward of the last attention layer
+// (ln_mode 0), the tanh backward of the last embedding layer (1), or dG only (2).
 void launch_desc_bwd(const float *geom, const float *G, int ldg, const float *T,
                      const float *dD, const int *pair_off, const int *nnei, int nloc, int sel,
                      int M, int axis, int ln_mode, const float *gamma, const float *xhat,

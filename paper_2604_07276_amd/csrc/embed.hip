@@ -1,0 +1,303 @@
+// Fused embedding net (layers 2 and 3) forward, and its input-gradient
+// adjoint with recomputation, for the three-layer type-embedded embedding net
+// of DPA-1 (Sec. II-B: the embedding matrix G carries the type embedding).
+//
+// The first layer h1 = tanh(table[t_j][t_i] + ws * s) is produced per pair by
+// the geometry kernel.  Here one wavefront takes 32 pairs through
+//   h2 = tanh(h1 W2 + b2) + res(h1),   G0 = tanh(h2 W3 + b3) + res(h2)
+// on v_mfma_f32_16x16x4_f32 with the transposed-product layout (each lane
+// holds four consecutive columns of one row), in which the output of one
+// layer is already the B operand of the next, so nothing but the residual
+// lookups leaves the registers.  The adjoint recomputes h2 and the tanh
+// outputs from h1 instead of storing them, and ends with the scalar
+// dE/ds = sum_o dE/du1[o] * ws[o] per pair.
+#include "dpa1_internal.h"
+
+namespace dpa1 {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int MT = 2;  // 16-row tiles per wavefront
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k]  (W row-major [NTILE*16][KCH*16])
+template <int KCH, int NTILE>
+__device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
+                                      const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < KCH; ++c) {
+    floatx4 w[NTILE];
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt)
+      w[nt] = *(const floatx4 *)(W + (size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(w[nt][t], x[mt][c][t], acc[mt][nt]);
+  }
+}
+
+// value of the residual term for output column n: x[n] (identity), x[n mod fin]
+// (doubling) or 0, read from the wave's LDS copy of its rows.
+__device__ __forceinline__ float res_fwd(const float *rowp, int mode, int fin, int n) {
+  if (mode == RES_IDENT) return rowp[n];
+  if (mode == RES_DOUBLE) return rowp[n % fin];
+  return 0.f;
+}
+// gradient flowing back through the residual into input column k
+__device__ __forceinline__ float res_bwd(const float *rowp, int mode, int fin, int fout, int k) {
+  if (mode == RES_IDENT) return rowp[k];
+  if (mode == RES_DOUBLE) return rowp[k] + (k + fin < fout ? rowp[k + fin] : 0.f);
+  return 0.f;
+}
+
+struct EmbArgs {
+  const float *h1;        // [P][ld0]
+  const float *W2t, *b2;  // [ld1][ld0], [ld1]
+  const float *W3t, *b3;  // [ld2][ld1], [ld2]
+  const float *W2b, *W3b; // [ld0][ld1], [ld1][ld2]  (adjoint operands)
+  const float *ws;        // [ld0]
+  int n0, n1, n2;         // real widths
+  int res2, res3;         // residual rules of layers 2 and 3
+  const int *Pptr;
+};
+
+template <int C0, int C1, int C2>
+__global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
+  constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
+  __shared__ float xs[4][MT * 16][LD1 + 1];  // per wave: rows of h1 then h2
+  const int P = *a.Pptr;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  if (row0 >= P) return;
+  const int r = lane & 15, g = lane >> 4;
+  float(*xw)[LD1 + 1] = xs[wave];
+
+  floatx4 x0[MT][C0];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = row0 + mt * 16 + r;
+    const int rr = row < P ? row : 0;
+#pragma unroll
+    for (int c = 0; c < C0; ++c) {
+      x0[mt][c] = *(const floatx4 *)(a.h1 + (size_t)rr * LD0 + 16 * c + 4 * g);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
+    }
+  }
+  floatx4 acc1[MT][C1];
+  layer<C0, C1>(a.W2t, r, g, x0, acc1);
+  __builtin_amdgcn_wave_barrier();
+  floatx4 x1[MT][C1];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = nt * 16 + 4 * g + v;
+        float h = 0.f;
+        if (n < a.n1)
+          h = tanhf(acc1[mt][nt][v] + a.b2[n]) + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
+        x1[mt][nt][v] = h;
+      }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
+  floatx4 acc2[MT][C2];
+  layer<C1, C2>(a.W3t, r, g, x1, acc2);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = row0 + mt * 16 + r;
+    if (row >= P) continue;
+#pragma unroll
+    for (int nt = 0; nt < C2; ++nt) {
+      floatx4 o;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = nt * 16 + 4 * g + v;
+        o[v] = n < a.n2 ? tanhf(acc2[mt][nt][v] + a.b3[n]) +
+                              res_fwd(xw[mt * 16 + r], a.res3, a.n1, n)
+                        : 0.f;
+      }
+      *(floatx4 *)(G0 + (size_t)row * LD2 + nt * 16 + 4 * g) = o;
+    }
+  }
+}
+
+template <int C0, int C1, int C2>
+__global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__restrict__ dG0,
+                                                    float *__restrict__ gs) {
+  constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
+  __shared__ float xs[4][MT * 16][LD2 + 1];  // per wave: h1, h2, dG0, dh2 rows in turn
+  const int P = *a.Pptr;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  if (row0 >= P) return;
+  const int r = lane & 15, g = lane >> 4;
+  float(*xw)[LD2 + 1] = xs[wave];
+
+  // ---- recompute the forward
+  floatx4 x0[MT][C0];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = row0 + mt * 16 + r;
+    const int rr = row < P ? row : 0;
+#pragma unroll
+    for (int c = 0; c < C0; ++c) {
+      x0[mt][c] = *(const floatx4 *)(a.h1 + (size_t)rr * LD0 + 16 * c + 4 * g);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
+    }
+  }
+  floatx4 t1[MT][C1], x1[MT][C1];
+  {
+    floatx4 acc1[MT][C1];
+    layer<C0, C1>(a.W2t, r, g, x0, acc1);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          float t = 0.f, h = 0.f;
+          if (n < a.n1) {
+            t = tanhf(acc1[mt][nt][v] + a.b2[n]);
+            h = t + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
+          }
+          t1[mt][nt][v] = t;
+          x1[mt][nt][v] = h;
+        }
+  }
+  floatx4 d2[MT][C2];  // tanh output of layer 3, then dE/du3
+  {
+    floatx4 acc2[MT][C2];
+    layer<C1, C2>(a.W3t, r, g, x1, acc2);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < C2; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          d2[mt][nt][v] = n < a.n2 ? tanhf(acc2[mt][nt][v] + a.b3[n]) : 0.f;
+        }
+  }
+  // ---- adjoint: du3 = dG0 (1 - t3^2); dG0 rows also go to LDS for the residual
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = row0 + mt * 16 + r;
+    const int rr = row < P ? row : 0;
+#pragma unroll
+    for (int nt = 0; nt < C2; ++nt) {
+      const floatx4 gv = *(const floatx4 *)(dG0 + (size_t)rr * LD2 + nt * 16 + 4 * g);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        xw[mt * 16 + r][nt * 16 + 4 * g + v] = gv[v];
+        const float t = d2[mt][nt][v];
+        d2[mt][nt][v] = gv[v] * (1.0f - t * t);
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // dh2 = du3 W3^T + res^T(dG0) ; du2 = dh2 (1 - t2^2)
+  floatx4 du2[MT][C1];
+  {
+    floatx4 acc[MT][C1];
+    layer<C2, C1>(a.W3b, r, g, d2, acc);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = nt * 16 + 4 * g + v;
+          float d = 0.f;
+          if (k < a.n1) d = acc[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res3, a.n1, a.n2, k);
+          acc[mt][nt][v] = d;  // dh2
+          const float t = t1[mt][nt][v];
+          du2[mt][nt][v] = d * (1.0f - t * t);
+        }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = acc[mt][nt][v];
+    __builtin_amdgcn_wave_barrier();
+  }
+  // dh1 = du2 W2^T + res^T(dh2) ; du1 = dh1 (1 - h1^2) ; gs = du1 . ws
+  floatx4 acc0[MT][C0];
+  layer<C1, C0>(a.W2b, r, g, du2, acc0);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    float s = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < C0; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = nt * 16 + 4 * g + v;
+        if (k < a.n0) {
+          const float d = acc0[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res2, a.n0, a.n1, k);
+          const float h = x0[mt][nt][v];
+          s += d * (1.0f - h * h) * a.ws[k];
+        }
+      }
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    const int row = row0 + mt * 16 + r;
+    if (g == 0 && row < P) gs[row] = s;
+  }
+}
+
+template <class F>
+bool dispatch(int c0, int c1, int c2, F f) {
+  if (c0 == 2 && c1 == 4 && c2 == 7) {
+    f.template operator()<2, 4, 7>();
+    return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+bool emb_fused_supported(int ld0, int ld1, int ld2) {
+  return ld0 == 32 && ld1 == 64 && ld2 == 112;
+}
+
+void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
+  EmbArgs a{e.h1, e.W2t, e.b2, e.W3t, e.b3, e.W2b, e.W3b, e.ws, e.n0, e.n1, e.n2, e.res2, e.res3,
+            e.Pptr};
+  const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_emb_fwd<2, 4, 7>), dim3(blocks), dim3(256), 0, s, a, G0);
+}
+
+void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t s) {
+  EmbArgs a{e.h1, e.W2t, e.b2, e.W3t, e.b3, e.W2b, e.W3b, e.ws, e.n0, e.n1, e.n2, e.res2, e.res3,
+            e.Pptr};
+  const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_emb_bwd<2, 4, 7>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+}
+
+}  // namespace dpa1

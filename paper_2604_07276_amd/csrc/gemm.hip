@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int row = row0 + mt * 16 + r;
-    xok[mt] = row < M;
+    xok[mt] = row < M;  // rows past M read row 0 and are never stored
     xrow[mt] = a.X + (size_t)(xok[mt] ? row : 0) * a.ldx + 4 * g;
   }
   const float *wrow[NT];
@@ -72,8 +72,7 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   // accumulators back to back.
   floatx4 xv[MT], wv[NT], xn[MT], wn[NT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-    xv[mt] = xok[mt] ? *(const floatx4 *)(xrow[mt]) : floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int mt = 0; mt < MT; ++mt) xv[mt] = *(const floatx4 *)(xrow[mt]);
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
     wv[nt] = *(const floatx4 *)(wrow[nt]);
@@ -81,12 +80,11 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   for (int k0 = 0; k0 < a.K; k0 += 16) {
     const int kn = k0 + 16 < a.K ? k0 + 16 : k0;  // last chunk reloads itself (unused)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      xn[mt] = xok[mt] ? *(const floatx4 *)(xrow[mt] + kn) : floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt) xn[mt] = *(const floatx4 *)(xrow[mt] + kn);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
       wn[nt] = *(const floatx4 *)(wrow[nt] + kn);
-    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
     // Tiles past the last column tile (nt0 + nt >= ntt) multiply a duplicate of
     // tile 0 and are never stored: no branch inside the MFMA sequence.
 #pragma unroll
@@ -357,6 +355,10 @@ struct EpiQKVBwd {
         if (nt >= ntt) continue;
         const int n0 = nt * 16 + 4 * g;
         floatx4 dn;
+        if (mode == 2) {
+          *(floatx4 *)(dgin + rb + n0) = acc[mt][nt];
+          continue;
+        }
         if (mode == 0) {
           const floatx4 xh = *(const floatx4 *)(xhat + rb + n0);
 #pragma unroll
