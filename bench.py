@@ -48,21 +48,28 @@ def flop_model(nnei: np.ndarray, shape) -> dict:
     f = shape["fit"]
     fit = 2.0 * (fin0 * f[0] + sum(f[i] * f[i + 1] for i in range(len(f) - 1)) + f[-1]) * nloc
     emb_gemm = 2.0 * sum(emb[i] * emb[i + 1] for i in range(len(emb) - 1)) * P
-    return {
+    out = {
         "env_embed1": (2.0 * (1 + 2 * shape["tebd"]) * emb[0] * P, 1),
-        "emb_fwd": (emb_gemm, len(emb) - 1),
+        "emb_fwd": (emb_gemm, 1),
         "qkv_fwd": (L * 2.0 * M * 3 * d * P, L),
-        "attn_fwd": (L * 2.0 * 2 * d * n2, L),
         "oproj_ln_fwd": (L * 2.0 * d * M * P, L),
         "desc_fwd": (2.0 * 4 * M * P + 2.0 * 4 * M * shape["axis"] * nloc, 1),
         "fit_fwd": (fit, len(f)),
         "fit_bwd": (fit, len(f)),
         "desc_bwd": (2.0 * 2 * 4 * M * P + 2.0 * 2 * 4 * M * shape["axis"] * nloc, 1),
         "oproj_bwd": (L * 2.0 * d * M * P, L),
-        "attn_bwd": (L * 2.0 * 4 * d * n2, L),
         "qkv_bwd": (L * 2.0 * M * 3 * d * P, L),
-        "emb_bwd": (emb_gemm, len(emb) - 1),
+        "emb_bwd": (emb_gemm, 1),
     }
+    # attention core, per neighbour-count class (n in (32c, 32c + 32]):
+    # forward QK^T and AV; backward dA, dQ (query tiles) and dK, dV (key tiles)
+    nn = nnei.astype(np.float64)
+    for c, npad in enumerate((32, 64, 96, 128)):
+        sel_c = (nnei > npad - 32) & (nnei <= npad)
+        n2c = float((nn[sel_c] ** 2).sum())
+        for name in ("attn_fwd", "attn_bwd_q", "attn_bwd_k"):
+            out[f"{name}_n{npad}"] = (L * 2.0 * 2 * d * n2c, L)
+    return out
 
 
 def cpu_baseline(weights_path, sysm, budget_s: float) -> dict:

@@ -103,6 +103,30 @@ int dp_compute_device(dp_model *m, const double *d_coords, const int32_t *d_type
                       double *d_forces, double *d_virial, double *d_atom_energy,
                       void *hip_stream);
 
+/*
+ * Forward half of dp_compute_device, for use under reverse-mode automatic
+ * differentiation: computes d_energy [1] and (optionally) d_atom_energy
+ * [nloc] on the caller's stream and keeps every activation the adjoint needs
+ * in the handle.  The coordinates at d_coords must stay unchanged until the
+ * matching dp_backward_device has been enqueued.  Forces are the negative
+ * gradient of the energy (Eq. (2)); splitting the step this way lets a caller
+ * put per-atom weights on the energies (Eq. (5): E = sum e_i).
+ */
+int dp_forward_device(dp_model *m, const double *d_coords, const int32_t *d_types,
+                      const double *box, int nloc, int nghost, double *d_energy,
+                      double *d_atom_energy, void *hip_stream);
+
+/*
+ * Adjoint of the last dp_forward_device on this handle: writes
+ * d_grad_coords [(nloc+nghost)*3] = d(sum_i w_i e_i)/dx for every atom
+ * (ghosts included, Eq. (7)), with w = d_atom_weight [nloc] (device, or NULL
+ * for all ones), and optionally the weighted virial d_virial [9]
+ * (Xi_ab = -sum_i w_i sum_j d_ij,a de_i/dd_ij,b).  May be called more than
+ * once per forward with different weights.  Asynchronous on the stream.
+ */
+int dp_backward_device(dp_model *m, const double *d_atom_weight, double *d_grad_coords,
+                       double *d_virial, void *hip_stream);
+
 /* Wait for the handle's last step and return its device-side status. */
 int dp_sync(dp_model *m);
 

@@ -22,8 +22,9 @@ STATUS_NAMES = {
     -1: "DP_ERR_ARG", -2: "DP_ERR_TYPE", -3: "DP_ERR_BOX", -4: "DP_ERR_SEL_OVERFLOW",
     -5: "DP_ERR_WEIGHTS", -6: "DP_ERR_DEVICE", -7: "DP_ERR_OOM",
 }
-EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_sync", "dp_debug_nlist",
-            "dp_set_timing", "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error")
+EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
+            "dp_backward_device", "dp_sync", "dp_debug_nlist", "dp_set_timing", "dp_kernel_times",
+            "dp_model_info", "dp_destroy", "dp_last_error")
 
 _lib = None
 
@@ -48,6 +49,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_create.argtypes = [ctypes.c_char_p, D, I, ctypes.POINTER(P)]
     lib.dp_compute.argtypes = [P, P, P, P, I, I, P, P, P, P]
     lib.dp_compute_device.argtypes = [P, P, P, P, I, I, P, P, P, P, P]
+    lib.dp_forward_device.argtypes = [P, P, P, P, I, I, P, P, P]
+    lib.dp_backward_device.argtypes = [P, P, P, P, P]
     lib.dp_sync.argtypes = [P]
     lib.dp_debug_nlist.argtypes = [P, P, P]
     lib.dp_set_timing.argtypes = [P, I]
@@ -57,8 +60,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_destroy.restype = None
     lib.dp_last_error.argtypes = []
     lib.dp_last_error.restype = ctypes.c_char_p
-    for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_sync", "dp_debug_nlist",
-                 "dp_set_timing", "dp_kernel_times", "dp_model_info"):
+    for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
+                 "dp_backward_device", "dp_sync", "dp_debug_nlist", "dp_set_timing",
+                 "dp_kernel_times", "dp_model_info"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -138,6 +142,26 @@ class Model:
         _check(_lib.dp_compute_device(self._h, _ptr(coords), _ptr(types), _ptr(boxa), nloc,
                                       nghost, _ptr(energy), _ptr(forces), _ptr(virial),
                                       _ptr(atom_energy), sp))
+
+    def forward_device(self, coords, types, box, nloc: int, nghost: int, energy,
+                       atom_energy=None, stream=None):
+        """Forward half (dp_forward_device): energies only, activations kept."""
+        import torch
+        boxa = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(_lib.dp_forward_device(self._h, _ptr(coords), _ptr(types), _ptr(boxa), nloc,
+                                      nghost, _ptr(energy), _ptr(atom_energy), sp))
+
+    def backward_device(self, grad_coords, atom_weight=None, virial=None, stream=None):
+        """Adjoint of the last forward (dp_backward_device): d(sum_i w_i e_i)/dx."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(_lib.dp_backward_device(self._h, _ptr(atom_weight), _ptr(grad_coords),
+                                       _ptr(virial), sp))
 
     def sync(self):
         """Wait for the last step; raises on a device-side error (overflow, bad type)."""

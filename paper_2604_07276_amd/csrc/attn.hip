@@ -572,6 +572,7 @@ __global__ __launch_bounds__(128) void k_desc_fwd(const float *__restrict__ geom
   const int m = threadIdx.x;
   float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
   if (m < M) {
+#pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const float *gp = geom + (size_t)(base + j) * kGeom;
       const float s = gp[G_S];
@@ -608,8 +609,10 @@ __global__ __launch_bounds__(128) void k_desc_fwd(const float *__restrict__ geom
 
 // dT[c][m] = sum_a dD[m][a] T[c][a] + [m < axis] sum_m' dD[m'][m] T[c][m'];
 // per pair: dG_j = (1/sel) R~_j dT, dR~_j = (1/sel) dT G_j, then the
-// layer-norm backward of the last attention layer (ln_mode 0) or the tanh
-// backward of the last embedding layer (ln_mode 1).
+// layer-norm backward of the last attention layer (ln_mode 0), the tanh
+// backward of the last embedding layer (ln_mode 1), or dG only (ln_mode 2).
+// Sixteen lanes share a pair (lane li holds features li + 16k), so the row
+// reductions take four cross-lane steps and four pairs run per wavefront.
 __global__ __launch_bounds__(256) void k_desc_bwd(
     const float *__restrict__ geom, const float *__restrict__ G, int ldg,
     const float *__restrict__ T, const float *__restrict__ dD, int ldd,
@@ -617,8 +620,10 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
     int ln_mode, const float *__restrict__ gamma, const float *__restrict__ xhat,
     const float *__restrict__ rstd, const float *__restrict__ temb, float *__restrict__ dG,
     float *__restrict__ dnext, float *__restrict__ dRt) {
+  constexpr int KF = 8;  // features per lane: 16 lanes x 8 = 128 >= ldg
   __shared__ float Ts[4][128];
   __shared__ float dTs[4][128];
+  __shared__ float part[16][16][4];
   const int i = blockIdx.x;
   const int n = nnei[i];
   const int base = pair_off[i];
@@ -627,24 +632,44 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
     for (int c = 0; c < 4; ++c) Ts[c][tid] = tid < M ? T[(size_t)i * 4 * M + c * M + tid] : 0.f;
   }
   __syncthreads();
-  const float inv = 1.0f / (float)sel;
-  if (tid < M) {
-    const float *dr = dD + (size_t)i * ldd;
-    float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-    for (int a = 0; a < axis; ++a) {
-      const float x = dr[tid * axis + a];
-      d0 += x * Ts[0][a];
-      d1 += x * Ts[1][a];
-      d2 += x * Ts[2][a];
-      d3 += x * Ts[3][a];
+  const float *dr = dD + (size_t)i * ldd;
+  // second term, spread over all threads: a = tid % 16, rows m' = tid/16 + 16k
+  {
+    const int aa = tid & 15, pp = tid >> 4;
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+    if (aa < axis) {
+      for (int mm = pp; mm < M; mm += 16) {
+        const float x = dr[mm * axis + aa];
+        q0 += x * Ts[0][mm];
+        q1 += x * Ts[1][mm];
+        q2 += x * Ts[2][mm];
+        q3 += x * Ts[3][mm];
+      }
     }
-    if (tid < axis) {
-      for (int mm = 0; mm < M; ++mm) {
-        const float x = dr[mm * axis + tid];
-        d0 += x * Ts[0][mm];
-        d1 += x * Ts[1][mm];
-        d2 += x * Ts[2][mm];
-        d3 += x * Ts[3][mm];
+    part[pp][aa][0] = q0;
+    part[pp][aa][1] = q1;
+    part[pp][aa][2] = q2;
+    part[pp][aa][3] = q3;
+  }
+  __syncthreads();
+  const float inv = 1.0f / (float)sel;
+  if (tid < 128) {
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+    if (tid < M) {
+      for (int a = 0; a < axis; ++a) {
+        const float x = dr[tid * axis + a];
+        d0 += x * Ts[0][a];
+        d1 += x * Ts[1][a];
+        d2 += x * Ts[2][a];
+        d3 += x * Ts[3][a];
+      }
+      if (tid < axis && tid < 16) {
+        for (int pp = 0; pp < 16; ++pp) {
+          d0 += part[pp][tid][0];
+          d1 += part[pp][tid][1];
+          d2 += part[pp][tid][2];
+          d3 += part[pp][tid][3];
+        }
       }
     }
     dTs[0][tid] = d0 * inv;
@@ -653,37 +678,38 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
     dTs[3][tid] = d3 * inv;
   }
   __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
+  const int grp = tid >> 4, li = tid & 15;
   const float invm = 1.0f / (float)M;
-  for (int j = wave; j < n; j += 4) {
+  for (int j = grp; j < n; j += 16) {
     const size_t p = (size_t)(base + j);
     const float *gp = geom + p * kGeom;
     const float s = gp[G_S];
     const float R0 = s, R1 = s * gp[G_RX], R2 = s * gp[G_RY], R3 = s * gp[G_RZ];
-    float dg[2], xh[2];
+    float dg[KF], xh[KF];
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int m = lane + 64 * h;
-      dg[h] = 0.f;
-      xh[h] = 0.f;
+    for (int k = 0; k < KF; ++k) {
+      const int m = li + 16 * k;
+      dg[k] = 0.f;
+      xh[k] = 0.f;
       if (m < M) {
         const float gm = G[p * ldg + m];
         const float v = R0 * dTs[0][m] + R1 * dTs[1][m] + R2 * dTs[2][m] + R3 * dTs[3][m];
-        dg[h] = v;
+        dg[k] = v;
         a0 += gm * dTs[0][m];
         a1 += gm * dTs[1][m];
         a2 += gm * dTs[2][m];
         a3 += gm * dTs[3][m];
         if (ln_mode == 0) {
-          xh[h] = xhat[p * ldg + m];
+          xh[k] = xhat[p * ldg + m];
           const float dx = gamma[m] * v;
           s1 += dx;
-          s2 += dx * xh[h];
+          s2 += dx * xh[k];
         }
       }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
       a0 += __shfl_xor(a0, off);
       a1 += __shfl_xor(a1, off);
       a2 += __shfl_xor(a2, off);
@@ -693,29 +719,23 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
     }
     const float rs = ln_mode == 0 ? rstd[p] : 0.f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int m = lane + 64 * h;
+    for (int k = 0; k < KF; ++k) {
+      const int m = li + 16 * k;
       if (m < ldg) {
         float nx = 0.f;
         if (m < M) {
           if (ln_mode == 0) {
-            nx = rs * (gamma[m] * dg[h] - s1 * invm - xh[h] * s2 * invm);
+            nx = rs * (gamma[m] * dg[k] - s1 * invm - xh[k] * s2 * invm);
           } else if (ln_mode == 1) {
             const float t = temb[p * ldg + m];
-            nx = dg[h] * (1.0f - t * t);
+            nx = dg[k] * (1.0f - t * t);
           }
         }
-        dG[p * ldg + m] = dg[h];
+        dG[p * ldg + m] = dg[k];
         if (ln_mode != 2) dnext[p * ldg + m] = nx;
       }
     }
-    if (lane == 0) {
-      float *dp = dRt + 4 * p;
-      dp[0] = a0;
-      dp[1] = a1;
-      dp[2] = a2;
-      dp[3] = a3;
-    }
+    if (li == 0) *(float4 *)(dRt + 4 * p) = make_float4(a0, a1, a2, a3);
   }
 }
 
@@ -759,14 +779,47 @@ void bwdk_one(const float *qkv, const float *dO, const float *geom, const int *p
 
 }  // namespace
 
-void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, const int *nnei,
-                     int nloc, int sel, int dattn, float shift, float *out, hipStream_t s) {
-  (void)dattn;
+int attn_class_count(int sel) { return sel <= 32 ? 1 : sel <= 64 ? 2 : sel <= 96 ? 3 : 4; }
+int attn_class_npad(int cls) { return 32 * (cls + 1); }
+
+void launch_attn_fwd_class(int cls, const float *qkv, const float *geom, const int *pair_off,
+                           const int *nnei, int nloc, int sel, float shift, float *out,
+                           hipStream_t s) {
   if (nloc <= 0) return;
-  fwd_one<32>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 0, s);
-  if (sel > 32) fwd_one<64>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 32, s);
-  if (sel > 64) fwd_one<96>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 64, s);
-  if (sel > 96) fwd_one<128>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 96, s);
+  switch (cls) {
+    case 0: fwd_one<32>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 0, s); break;
+    case 1: fwd_one<64>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 32, s); break;
+    case 2: fwd_one<96>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 64, s); break;
+    default: fwd_one<128>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 96, s); break;
+  }
+}
+
+void launch_attn_bwd_q_class(int cls, const float *qkv, const float *o, const float *dO,
+                             const float *geom, const int *pair_off, const int *nnei, int nloc,
+                             int sel, float shift, float *dqkv, float *astat, float *qside,
+                             hipStream_t s) {
+  if (nloc <= 0) return;
+  float4 *a4 = (float4 *)astat, *q4 = (float4 *)qside;
+  switch (cls) {
+    case 0: bwdq_one<32>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 0, s); break;
+    case 1: bwdq_one<64>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 32, s); break;
+    case 2: bwdq_one<96>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 64, s); break;
+    default: bwdq_one<128>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 96, s); break;
+  }
+}
+
+void launch_attn_bwd_k_class(int cls, const float *qkv, const float *dO, const float *geom,
+                             const int *pair_off, const int *nnei, int nloc, float shift,
+                             float *dqkv, const float *astat, const float *qside, float *gw,
+                             float *gr, int accumulate, hipStream_t s) {
+  if (nloc <= 0) return;
+  const float4 *a4 = (const float4 *)astat, *q4 = (const float4 *)qside;
+  switch (cls) {
+    case 0: bwdk_one<32>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 0, s); break;
+    case 1: bwdk_one<64>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 32, s); break;
+    case 2: bwdk_one<96>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 64, s); break;
+    default: bwdk_one<128>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 96, s); break;
+  }
 }
 
 hipError_t set_attn_bwd_lds_limit() {
@@ -780,33 +833,6 @@ hipError_t set_attn_bwd_lds_limit() {
     e = hipFuncSetAttribute((const void *)k_attn_fwd<128>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<128>());
   return e;
-}
-
-void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
-                     const int *pair_off, const int *nnei, int nloc, int sel, int dattn,
-                     float shift, float *dqkv, float *gw, float *gr, float *scratch4a,
-                     float *scratch4b, int accumulate, hipStream_t s) {
-  (void)dattn;
-  if (nloc <= 0) return;
-  float4 *astat = (float4 *)scratch4a, *qside = (float4 *)scratch4b;
-  bwdq_one<32>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 0, s);
-  if (sel > 32)
-    bwdq_one<64>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 32, s);
-  if (sel > 64)
-    bwdq_one<96>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 64, s);
-  if (sel > 96)
-    bwdq_one<128>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, astat, qside, 96, s);
-  bwdk_one<32>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr, accumulate,
-               0, s);
-  if (sel > 32)
-    bwdk_one<64>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr,
-                 accumulate, 32, s);
-  if (sel > 64)
-    bwdk_one<96>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr,
-                 accumulate, 64, s);
-  if (sel > 96)
-    bwdk_one<128>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, astat, qside, gw, gr,
-                  accumulate, 96, s);
 }
 
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,

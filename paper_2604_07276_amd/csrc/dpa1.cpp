@@ -153,6 +153,12 @@ struct dp_model {
   hipStream_t last = nullptr;
   bool have_step = false;
   int last_nloc = 0;
+  struct FwdState {
+    const double *coords;  // caller's device coordinates of the last forward
+    CellGrid grid;
+    int nloc, nall;
+    bool valid;
+  } fwd{};
   Timer timer;
 
   ~dp_model() {
@@ -271,7 +277,8 @@ int load_weights(dp_model *m, const char *path) {
     if (w < 1 || w > 128) return fail(DP_ERR_WEIGHTS, "embedding widths must be in [1, 128]");
   for (int w : m->fit)
     if (w < 1 || w > 4096) return fail(DP_ERR_WEIGHTS, "bad fitting width");
-  if (m->axis < 1 || m->axis > m->M) return fail(DP_ERR_WEIGHTS, "bad axis width");
+  if (m->axis < 1 || m->axis > m->M || m->axis > 16)
+    return fail(DP_ERR_WEIGHTS, "axis width must be in [1, min(16, M)]");
   if (m->n_attn < 0 || m->n_attn > 16) return fail(DP_ERR_WEIGHTS, "bad attention layer count");
   if (m->n_attn > 0 && m->dattn != 128)
     return fail(DP_ERR_WEIGHTS, "attention width %d unsupported (this build: 128)", m->dattn);
@@ -602,6 +609,14 @@ __global__ void k_bbox(const double *x, int n, double *out) {
 
 // ------------------------------------------------------------------- the step
 
+// timer names of the per-class attention launches (class c covers n in (32c, 32c + 32])
+const char *const kAttnFwdName[4] = {"attn_fwd_n32", "attn_fwd_n64", "attn_fwd_n96",
+                                     "attn_fwd_n128"};
+const char *const kAttnBwdQName[4] = {"attn_bwd_q_n32", "attn_bwd_q_n64", "attn_bwd_q_n96",
+                                      "attn_bwd_q_n128"};
+const char *const kAttnBwdKName[4] = {"attn_bwd_k_n32", "attn_bwd_k_n64", "attn_bwd_k_n96",
+                                      "attn_bwd_k_n128"};
+
 #define RUN(name, call)                                           \
   do {                                                            \
     hipEvent_t a_ = nullptr, b_ = nullptr;                        \
@@ -617,9 +632,11 @@ __global__ void k_bbox(const double *x, int n, double *out) {
     }                                                             \
   } while (0)
 
-int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, const CellGrid &grid,
-                 int nloc, int nall, double *d_energy, double *d_forces, double *d_virial,
-                 double *d_atom_energy, hipStream_t s) {
+// Forward half of the step: neighbour lists through the atomic energies.
+// Leaves every activation the adjoint needs in the workspace.
+int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
+                    const CellGrid &grid, int nloc, int nall, double *d_energy,
+                    double *d_atom_energy, hipStream_t s) {
   auto &w = m->w;
   const int sel = m->sel;
   const int Pmax = nloc * sel;
@@ -667,8 +684,9 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
     const auto &A = m->attn[a];
     GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax};
     RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s));
-    RUN("attn_fwd", launch_attn_fwd(w.qkv[a], w.geom, w.pair_off, w.nnei, nloc, sel, D,
-                                    (float)m->shift, w.o[a], s));
+    for (int cls = 0; cls < attn_class_count(sel); ++cls)
+      RUN(kAttnFwdName[cls], launch_attn_fwd_class(cls, w.qkv[a], w.geom, w.pair_off, w.nnei,
+                                                   nloc, sel, (float)m->shift, w.o[a], s));
     GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax};
     RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
                                     w.G[a + 1], w.xhat[a], w.rstd[a], s));
@@ -690,6 +708,37 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
   }
   RUN("energy", launch_energy(w.z[nf - 1], w.tf[nf - 1], m->ldf[nf - 1], m->fit[nf - 1],
                               m->w_out, m->b_out, m->ebias, d_types, nloc, w.e, w.fa[nf - 1], s));
+  if (d_energy)
+    RUN("reduce", launch_reduce(w.e, w.vir_part, nloc, d_energy, nullptr, d_atom_energy, s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(m->flags_host, m->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, s));
+  m->last = s;
+  m->have_step = true;
+  m->last_nloc = nloc;
+  m->fwd = dp_model::FwdState{d_coords, grid, nloc, nall, true};
+  return DP_OK;
+}
+
+// Adjoint half: from unit seeds de_i/de_i down to g_ij = de_i/dd_ij, then the
+// weighted gather sign * (-sum_i wgt_i de_i/dx_k) and the virial.
+int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
+                     double *d_virial, hipStream_t s) {
+  auto &w = m->w;
+  const dp_model::FwdState &fs = m->fwd;
+  const double *d_coords = fs.coords;
+  const CellGrid &grid = fs.grid;
+  const int nloc = fs.nloc, nall = fs.nall;
+  const int sel = m->sel;
+  const int Pmax = nloc * sel;
+  const int *Pptr = w.pair_off + nloc;
+  const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
+  const int D = m->dattn, ldM = m->ldM;
+  const bool emb_fused = ne == 3 && emb_fused_supported(m->lde[0], m->lde[1], m->lde[2]);
+  EmbLaunch el{};
+  if (emb_fused)
+    el = EmbLaunch{w.h[0], m->embl[1].Wt, m->embl[1].b, m->embl[2].Wt, m->embl[2].b,
+                   m->embl[1].Wb, m->embl[2].Wb, m->ws, m->emb[0], m->emb[1], m->emb[2],
+                   m->embl[1].res, m->embl[2].res, Pptr, Pmax};
   // fitting adjoint: fa[l] = dz_l * (1 - t_l^2) ; dz_{l-1} = fa[l] W_l^T + res^T(dz_l)
   for (int l = nf - 1; l >= 1; --l) {
     const Linear &L = m->fitl[l];
@@ -738,9 +787,15 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
     const auto &A = m->attn[a];
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s));
-    RUN("attn_bwd", launch_attn_bwd(w.qkv[a], w.o[a], w.dO, w.geom, w.pair_off, w.nnei, nloc,
-                                    sel, D, (float)m->shift, w.dqkv, w.gw, w.gr, w.astat,
-                                    w.qside, a != na - 1, s));
+    for (int cls = 0; cls < attn_class_count(sel); ++cls)
+      RUN(kAttnBwdQName[cls],
+          launch_attn_bwd_q_class(cls, w.qkv[a], w.o[a], w.dO, w.geom, w.pair_off, w.nnei, nloc,
+                                  sel, (float)m->shift, w.dqkv, w.astat, w.qside, s));
+    for (int cls = 0; cls < attn_class_count(sel); ++cls)
+      RUN(kAttnBwdKName[cls],
+          launch_attn_bwd_k_class(cls, w.qkv[a], w.dO, w.geom, w.pair_off, w.nnei, nloc,
+                                  (float)m->shift, w.dqkv, w.astat, w.qside, w.gw, w.gr,
+                                  a != na - 1, s));
     GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax};
     const int mode = a > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = a > 0 ? m->attn[a - 1].gamma : nullptr;
@@ -767,14 +822,20 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
   }
   RUN("env_bwd", launch_env_bwd(w.geom, w.gs, w.dRt, w.gw, w.gr, Pptr, Pmax, 0.f, w.g, s));
   RUN("forces", launch_forces(d_coords, grid, nloc, nall, sel, w.nlist, w.nnei, w.pair_off, w.g,
-                              d_forces, w.vir_part, s));
-  RUN("reduce", launch_reduce(w.e, w.vir_part, nloc, d_energy, d_virial, d_atom_energy, s));
+                              wgt, sign, d_out, w.vir_part, s));
+  if (d_virial)
+    RUN("reduce", launch_reduce(w.e, w.vir_part, nloc, nullptr, d_virial, nullptr, s));
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(m->flags_host, m->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, s));
   m->last = s;
-  m->have_step = true;
-  m->last_nloc = nloc;
   return DP_OK;
+}
+
+int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, const CellGrid &grid,
+                 int nloc, int nall, double *d_energy, double *d_forces, double *d_virial,
+                 double *d_atom_energy, hipStream_t s) {
+  int rc = enqueue_forward(m, d_coords, d_types, grid, nloc, nall, d_energy, d_atom_energy, s);
+  if (rc) return rc;
+  return enqueue_backward(m, nullptr, 1.0, d_forces, d_virial, s);
 }
 
 int check_flags(dp_model *m) {
@@ -962,6 +1023,47 @@ int dp_compute_device(dp_model *m, const double *d_coords, const int32_t *d_type
   if ((rc = ensure_workspace(m, nloc, nall, grid.ncell))) return rc;
   return enqueue_step(m, d_coords, d_types, grid, nloc, nall, d_energy, d_forces, d_virial,
                       d_atom_energy, s);
+}
+
+int dp_forward_device(dp_model *m, const double *d_coords, const int32_t *d_types,
+                      const double *box, int nloc, int nghost, double *d_energy,
+                      double *d_atom_energy, void *hip_stream) {
+  g_err.clear();
+  double dummy = 0.0;
+  int rc = common_checks(m, d_coords, d_types, nloc, nghost, d_energy, &dummy, &dummy);
+  if (rc) return rc;
+  const int nall = nloc + nghost;
+  if ((rc = set_device(m))) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  if (!box && nall > 0) {
+    double hb[6];
+    hipLaunchKernelGGL(k_bbox, dim3(1), dim3(256), 0, s, d_coords, nall, m->bbox);
+    HIP_TRY(hipMemcpyAsync(hb, m->bbox, sizeof(hb), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = hb[c];
+      hi[c] = hb[3 + c];
+      if (!std::isfinite(lo[c]) || !std::isfinite(hi[c]))
+        return fail(DP_ERR_ARG, "coordinates are not finite");
+    }
+  }
+  CellGrid grid;
+  if ((rc = make_grid(m, box, lo, hi, grid))) return rc;
+  if ((rc = ensure_workspace(m, nloc, nall, grid.ncell))) return rc;
+  return enqueue_forward(m, d_coords, d_types, grid, nloc, nall, d_energy, d_atom_energy, s);
+}
+
+int dp_backward_device(dp_model *m, const double *d_atom_weight, double *d_grad_coords,
+                       double *d_virial, void *hip_stream) {
+  g_err.clear();
+  if (!m) return fail(DP_ERR_ARG, "model handle is NULL");
+  if (!m->fwd.valid) return fail(DP_ERR_ARG, "no forward step to differentiate");
+  if (m->fwd.nall > 0 && !d_grad_coords) return fail(DP_ERR_ARG, "d_grad_coords is NULL");
+  int rc;
+  if ((rc = set_device(m))) return rc;
+  return enqueue_backward(m, d_atom_weight, -1.0, d_grad_coords, d_virial,
+                          (hipStream_t)hip_stream);
 }
 
 int dp_sync(dp_model *m) {

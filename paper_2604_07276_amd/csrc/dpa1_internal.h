@@ -125,17 +125,28 @@ void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t
 // ---------------------------------------------------------------------------
 // per-centre kernels (attn.hip)
 // ---------------------------------------------------------------------------
-// Gated neighbour self-attention core, forward: O = (P o H) V per centre.
-void launch_attn_fwd(const float *qkv, const float *geom, const int *pair_off, const int *nnei,
-                     int nloc, int sel, int dattn, float shift, float *out, hipStream_t s);
-// Backward of the core: dQKV, and accumulation of dE/dsw and dE/drhat per pair.
+// Gated neighbour self-attention core.  Centres are split by neighbour
+// count into classes of 32/64/96/128 slots (class c covers n in
+// (32c, 32(c+1)]); every launch below covers one class.
+int attn_class_count(int sel);
+int attn_class_npad(int cls);
+// Forward: O = (P o H) V per centre.
+void launch_attn_fwd_class(int cls, const float *qkv, const float *geom, const int *pair_off,
+                           const int *nnei, int nloc, int sel, float shift, float *out,
+                           hipStream_t s);
+// Backward, query tiles: dQ, softmax statistics and query-side gate/switch
+// gradients (astat, qside: per-pair float4 buffers read by the key-tile pass).
+void launch_attn_bwd_q_class(int cls, const float *qkv, const float *o, const float *dO,
+                             const float *geom, const int *pair_off, const int *nnei, int nloc,
+                             int sel, float shift, float *dqkv, float *astat, float *qside,
+                             hipStream_t s);
+// Backward, key tiles: dK, dV and the total dE/dsw, dE/drhat per pair
+// (accumulated onto gw/gr when accumulate != 0).
+void launch_attn_bwd_k_class(int cls, const float *qkv, const float *dO, const float *geom,
+                             const int *pair_off, const int *nnei, int nloc, float shift,
+                             float *dqkv, const float *astat, const float *qside, float *gw,
+                             float *gr, int accumulate, hipStream_t s);
 hipError_t set_attn_bwd_lds_limit();
-// scratch4a/scratch4b: two per-pair float4 buffers (softmax statistics and
-// query-side sums handed from the query-tile kernel to the key-tile kernel).
-void launch_attn_bwd(const float *qkv, const float *o, const float *dO, const float *geom,
-                     const int *pair_off, const int *nnei, int nloc, int sel, int dattn,
-                     float shift, float *dqkv, float *gw, float *gr, float *scratch4a,
-                     float *scratch4b, int accumulate, hipStream_t s);
 // Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,
                      const int *nnei, int nloc, int sel, int M, int axis, float *T, float *dmat,
@@ -160,11 +171,15 @@ void launch_env_bwd(const float *geom, const float *gs, const float *dRt, const 
                     const float *gr, const int *Mptr, int Mmax, float sel_inv_unused,
                     float *g, hipStream_t s);
 // Forces by a deterministic gather over the full neighbour lists, per-centre
-// virial partials and FP64 outputs.
+// virial partials and FP64 outputs.  With per-centre weights wgt (nullable =
+// all ones) the result is sign * (-sum_i wgt_i de_i/dx_k); sign = +1 gives
+// forces, sign = -1 the gradient of sum_i wgt_i e_i.
 void launch_forces(const double *coords, CellGrid grid, int nloc, int nall, int sel,
                    const int *nlist, const int *nnei, const int *pair_off, const float *g,
-                   double *forces, double *vir_part, hipStream_t s);
+                   const double *wgt, double sign, double *forces, double *vir_part,
+                   hipStream_t s);
 // E = sum e_i, Xi = sum of partials (fixed-order FP64 reductions); atom_energy.
+// energy == nullptr skips the energy part, virial == nullptr the virial part.
 void launch_reduce(const float *e, const double *vir_part, int nloc, double *energy,
                    double *virial, double *atom_energy, hipStream_t s);
 

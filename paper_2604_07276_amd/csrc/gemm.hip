@@ -101,6 +101,68 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
 }
 
+// Persistent variant for the large pair-batched products whose weight tile
+// fits in LDS (K = KCH*16 <= 128): each workgroup stages its W^T column
+// block [NT*16][K] in LDS once and then walks over row tiles (4 waves x
+// 16*MT rows), so weights are read from L2 once per workgroup instead of once
+// per wavefront.  A wavefront loads the whole K extent of its rows with
+// 16-byte loads up front and reads the weights from LDS with 16-byte LDS
+// loads.  gridDim.x is a multiple of 8 so that the column blocks of one row
+// tile are dispatched to the same XCD (shared L2 for the activations).
+template <int MT, int NT, int KCH, class Epi>
+__global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
+  constexpr int K = KCH * 16;
+  constexpr int LDW = K + 4;
+  extern __shared__ float wsm[];  // [NT * 16][LDW]
+  const int M = a.Mptr ? *a.Mptr : a.Mmax;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int nt0 = blockIdx.y * NT;
+  const int ntt = a.Npad / 16;
+  const int r = lane & 15;
+  const int g = lane >> 4;
+  for (int idx = threadIdx.x; idx < NT * 16 * KCH * 4; idx += blockDim.x) {
+    const int row = idx / (KCH * 4), c4 = idx % (KCH * 4);
+    const int n = nt0 * 16 + row;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (n < a.Npad) v = *(const float4 *)(a.Wt + (size_t)n * a.K + 4 * c4);
+    *(float4 *)(wsm + row * LDW + 4 * c4) = v;
+  }
+  __syncthreads();
+  const float *wl = wsm + r * LDW + 4 * g;
+  for (int rt = blockIdx.x; rt * 64 * MT < M; rt += gridDim.x) {
+    const int row0 = (rt * 4 + wave) * 16 * MT;
+    if (row0 >= M) continue;
+    floatx4 xr[MT][KCH];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      const float *xp = a.X + (size_t)(row < M ? row : 0) * a.ldx + 4 * g;
+#pragma unroll
+      for (int c = 0; c < KCH; ++c) xr[mt][c] = *(const floatx4 *)(xp + 16 * c);
+    }
+    floatx4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) {
+      floatx4 w[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * LDW + 16 * c);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt][nt] = mfma4(w[nt][t], xr[mt][c][t], acc[mt][nt]);
+    }
+    epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
+  }
+}
+
 // ------------------------------------------------------------------ epilogues
 
 struct EpiLinear {
@@ -437,6 +499,20 @@ void dispatch_nt(const GemmArgs &a, const Epi &e, int nt, hipStream_t s) {
   }
 }
 
+template <class Epi, int NT, int KCH>
+void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
+  constexpr int MT = 2;
+  const int ntt = a.Npad / 16;
+  const unsigned gy = (unsigned)((ntt + NT - 1) / NT);
+  const int row_tiles = (a.Mmax + 64 * MT - 1) / (64 * MT);
+  int gx = (512 + (int)gy - 1) / (int)gy;  // about two workgroups per CU in total
+  gx = (gx + 7) / 8 * 8;
+  if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
+  if (gx <= 0) return;
+  const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4);
+  hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi>), dim3(gx, gy), dim3(256), lds, s, a, e);
+}
+
 // Rows per wave: two 16-row tiles for the large pair-batched products,
 // one for the centre-batched fitting net (more blocks for fewer rows).
 template <class Epi>
@@ -444,6 +520,12 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
   const int ntt = a.Npad / 16;
   int nt = ntt < 8 ? ntt : 8;
   if (full_rows && ntt > 8) nt = ntt;  // callers guarantee ntt <= 8 for row reductions
+  if (a.Mmax >= 65536 && (a.K == 112 || a.K == 128) && (nt == 7 || nt == 8)) {
+    if (nt == 7 && a.K == 112) return launch_lds<Epi, 7, 7>(a, e, s);
+    if (nt == 7 && a.K == 128) return launch_lds<Epi, 7, 8>(a, e, s);
+    if (nt == 8 && a.K == 112) return launch_lds<Epi, 8, 7>(a, e, s);
+    return launch_lds<Epi, 8, 8>(a, e, s);
+  }
   if (a.Mmax >= 65536) dispatch_nt<Epi, 2>(a, e, nt, s);
   else dispatch_nt<Epi, 1>(a, e, nt, s);
 }

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ x, Ce
                                                 const int *__restrict__ nnei,
                                                 const int *__restrict__ pair_off,
                                                 const float *__restrict__ g,
+                                                const double *__restrict__ wgt, double sign,
                                                 double *__restrict__ forces,
                                                 double *__restrict__ vir_part) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -121,11 +122,12 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ x, Ce
   for (int c = 0; c < 9; ++c) v[c] = 0.0;
   const bool local = k < nloc;
   const int base = local ? pair_off[k] : 0;
+  const double wk = (local && wgt) ? wgt[k] : 1.0;
   for (int s = lane; s < nk; s += kWave) {
     const int j = row[s];
     if (local) {
       const float4 gk = *(const float4 *)(g + 4 * (size_t)(base + s));
-      const double gx = gk.x, gy = gk.y, gz = gk.z;
+      const double gx = wk * gk.x, gy = wk * gk.y, gz = wk * gk.z;
       f0 += gx;
       f1 += gy;
       f2 += gz;
@@ -139,9 +141,10 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ x, Ce
       const int t = find_slot(nlist + (size_t)j * sel, nnei[j], k);
       if (t >= 0) {
         const float4 gj = *(const float4 *)(g + 4 * (size_t)(pair_off[j] + t));
-        f0 -= gj.x;
-        f1 -= gj.y;
-        f2 -= gj.z;
+        const double wj = wgt ? wgt[j] : 1.0;
+        f0 -= wj * gj.x;
+        f1 -= wj * gj.y;
+        f2 -= wj * gj.z;
       }
     }
   }
@@ -151,9 +154,9 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ x, Ce
   if (local)
     for (int c = 0; c < 9; ++c) v[c] = wave_sum(v[c]);
   if (lane == 0) {
-    forces[3 * (size_t)k + 0] = f0;
-    forces[3 * (size_t)k + 1] = f1;
-    forces[3 * (size_t)k + 2] = f2;
+    forces[3 * (size_t)k + 0] = sign * f0;
+    forces[3 * (size_t)k + 1] = sign * f1;
+    forces[3 * (size_t)k + 2] = sign * f2;
     if (local)
       for (int c = 0; c < 9; ++c) vir_part[9 * (size_t)k + c] = v[c];
   }
@@ -166,16 +169,20 @@ __global__ __launch_bounds__(1024) void k_reduce(const float *__restrict__ e,
                                                  double *__restrict__ energy,
                                                  double *__restrict__ virial,
                                                  double *__restrict__ atom_energy) {
+  // energy == nullptr skips the energy, virial == nullptr the virial
   __shared__ double red[10][16];
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
   double acc[10];
   for (int c = 0; c < 10; ++c) acc[c] = 0.0;
   for (int i = t; i < nloc; i += 1024) {
-    const double ei = (double)e[i];
-    acc[0] += ei;
-    if (atom_energy) atom_energy[i] = ei;
-    for (int c = 0; c < 9; ++c) acc[1 + c] += vir_part[9 * (size_t)i + c];
+    if (energy) {
+      const double ei = (double)e[i];
+      acc[0] += ei;
+      if (atom_energy) atom_energy[i] = ei;
+    }
+    if (virial)
+      for (int c = 0; c < 9; ++c) acc[1 + c] += vir_part[9 * (size_t)i + c];
   }
   for (int c = 0; c < 10; ++c) {
     const double v = wave_sum(acc[c]);
@@ -188,8 +195,9 @@ __global__ __launch_bounds__(1024) void k_reduce(const float *__restrict__ e,
       tot[c] = 0.0;
       for (int w = 0; w < 16; ++w) tot[c] += red[c][w];
     }
-    energy[0] = tot[0];
-    for (int c = 0; c < 9; ++c) virial[c] = tot[1 + c];
+    if (energy) energy[0] = tot[0];
+    if (virial)
+      for (int c = 0; c < 9; ++c) virial[c] = tot[1 + c];
   }
 }
 
@@ -212,10 +220,11 @@ void launch_env_bwd(const float *geom, const float *gs, const float *dRt, const 
 
 void launch_forces(const double *coords, CellGrid grid, int nloc, int nall, int sel,
                    const int *nlist, const int *nnei, const int *pair_off, const float *g,
-                   double *forces, double *vir_part, hipStream_t s) {
+                   const double *wgt, double sign, double *forces, double *vir_part,
+                   hipStream_t s) {
   if (nall <= 0) return;
   hipLaunchKernelGGL(k_forces, dim3((nall + 3) / 4), dim3(256), 0, s, coords, grid, nloc, nall,
-                     sel, nlist, nnei, pair_off, g, forces, vir_part);
+                     sel, nlist, nnei, pair_off, g, wgt, sign, forces, vir_part);
 }
 
 void launch_reduce(const float *e, const double *vir_part, int nloc, double *energy,
