@@ -75,14 +75,14 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld
 // per lane per four MFMA steps.
 template <int NPAD>
 __device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, int base, int n,
-                                        float *XT) {
+                                        float *XT, int tid) {
   constexpr int LDT = NPAD + 4;
   constexpr int THREADS = NPAD / 16 * 64;
   constexpr int ITER = NPAD * 32 / THREADS;  // = 8
   float4 v[ITER];
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
-    const int idx = threadIdx.x + it * THREADS;
+    const int idx = tid + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
     const int rr = row < n ? row : 0;
     v[it] = *(const float4 *)(src + (size_t)(base + rr) * ld + 4 * c4);
@@ -90,7 +90,7 @@ __device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, i
   }
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
-    const int idx = threadIdx.x + it * THREADS;
+    const int idx = tid + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
     float *d = XT + (4 * c4) * LDT + row;
     d[0] = v[it].x;
@@ -102,8 +102,8 @@ __device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, i
 
 template <int NPAD>
 __device__ __forceinline__ void stage_gate(const float *__restrict__ geom, int base, int n,
-                                           float4 *kg) {
-  for (int t = threadIdx.x; t < NPAD; t += blockDim.x) {
+                                           float4 *kg, int tid) {
+  for (int t = tid; t < NPAD; t += NPAD / 16 * 64) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (t < n) {
       const float *gp = geom + (size_t)(base + t) * kGeom;
@@ -119,14 +119,27 @@ template <int NPAD>
 __device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int g,
                                           const floatx4 &bt, floatx4 (&acc)[8]) {
   constexpr int LDT = NPAD + 4;
-  floatx4 x[8];
 #pragma unroll
-  for (int ft = 0; ft < 8; ++ft)
-    x[ft] = *(const floatx4 *)(XT + (ft * 16 + r) * LDT + tile * 16 + 4 * g);
+  for (int h = 0; h < 2; ++h) {  // two halves of the features: 16 operand registers
+    floatx4 x[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+    for (int f = 0; f < 4; ++f)
+      x[f] = *(const floatx4 *)(XT + ((4 * h + f) * 16 + r) * LDT + tile * 16 + 4 * g);
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) acc[ft] = mfma4(x[ft][t], bt[t], acc[ft]);
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+  }
+}
+
+// The thread index, opaque to the optimiser.  Taken afresh in every
+// iteration of the per-centre loops so that per-lane addresses are
+// recomputed there instead of being hoisted out of the loop and held in
+// registers for its whole duration (which made the large classes spill).
+__device__ __forceinline__ int fresh_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // Keeps the compiler from hoisting the loads of later iterations (which
@@ -173,120 +186,109 @@ __device__ __forceinline__ void qk_tiles(const float *__restrict__ krows, int ld
   }
 }
 
-// One 16x16 tile of rows x kreg^T: lane (row r of the 16-row tile at 'row0',
-// lane group g) supplies the A operand from global memory, breg the B operand.
-__device__ __forceinline__ floatx4 rows_times(const float *__restrict__ rows, int ld, int base,
-                                              int n, int row0, int r, int g,
-                                              const floatx4 (&breg)[8]) {
-  const int row = row0 + r;
-  const bool ok = row < n;
-  const float *p = rows + (size_t)(base + (ok ? row : 0)) * ld + 4 * g;
-  const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
-  floatx4 a0 = zero, a1 = zero;
-  floatx4 x0 = *(const floatx4 *)(p);
-  x0 = ok ? x0 : zero;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    floatx4 x1 = zero;
-    if (c + 1 < 8) {
-      x1 = *(const floatx4 *)(p + 16 * (c + 1));
-      x1 = ok ? x1 : zero;
-    }
-    SCHED_FENCE();
-    if (c & 1) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) a1 = mfma4(x0[t], breg[c][t], a1);
-    } else {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) a0 = mfma4(x0[t], breg[c][t], a0);
-    }
-    x0 = x1;
-  }
-  return a0 + a1;
-}
-
 // --------------------------------------------------------------------- forward
 //
-// One workgroup per centre whose neighbour count lies in (nlo, NPAD]; one
-// wavefront per 16-query tile.  V is staged transposed in LDS for A V.
+// Centres are processed by a persistent grid: block b takes the centres
+// b, b + gridDim.x, ... of its class list (every centre of a class costs the
+// same padded work, so the static split is balanced).  One wavefront per
+// 16-query tile.  V is staged transposed in LDS for A V.  The scaled dot
+// products lam = q.k/sqrt(d) (row stride kLamLd, all NPAD key columns of
+// every query row) and the softmax statistics (m, 1/Z) of every query are
+// stored for the adjoint, which then does not recompute Q K^T.
+
+constexpr int kLamLd = kAttnLamLd;
 
 template <int NPAD>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) void k_attn_fwd(
     const float *__restrict__ qkv, const float *__restrict__ geom,
-    const int *__restrict__ pair_off, const int *__restrict__ nnei, int sel, float shift,
-    float *__restrict__ out, int nlo) {
+    const int *__restrict__ pair_off, const int *__restrict__ nnei,
+    const int *__restrict__ clist, const int *__restrict__ ccount, int sel, float shift,
+    float *__restrict__ out, float *__restrict__ lam, float2 *__restrict__ fstat) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;
   float *VT = (float *)(smem + NPAD);
-  const int i = blockIdx.x;
-  const int n = nnei[i];
-  if (n <= nlo || n > NPAD) return;  // uniform over the block
-  const int base = pair_off[i];
-  const int ntile = (n + 15) >> 4;
   const int ld = kQKV * 128;
-  stage_gate<NPAD>(geom, base, n, kg);
-  stage_t<NPAD>(qkv + 256, ld, base, n, VT);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  if (wave >= ntile) return;
-  const int r = lane & 15, g = lane >> 4;
-  const int q = wave * 16 + r;
-  const bool qok = q < n;
   const float inv_sqrt_d = 0.08838834764831845f;  // 1/sqrt(128)
+  const int cnt = *ccount;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int tid = fresh_tid();
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int i = clist[it];
+    const int n = nnei[i];
+    const int base = pair_off[i];
+    const int ntile = (n + 15) >> 4;
+    stage_gate<NPAD>(geom, base, n, kg, tid);
+    stage_t<NPAD>(qkv + 256, ld, base, n, VT, tid);
+    __syncthreads();
+    if (wave < ntile) {
+      const int q = wave * 16 + r;
+      const bool qok = q < n;
+      floatx4 qv[8];
+      load_rows(qkv, ld, base, n, q, g, qv);
+      floatx4 st[NT];
+      qk_tiles<NT>(qkv + 128, ld, base, n, ntile, r, g, qv, st);
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) st[kt] *= inv_sqrt_d;
+      if (qok) {
+        float *lp = lam + (size_t)(base + q) * kLamLd + 4 * g;
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) *(floatx4 *)(lp + 16 * kt) = st[kt];
+      }
 
-  floatx4 qv[8];
-  load_rows(qkv, ld, base, n, q, g, qv);
-  floatx4 st[NT];
-  qk_tiles<NT>(qkv + 128, ld, base, n, ntile, r, g, qv, st);
+      const float4 gq = kg[q];
+      const float wq = qok ? gq.w : 0.f;
+      float mx = -FLT_MAX;
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = kt * 16 + 4 * g + v;
+          float l = (st[kt][v] + shift) * wq * kg[k].w - shift;
+          l = k < n ? l : -INFINITY;
+          st[kt][v] = l;
+          mx = fmaxf(mx, l);
+        }
+      }
+      const float m = fmaxf(max_groups(mx), -shift);
+      float z = 0.f;
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float e = expf(st[kt][v] - m);
+          st[kt][v] = e;
+          z += e;
+        }
+      }
+      z = sum_groups(z) + (float)(sel - n) * expf(-shift - m);
+      const float invz = 1.0f / z;
+      if (g == 0 && qok) fstat[base + q] = make_float2(m, invz);
 
-  const float4 gq = kg[q];
-  const float wq = qok ? gq.w : 0.f;
-  float mx = -FLT_MAX;
+      floatx4 oacc[8];
 #pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
+      for (int ft = 0; ft < 8; ++ft) oacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = kt * 16 + 4 * g + v;
-      float l = (st[kt][v] * inv_sqrt_d + shift) * wq * kg[k].w - shift;
-      l = k < n ? l : -INFINITY;
-      st[kt][v] = l;
-      mx = fmaxf(mx, l);
+      for (int kt = 0; kt < NT; ++kt) {
+        floatx4 at;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float4 gk = kg[kt * 16 + 4 * g + v];
+          const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
+          at[v] = st[kt][v] * invz * wq * gk.w * c;
+        }
+        accum_lds<NPAD>(VT, kt, r, g, at, oacc);
+      }
+      if (qok) {
+        float *op = out + (size_t)(base + q) * 128 + 4 * g;
+#pragma unroll
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(op + 16 * ft) = oacc[ft];
+      }
     }
+    __syncthreads();  // LDS is restaged for the next centre
   }
-  const float m = fmaxf(max_groups(mx), -shift);
-  float z = 0.f;
-#pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float e = expf(st[kt][v] - m);
-      st[kt][v] = e;
-      z += e;
-    }
-  }
-  z = sum_groups(z) + (float)(sel - n) * expf(-shift - m);
-  const float invz = 1.0f / z;
-
-  floatx4 oacc[8];
-#pragma unroll
-  for (int ft = 0; ft < 8; ++ft) oacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
-    floatx4 at;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float4 gk = kg[kt * 16 + 4 * g + v];
-      const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
-      at[v] = st[kt][v] * invz * wq * gk.w * c;
-    }
-    accum_lds<NPAD>(VT, kt, r, g, at, oacc);
-  }
-  if (!qok) return;
-  float *op = out + (size_t)(base + q) * 128 + 4 * g;
-#pragma unroll
-  for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(op + 16 * ft) = oacc[ft];
 }
 
 // -------------------------------------------------------------------- backward
@@ -297,133 +299,112 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
 //   dS = dL w_q w_k / sqrt(d) ; dQ = dS K ; dK = dS^T Q
 //   X = dL (lam + S) + dH c  -> dw_q += sum_k X w_k, dw_k += sum_q X w_q
 //   Y = dH w_q w_k           -> drhat_q += sum_k Y rhat_k, drhat_k += sum_q Y rhat_q
-// Phase A (wave = query tile): logits, softmax statistics, dA, dS, dQ and the
-// query-side sums (K^T in LDS).  Phase B1 (wave = key tile): logits and dA
-// recomputed in the key-major layout, dK and the key-side sums (Q^T in LDS);
-// the tile of A is kept in registers for phase B2: dV (dO^T in LDS).
-
-// Backward, in two kernels per class.  k_attn_bwd_q (wave = query tile):
-// logits, softmax statistics, dA, dS, dQ and the query-side sums (K^T in
-// LDS); it writes the statistics (m, 1/Z, D_q) and the query-side sums per
-// pair.  k_attn_bwd_k (wave = key tile): logits and dA recomputed key-major,
-// dK and the key-side sums (Q^T in LDS), then dV from the tile of A kept in
-// registers (dO^T in LDS); it adds both sides into dE/dsw and dE/drhat.
+// Two kernels per class, both reading lam and (m, 1/Z) stored by the forward.
+// k_attn_bwd_q (wave = query tile): dA, dS, dQ (K^T in LDS) and the
+// query-side sums; it writes (m, 1/Z, D_q) and the query-side sums per pair.
+// k_attn_bwd_k (wave = key tile): dA recomputed key-major, dK (Q^T in LDS)
+// and the key-side sums, then dV from the tile of A kept in registers (dO^T
+// in LDS); it adds both sides into dE/dsw and dE/drhat.
 
 template <int NPAD>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_q(
     const float *__restrict__ qkv, const float *__restrict__ o, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
-    const int *__restrict__ nnei, int sel, float shift, float *__restrict__ dqkv,
-    float4 *__restrict__ astat, float4 *__restrict__ qside, int nlo) {
+    const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
+    int sel, float shift, const float *__restrict__ lam, const float2 *__restrict__ fstat,
+    float *__restrict__ dqkv, float4 *__restrict__ astat, float4 *__restrict__ qside) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;                // [NPAD] rhat, sw
   float *XT = (float *)(kg + NPAD);  // [128][NPAD + 4]
-  const int i = blockIdx.x;
-  const int n = nnei[i];
-  if (n <= nlo || n > NPAD) return;  // uniform over the block
-  const int base = pair_off[i];
-  const int ntile = (n + 15) >> 4;
   const int ld = kQKV * 128;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, g = lane >> 4;
   const float inv_sqrt_d = 0.08838834764831845f;
+  const int cnt = *ccount;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int tid = fresh_tid();
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int i = clist[it];
+    const int n = nnei[i];
+    const int base = pair_off[i];
+    const int ntile = (n + 15) >> 4;
+    stage_gate<NPAD>(geom, base, n, kg, tid);
+    stage_t<NPAD>(qkv + 128, ld, base, n, XT, tid);  // K^T
+    __syncthreads();
 
-  stage_gate<NPAD>(geom, base, n, kg);
-  stage_t<NPAD>(qkv + 128, ld, base, n, XT);  // K^T
-  __syncthreads();
+    if (wave < ntile) {
+      const int q = wave * 16 + r;
+      const bool qok = q < n;
+      const int qr = qok ? q : 0;
+      const float4 gq = kg[q];
+      const float wq = qok ? gq.w : 0.f;
+      // lam of this query row, read one key tile ahead of its use
+      const float *lp = lam + (size_t)(base + qr) * kLamLd + 4 * g;
+      const float2 fs = fstat[base + qr];
+      const float m = fs.x, invz = fs.y;
 
-  // ---------------- phase A: wave = query tile
-  if (wave < ntile) {
-    const int q = wave * 16 + r;
-    const bool qok = q < n;
-    const float4 gq = kg[q];
-    const float wq = qok ? gq.w : 0.f;
-    floatx4 lam[NT];
-    {
-      floatx4 qv[8];
-      load_rows(qkv, ld, base, n, q, g, qv);
-      qk_tiles<NT>(qkv + 128, ld, base, n, ntile, r, g, qv, lam);
-    }
-    float mx = -FLT_MAX;
+      floatx4 da[NT];
+      float dq;
+      {
+        floatx4 dov[8], ov[8];
+        load_rows(dO, 128, base, n, q, g, dov);
+        load_rows(o, 128, base, n, q, g, ov);
+        dq = 0.f;
 #pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
-  #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = kt * 16 + 4 * g + v;
-        lam[kt][v] *= inv_sqrt_d;
-        const float l = k < n ? (lam[kt][v] + shift) * wq * kg[k].w - shift : -INFINITY;
-        mx = fmaxf(mx, l);
+        for (int c = 0; c < 8; ++c)
+          dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
+                dov[c][3] * ov[c][3];
+        dq = sum_groups(dq);
+        qk_tiles<NT>(qkv + 256, ld, base, n, ntile, r, g, dov, da);  // dA^T tiles
       }
-    }
-    const float m = fmaxf(max_groups(mx), -shift);
-    float z = 0.f;
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
-  #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = kt * 16 + 4 * g + v;
-        if (k < n) z += expf((lam[kt][v] + shift) * wq * kg[k].w - shift - m);
-      }
-    }
-    z = sum_groups(z) + (float)(sel - n) * expf(-shift - m);
-    const float invz = 1.0f / z;
+      if (g == 0 && qok) astat[base + q] = make_float4(m, invz, dq, 0.f);
 
-    floatx4 da[NT];
-    float dq;
-    {
-      floatx4 dov[8], ov[8];
-      load_rows(dO, 128, base, n, q, g, dov);
-      load_rows(o, 128, base, n, q, g, ov);
-      dq = 0.f;
+      floatx4 dqacc[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
-              dov[c][3] * ov[c][3];
-      dq = sum_groups(dq);
-      qk_tiles<NT>(qkv + 256, ld, base, n, ntile, r, g, dov, da);  // dA^T tiles
-    }
-    if (g == 0 && qok) astat[base + q] = make_float4(m, invz, dq, 0.f);
-
-    floatx4 dqacc[8];
+      for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
+      floatx4 lcur = *(const floatx4 *)lp, lnxt;
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
+      for (int kt = 0; kt < NT; ++kt) {
+        if (kt + 1 < NT) lnxt = *(const floatx4 *)(lp + 16 * (kt + 1));
         floatx4 ds;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = kt * 16 + 4 * g + v;
-        const float4 gk = kg[k];
-        const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
-        const float ww = wq * gk.w;
-        const float l = (lam[kt][v] + shift) * ww - shift;
-        const float p = (qok && k < n) ? expf(l - m) * invz : 0.f;
-        const float h = ww * c;
-        const float dH = da[kt][v] * p;
-        const float dL = p * (da[kt][v] * h - dq);
-        ds[v] = dL * ww * inv_sqrt_d;
-        const float X = dL * (lam[kt][v] + shift) + dH * c;
-        const float Y = dH * ww;
-        dwq += X * gk.w;
-        drqx += Y * gk.x;
-        drqy += Y * gk.y;
-        drqz += Y * gk.z;
+        for (int v = 0; v < 4; ++v) {
+          const int k = kt * 16 + 4 * g + v;
+          const bool ok = qok && k < n;
+          const float4 gk = kg[k];
+          const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
+          const float ww = wq * gk.w;
+          const float lm = ok ? lcur[v] : 0.f;
+          const float l = (lm + shift) * ww - shift;
+          const float p = ok ? expf(l - m) * invz : 0.f;
+          const float h = ww * c;
+          const float dH = da[kt][v] * p;
+          const float dL = p * (da[kt][v] * h - dq);
+          ds[v] = dL * ww * inv_sqrt_d;
+          const float X = dL * (lm + shift) + dH * c;
+          const float Y = dH * ww;
+          dwq += X * gk.w;
+          drqx += Y * gk.x;
+          drqy += Y * gk.y;
+          drqz += Y * gk.z;
+        }
+        accum_lds<NPAD>(XT, kt, r, g, ds, dqacc);
+        lcur = lnxt;
       }
-      accum_lds<NPAD>(XT, kt, r, g, ds, dqacc);
-    }
-    dwq = sum_groups(dwq);
-    drqx = sum_groups(drqx);
-    drqy = sum_groups(drqy);
-    drqz = sum_groups(drqz);
-    if (g == 0 && qok) qside[base + q] = make_float4(dwq, drqx, drqy, drqz);
-    if (qok) {
-      float *dp = dqkv + (size_t)(base + q) * ld + 4 * g;
+      dwq = sum_groups(dwq);
+      drqx = sum_groups(drqx);
+      drqy = sum_groups(drqy);
+      drqz = sum_groups(drqz);
+      if (g == 0 && qok) qside[base + q] = make_float4(dwq, drqx, drqy, drqz);
+      if (qok) {
+        float *dp = dqkv + (size_t)(base + q) * ld + 4 * g;
 #pragma unroll
-      for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dqacc[ft];
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dqacc[ft];
+      }
     }
+    __syncthreads();  // LDS is restaged for the next centre
   }
 }
 
@@ -431,128 +412,165 @@ template <int NPAD>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_k(
     const float *__restrict__ qkv, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
-    const int *__restrict__ nnei, float shift, float *__restrict__ dqkv,
+    const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
+    float shift, const float *__restrict__ lam, float *__restrict__ dqkv,
     const float4 *__restrict__ astat, const float4 *__restrict__ qsbuf,
-    float *__restrict__ gw, float *__restrict__ gr, int accumulate, int nlo) {
+    float *__restrict__ gw, float *__restrict__ gr, int accumulate) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;                 // [NPAD] rhat, sw
   float4 *stats = kg + NPAD;         // [NPAD] m, 1/Z, D_q of each query
   float *XT = (float *)(stats + NPAD);  // [128][NPAD + 4]
-  const int i = blockIdx.x;
-  const int n = nnei[i];
-  if (n <= nlo || n > NPAD) return;  // uniform over the block
-  const int base = pair_off[i];
-  const int ntile = (n + 15) >> 4;
   const int ld = kQKV * 128;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, g = lane >> 4;
   const float inv_sqrt_d = 0.08838834764831845f;
-  stage_gate<NPAD>(geom, base, n, kg);
-  for (int t = threadIdx.x; t < NPAD; t += blockDim.x)
-    stats[t] = t < n ? astat[base + t] : make_float4(0.f, 1.f, 0.f, 0.f);
-  stage_t<NPAD>(qkv, ld, base, n, XT);  // Q^T
-  __syncthreads();
+  const int cnt = *ccount;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int tid = fresh_tid();
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int i = clist[it];
+    const int n = nnei[i];
+    const int base = pair_off[i];
+    const int ntile = (n + 15) >> 4;
+    stage_gate<NPAD>(geom, base, n, kg, tid);
+    for (int t = tid; t < NPAD; t += NPAD / 16 * 64)
+      stats[t] = t < n ? astat[base + t] : make_float4(0.f, 1.f, 0.f, 0.f);
+    stage_t<NPAD>(qkv, ld, base, n, XT, tid);  // Q^T
+    __syncthreads();
 
-  // ---------------- phase B1: wave = key tile
-  const int kk = wave * 16 + r;
-  const bool kok = kk < n;
-  floatx4 at[NT];
-  float dwk = 0.f, drkx = 0.f, drky = 0.f, drkz = 0.f;
-  if (wave < ntile) {
-    const float4 gk = kg[kk];
-    const float wk = kok ? gk.w : 0.f;
-    // logits and dA for this key tile against every query tile, key-major:
-    // lane holds key r and queries 4g + v of each query tile
-    floatx4 sk[NT], dk[NT];
-    {
-      floatx4 kreg[8];
-      load_rows(qkv + 128, ld, base, n, kk, g, kreg);
-      qk_tiles<NT>(qkv, ld, base, n, ntile, r, g, kreg, sk);
-    }
-    {
-      floatx4 vreg[8];
-      load_rows(qkv + 256, ld, base, n, kk, g, vreg);
-      qk_tiles<NT>(dO, 128, base, n, ntile, r, g, vreg, dk);
-    }
-    floatx4 dkacc[8];
+    // ---------------- phase 1: wave = key tile; dK and the key-side sums
+    const int kk = wave * 16 + r;
+    const bool kok = kk < n;
+    floatx4 at[NT];
+    float dwk = 0.f, drkx = 0.f, drky = 0.f, drkz = 0.f;
+    if (wave < ntile) {
+      const float4 gk = kg[kk];
+      const float wk = kok ? gk.w : 0.f;
+      // lam of this key against the queries of one tile (lane: key r,
+      // queries 4g + v), read one query tile ahead
+      const float *lc = lam + (size_t)base * kLamLd + kk;
+      auto lam_tile = [&](int qt, float (&lv)[4]) {
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int qt = 0; qt < NT; ++qt) {
-      at[qt] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if (qt >= ntile) continue;
-      floatx4 ds;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int qq = qt * 16 + 4 * g + v;
-        const float4 sq = stats[qq];
-        const float4 gq = kg[qq];
-        const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
-        const float ww = gq.w * wk;
-        const float lm = sk[qt][v] * inv_sqrt_d;
-        const float l = (lm + shift) * ww - shift;
-        const float p = (kok && qq < n) ? expf(l - sq.x) * sq.y : 0.f;
-        const float h = ww * c;
-        const float dav = dk[qt][v];
-        const float dH = dav * p;
-        const float dL = p * (dav * h - sq.z);
-        at[qt][v] = p * h;
-        ds[v] = dL * ww * inv_sqrt_d;
-        const float X = dL * (lm + shift) + dH * c;
-        const float Y = dH * ww;
-        dwk += X * gq.w;
-        drkx += Y * gq.x;
-        drky += Y * gq.y;
-        drkz += Y * gq.z;
+        for (int v = 0; v < 4; ++v) {
+          const int qq = qt * 16 + 4 * g + v;
+          lv[v] = lc[(qq < n ? qq : 0) * kLamLd];
+        }
+      };
+      float lcur[4], lnxt[4];
+      lam_tile(0, lcur);
+      // dA key-major: lane holds key r and queries 4g + v of each query tile
+      floatx4 dk[NT];
+      {
+        floatx4 vreg[8];
+        load_rows(qkv + 256, ld, base, n, kk, g, vreg);
+        qk_tiles<NT>(dO, 128, base, n, ntile, r, g, vreg, dk);
       }
-      accum_lds<NPAD>(XT, qt, r, g, ds, dkacc);
-    }
-    if (kok) {
-      float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+      floatx4 dkacc[8];
 #pragma unroll
-      for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+      for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int qt = 0; qt < NT; ++qt) {
+        at[qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (qt >= ntile) continue;
+        if (qt + 1 < NT) lam_tile(qt + 1, lnxt);
+        floatx4 ds;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int qq = qt * 16 + 4 * g + v;
+          const bool ok = kok && qq < n;
+          const float4 sq = stats[qq];
+          const float4 gq = kg[qq];
+          const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
+          const float ww = gq.w * wk;
+          const float lm = ok ? lcur[v] : 0.f;
+          const float l = (lm + shift) * ww - shift;
+          const float p = ok ? expf(l - sq.x) * sq.y : 0.f;
+          const float h = ww * c;
+          const float dav = dk[qt][v];
+          const float dH = dav * p;
+          const float dL = p * (dav * h - sq.z);
+          at[qt][v] = p * h;
+          ds[v] = dL * ww * inv_sqrt_d;
+          const float X = dL * (lm + shift) + dH * c;
+          const float Y = dH * ww;
+          dwk += X * gq.w;
+          drkx += Y * gq.x;
+          drky += Y * gq.y;
+          drkz += Y * gq.z;
+        }
+        accum_lds<NPAD>(XT, qt, r, g, ds, dkacc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lcur[v] = lnxt[v];
+      }
+      if (kok) {
+        float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+#pragma unroll
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+      }
+      dwk = sum_groups(dwk);
+      drkx = sum_groups(drkx);
+      drky = sum_groups(drky);
+      drkz = sum_groups(drkz);
     }
-    dwk = sum_groups(dwk);
-    drkx = sum_groups(drkx);
-    drky = sum_groups(drky);
-    drkz = sum_groups(drkz);
-  }
-  __syncthreads();
-  stage_t<NPAD>(dO, 128, base, n, XT);  // dO^T
-  __syncthreads();
+    __syncthreads();
+    stage_t<NPAD>(dO, 128, base, n, XT, tid);  // dO^T
+    __syncthreads();
 
-  // ---------------- phase B2: dV = A^T dO
-  if (wave < ntile) {
-    floatx4 dvacc[8];
+    // ---------------- phase 2: dV = A^T dO
+    if (wave < ntile) {
+      floatx4 dvacc[8];
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int qt = 0; qt < NT; ++qt)
-      if (qt < ntile) accum_lds<NPAD>(XT, qt, r, g, at[qt], dvacc);
-    if (kok) {
-      float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
+      for (int qt = 0; qt < NT; ++qt)
+        if (qt < ntile) accum_lds<NPAD>(XT, qt, r, g, at[qt], dvacc);
+      if (kok) {
+        float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
 #pragma unroll
-      for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
-      if (g == 0) {
-        const float4 qs = qsbuf[base + kk];
-        const size_t p = (size_t)(base + kk);
-        const float tw = qs.x + dwk, tx = qs.y + drkx, ty = qs.z + drky, tz = qs.w + drkz;
-        if (accumulate) {
-          gw[p] += tw;
-          gr[4 * p + 0] += tx;
-          gr[4 * p + 1] += ty;
-          gr[4 * p + 2] += tz;
-        } else {
-          gw[p] = tw;
-          gr[4 * p + 0] = tx;
-          gr[4 * p + 1] = ty;
-          gr[4 * p + 2] = tz;
-          gr[4 * p + 3] = 0.f;
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
+        if (g == 0) {
+          const float4 qs = qsbuf[base + kk];
+          const size_t p = (size_t)(base + kk);
+          const float tw = qs.x + dwk, tx = qs.y + drkx, ty = qs.z + drky, tz = qs.w + drkz;
+          if (accumulate) {
+            gw[p] += tw;
+            gr[4 * p + 0] += tx;
+            gr[4 * p + 1] += ty;
+            gr[4 * p + 2] += tz;
+          } else {
+            gw[p] = tw;
+            gr[4 * p + 0] = tx;
+            gr[4 * p + 1] = ty;
+            gr[4 * p + 2] = tz;
+            gr[4 * p + 3] = 0.f;
+          }
         }
       }
     }
+    __syncthreads();  // LDS is restaged for the next centre
+  }
+}
+
+// Class lists: centre i with n = nnei[i] > 0 goes to class (n - 1) / 32.
+// Positions are taken with one atomic per wavefront and class, so the order
+// inside a list varies from run to run; every centre is computed on its own,
+// so results do not depend on it.
+__global__ void k_attn_classes(const int *__restrict__ nnei, int nloc, int *__restrict__ ccount,
+                               int *__restrict__ clist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int n = i < nloc ? nnei[i] : 0;
+  const int cls = n > 0 ? (n - 1) >> 5 : -1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const unsigned long long b = __ballot(cls == c);
+    if (b == 0ull) continue;
+    const int leader = __ffsll((long long)b) - 1;
+    int pos0 = 0;
+    if (lane == leader) pos0 = atomicAdd(&ccount[c], __popcll(b));
+    pos0 = __shfl(pos0, leader);
+    if (cls == c) clist[(size_t)c * nloc + pos0 + __popcll(b & ((1ull << lane) - 1ull))] = i;
   }
 }
 
@@ -740,8 +758,9 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
 }
 
 // Centres are grouped by neighbour count into classes of 32, 64, 96 and 128
-// slots; each class runs a kernel sized for it (blocks of the other classes
-// exit at once), so the common case does not pay for the largest LDS size.
+// slots; each class runs a kernel sized for it, over its own centre list, so
+// the common case does not pay for the largest LDS size and an empty class
+// costs one wave of exiting blocks.
 template <int NPAD>
 size_t fwd_lds() {
   return sizeof(float4) * NPAD + sizeof(float) * 128 * (NPAD + 4);
@@ -755,26 +774,47 @@ size_t bwdk_lds() {
   return sizeof(float4) * 2 * NPAD + sizeof(float) * 128 * (NPAD + 4);
 }
 
-template <int NPAD>
-void fwd_one(const float *qkv, const float *geom, const int *pair_off, const int *nnei, int nloc,
-             int sel, float shift, float *out, int nlo, hipStream_t s) {
-  hipLaunchKernelGGL(k_attn_fwd<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), fwd_lds<NPAD>(), s, qkv,
-                     geom, pair_off, nnei, sel, shift, out, nlo);
+// Persistent grid sizes: resident blocks per CU times CUs, per device.
+constexpr int kMaxDevices = 64;
+int g_grid[kMaxDevices][3][4];
+
+int grid_for(int kind, int cls) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  const int gsz = g_grid[dev][kind][cls];
+  return gsz > 0 ? gsz : 1024;
 }
-template <int NPAD>
-void bwdq_one(const float *qkv, const float *o, const float *dO, const float *geom,
-              const int *pair_off, const int *nnei, int nloc, int sel, float shift, float *dqkv,
-              float4 *astat, float4 *qside, int nlo, hipStream_t s) {
-  hipLaunchKernelGGL(k_attn_bwd_q<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), bwdq_lds<NPAD>(), s,
-                     qkv, o, dO, geom, pair_off, nnei, sel, shift, dqkv, astat, qside, nlo);
+
+template <class K>
+hipError_t occupancy_grid(K kernel, int threads, size_t lds, int cus, int *out) {
+  int nb = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds);
+  if (e != hipSuccess) return e;
+  *out = (nb > 0 ? nb : 1) * cus;
+  return hipSuccess;
 }
+
 template <int NPAD>
-void bwdk_one(const float *qkv, const float *dO, const float *geom, const int *pair_off,
-              const int *nnei, int nloc, float shift, float *dqkv, const float4 *astat,
-              const float4 *qside, float *gw, float *gr, int accumulate, int nlo, hipStream_t s) {
-  hipLaunchKernelGGL(k_attn_bwd_k<NPAD>, dim3(nloc), dim3(NPAD / 16 * 64), bwdk_lds<NPAD>(), s,
-                     qkv, dO, geom, pair_off, nnei, shift, dqkv, astat, qside, gw, gr, accumulate,
-                     nlo);
+hipError_t prepare_class(int dev, int cus, int cls) {
+  const int th = NPAD / 16 * 64;
+  hipError_t e = hipSuccess;
+  if (NPAD > 64) {
+    e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<NPAD>());
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_attn_bwd_q<NPAD>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdq_lds<NPAD>());
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_attn_bwd_k<NPAD>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdk_lds<NPAD>());
+  }
+  if (e == hipSuccess)
+    e = occupancy_grid(k_attn_fwd<NPAD>, th, fwd_lds<NPAD>(), cus, &g_grid[dev][0][cls]);
+  if (e == hipSuccess)
+    e = occupancy_grid(k_attn_bwd_q<NPAD>, th, bwdq_lds<NPAD>(), cus, &g_grid[dev][1][cls]);
+  if (e == hipSuccess)
+    e = occupancy_grid(k_attn_bwd_k<NPAD>, th, bwdk_lds<NPAD>(), cus, &g_grid[dev][2][cls]);
+  return e;
 }
 
 }  // namespace
@@ -782,57 +822,69 @@ void bwdk_one(const float *qkv, const float *dO, const float *geom, const int *p
 int attn_class_count(int sel) { return sel <= 32 ? 1 : sel <= 64 ? 2 : sel <= 96 ? 3 : 4; }
 int attn_class_npad(int cls) { return 32 * (cls + 1); }
 
-void launch_attn_fwd_class(int cls, const float *qkv, const float *geom, const int *pair_off,
-                           const int *nnei, int nloc, int sel, float shift, float *out,
-                           hipStream_t s) {
-  if (nloc <= 0) return;
-  switch (cls) {
-    case 0: fwd_one<32>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 0, s); break;
-    case 1: fwd_one<64>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 32, s); break;
-    case 2: fwd_one<96>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 64, s); break;
-    default: fwd_one<128>(qkv, geom, pair_off, nnei, nloc, sel, shift, out, 96, s); break;
-  }
-}
-
-void launch_attn_bwd_q_class(int cls, const float *qkv, const float *o, const float *dO,
-                             const float *geom, const int *pair_off, const int *nnei, int nloc,
-                             int sel, float shift, float *dqkv, float *astat, float *qside,
-                             hipStream_t s) {
-  if (nloc <= 0) return;
-  float4 *a4 = (float4 *)astat, *q4 = (float4 *)qside;
-  switch (cls) {
-    case 0: bwdq_one<32>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 0, s); break;
-    case 1: bwdq_one<64>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 32, s); break;
-    case 2: bwdq_one<96>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 64, s); break;
-    default: bwdq_one<128>(qkv, o, dO, geom, pair_off, nnei, nloc, sel, shift, dqkv, a4, q4, 96, s); break;
-  }
-}
-
-void launch_attn_bwd_k_class(int cls, const float *qkv, const float *dO, const float *geom,
-                             const int *pair_off, const int *nnei, int nloc, float shift,
-                             float *dqkv, const float *astat, const float *qside, float *gw,
-                             float *gr, int accumulate, hipStream_t s) {
-  if (nloc <= 0) return;
-  const float4 *a4 = (const float4 *)astat, *q4 = (const float4 *)qside;
-  switch (cls) {
-    case 0: bwdk_one<32>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 0, s); break;
-    case 1: bwdk_one<64>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 32, s); break;
-    case 2: bwdk_one<96>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 64, s); break;
-    default: bwdk_one<128>(qkv, dO, geom, pair_off, nnei, nloc, shift, dqkv, a4, q4, gw, gr, accumulate, 96, s); break;
-  }
-}
-
-hipError_t set_attn_bwd_lds_limit() {
-  hipError_t e = hipFuncSetAttribute((const void *)k_attn_bwd_q<128>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)bwdq_lds<128>());
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_attn_bwd_k<128>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdk_lds<128>());
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_attn_fwd<128>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<128>());
+hipError_t attn_prepare() {
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (e == hipSuccess) e = prepare_class<32>(dev, cus, 0);
+  if (e == hipSuccess) e = prepare_class<64>(dev, cus, 1);
+  if (e == hipSuccess) e = prepare_class<96>(dev, cus, 2);
+  if (e == hipSuccess) e = prepare_class<128>(dev, cus, 3);
   return e;
+}
+
+void launch_attn_classes(const int *nnei, int nloc, int *ccount, int *clist, hipStream_t s) {
+  if (nloc <= 0) return;
+  hipLaunchKernelGGL(k_attn_classes, dim3((nloc + 255) / 256), dim3(256), 0, s, nnei, nloc,
+                     ccount, clist);
+}
+
+#define ATTN_CLASS_SWITCH(cls, CALL) \
+  switch (cls) {                     \
+    case 0: { constexpr int NP = 32; CALL; } break;  \
+    case 1: { constexpr int NP = 64; CALL; } break;  \
+    case 2: { constexpr int NP = 96; CALL; } break;  \
+    default: { constexpr int NP = 128; CALL; } break; \
+  }
+
+void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *out, float *lam,
+                           float *fstat, hipStream_t s) {
+  if (a.nloc <= 0) return;
+  const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
+  const dim3 grid(grid_for(0, cls));
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL(k_attn_fwd<NP>, grid, dim3(NP / 16 * 64),
+                                            fwd_lds<NP>(), s, qkv, a.geom, a.pair_off, a.nnei,
+                                            cl, cc, a.sel, a.shift, out, lam, (float2 *)fstat));
+}
+
+void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
+                             const float *dO, const float *lam, const float *fstat, float *dqkv,
+                             float *astat, float *qside, hipStream_t s) {
+  if (a.nloc <= 0) return;
+  const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
+  const dim3 grid(grid_for(1, cls));
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL(k_attn_bwd_q<NP>, grid, dim3(NP / 16 * 64),
+                                            bwdq_lds<NP>(), s, qkv, o, dO, a.geom, a.pair_off,
+                                            a.nnei, cl, cc, a.sel, a.shift, lam,
+                                            (const float2 *)fstat, dqkv, (float4 *)astat,
+                                            (float4 *)qside));
+}
+
+void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
+                             const float *lam, float *dqkv, const float *astat,
+                             const float *qside, float *gw, float *gr, int accumulate,
+                             hipStream_t s) {
+  if (a.nloc <= 0) return;
+  const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
+  const dim3 grid(grid_for(2, cls));
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL(k_attn_bwd_k<NP>, grid, dim3(NP / 16 * 64),
+                                            bwdk_lds<NP>(), s, qkv, dO, a.geom, a.pair_off,
+                                            a.nnei, cl, cc, a.shift, lam, dqkv,
+                                            (const float4 *)astat, (const float4 *)qside, gw, gr,
+                                            accumulate));
 }
 
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,

@@ -140,6 +140,8 @@ struct dp_model {
     float *geom;
     std::vector<float *> h, te;        // embedding outputs / tanh parts
     std::vector<float *> qkv, o, xhat, rstd, G;  // per attention layer (G[a] input of layer a)
+    std::vector<float *> lam, fstat;   // per attention layer: scaled logits, (m, 1/Z)
+    int *ccount, *clist;               // attention class counts [4] and lists [4][nloc]
     float *T, *dmat, *e;
     std::vector<float *> z, tf;        // fitting outputs / tanh parts
     std::vector<float *> fa, fdz;      // fitting backward a_l and dz_l
@@ -452,6 +454,8 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
   w.nlist = c.take<int>((size_t)nall * m->sel);
   w.nnei = c.take<int>(nall);
   w.pair_off = c.take<int>(nloc + 1);
+  w.ccount = c.take<int>(4);
+  w.clist = c.take<int>(4 * (size_t)nloc);
   w.geom = c.take<float>(P * kGeom);
   const int ne = (int)m->emb.size();
   w.h.assign(ne, nullptr);
@@ -463,6 +467,8 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
   const int na = m->n_attn;
   w.qkv.assign(na, nullptr);
   w.o.assign(na, nullptr);
+  w.lam.assign(na, nullptr);
+  w.fstat.assign(na, nullptr);
   w.xhat.assign(na, nullptr);
   w.rstd.assign(na, nullptr);
   w.G.assign(na + 1, nullptr);
@@ -470,6 +476,8 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
   for (int a = 0; a < na; ++a) {
     w.qkv[a] = c.take<float>(P * 3 * m->dattn);
     w.o[a] = c.take<float>(P * m->dattn);
+    w.lam[a] = c.take<float>(P * kAttnLamLd);
+    w.fstat[a] = c.take<float>(P * 2);
     w.xhat[a] = c.take<float>(P * m->ldM);
     w.rstd[a] = c.take<float>(P);
     w.G[a + 1] = c.take<float>(P * m->ldM);
@@ -574,13 +582,14 @@ __global__ void k_fill_int(int *p, int n, int v) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
 }
-__global__ void k_init_flags(DevFlags *f) {
+__global__ void k_init_flags(DevFlags *f, int *ccount) {
   if (threadIdx.x == 0) {
     f->overflow_atom = INT_MAX;
     f->overflow_count = 0;
     f->bad_type_atom = INT_MAX;
     f->pad_ = 0;
   }
+  if (threadIdx.x < 4) ccount[threadIdx.x] = 0;
 }
 __global__ void k_bbox(const double *x, int n, double *out) {
   __shared__ double red[6][256];
@@ -643,7 +652,7 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
 
-  RUN("init", hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, m->flags));
+  RUN("init", hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, m->flags, w.ccount));
   RUN("check_types", launch_check_types(d_types, nall, m->ntypes, m->flags, w.types_safe, s));
   d_types = w.types_safe;
   RUN("cell_clear", {
@@ -658,6 +667,7 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   RUN("nlist", launch_nlist(d_coords, nloc, nall, grid, m->rcut, sel, w.atom_cell, w.cell_start,
                             w.cell_atoms, w.nlist, w.nnei, m->flags, s));
   RUN("pair_scan", launch_scan(w.nnei, nloc, w.pair_off, s));
+  if (na > 0) RUN("attn_classes", launch_attn_classes(w.nnei, nloc, w.ccount, w.clist, s));
   RUN("env_embed1",
       launch_env_embed1(d_coords, d_types, grid, nloc, sel, m->rcut, m->rcut_smth, w.nlist,
                         w.nnei, w.pair_off, m->type_table, m->ws, m->ntypes, m->emb[0],
@@ -680,13 +690,14 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   }
   // attention layers
   const int D = m->dattn, ldM = m->ldM;
+  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift};
   for (int a = 0; a < na; ++a) {
     const auto &A = m->attn[a];
     GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax};
     RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
-      RUN(kAttnFwdName[cls], launch_attn_fwd_class(cls, w.qkv[a], w.geom, w.pair_off, w.nnei,
-                                                   nloc, sel, (float)m->shift, w.o[a], s));
+      RUN(kAttnFwdName[cls],
+          launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
     GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax};
     RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
                                     w.G[a + 1], w.xhat[a], w.rstd[a], s));
@@ -733,6 +744,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
   const int D = m->dattn, ldM = m->ldM;
+  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift};
   const bool emb_fused = ne == 3 && emb_fused_supported(m->lde[0], m->lde[1], m->lde[2]);
   EmbLaunch el{};
   if (emb_fused)
@@ -789,13 +801,12 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnBwdQName[cls],
-          launch_attn_bwd_q_class(cls, w.qkv[a], w.o[a], w.dO, w.geom, w.pair_off, w.nnei, nloc,
-                                  sel, (float)m->shift, w.dqkv, w.astat, w.qside, s));
+          launch_attn_bwd_q_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a], w.dqkv,
+                                  w.astat, w.qside, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnBwdKName[cls],
-          launch_attn_bwd_k_class(cls, w.qkv[a], w.dO, w.geom, w.pair_off, w.nnei, nloc,
-                                  (float)m->shift, w.dqkv, w.astat, w.qside, w.gw, w.gr,
-                                  a != na - 1, s));
+          launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dqkv, w.astat, w.qside,
+                                  w.gw, w.gr, a != na - 1, s));
     GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax};
     const int mode = a > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = a > 0 ? m->attn[a - 1].gamma : nullptr;
@@ -908,7 +919,7 @@ int dp_create(const char *weights_path, double rcut, int sel, dp_model **out) {
     if (e == hipSuccess) e = hipMalloc(&m->bbox, 6 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc(&m->flags_host, sizeof(DevFlags));
     if (e == hipSuccess) e = hipStreamCreate(&m->own);
-    if (e == hipSuccess) e = set_attn_bwd_lds_limit();
+    if (e == hipSuccess) e = attn_prepare();
     if (e != hipSuccess) rc = fail(DP_ERR_DEVICE, "device setup failed: %s", hipGetErrorString(e));
   }
   if (rc != DP_OK) {

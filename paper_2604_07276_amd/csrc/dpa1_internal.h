@@ -127,26 +127,38 @@ void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t
 // ---------------------------------------------------------------------------
 // Gated neighbour self-attention core.  Centres are split by neighbour
 // count into classes of 32/64/96/128 slots (class c covers n in
-// (32c, 32(c+1)]); every launch below covers one class.
+// (32c, 32(c+1)]); every launch below covers one class, over the class's
+// centre list, with a persistent grid sized at attn_prepare().
 int attn_class_count(int sel);
 int attn_class_npad(int cls);
-// Forward: O = (P o H) V per centre.
-void launch_attn_fwd_class(int cls, const float *qkv, const float *geom, const int *pair_off,
-                           const int *nnei, int nloc, int sel, float shift, float *out,
-                           hipStream_t s);
-// Backward, query tiles: dQ, softmax statistics and query-side gate/switch
+// Row stride of the stored scaled logits (floats per pair).
+constexpr int kAttnLamLd = 128;
+// Per device, once: LDS limits of the large classes and persistent grid sizes.
+hipError_t attn_prepare();
+// Class lists from the neighbour counts: ccount [4] (zeroed beforehand),
+// clist [4][nloc].
+void launch_attn_classes(const int *nnei, int nloc, int *ccount, int *clist, hipStream_t s);
+struct AttnArgs {
+  const float *geom;
+  const int *pair_off, *nnei, *clist, *ccount;
+  int nloc, sel;
+  float shift;
+};
+// Forward: O = (P o H) V per centre; stores lam = QK^T/sqrt(d) per pair row
+// ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).
+void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *out, float *lam,
+                           float *fstat, hipStream_t s);
+// Backward, query tiles: dQ, (m, 1/Z, D_q) and the query-side gate/switch
 // gradients (astat, qside: per-pair float4 buffers read by the key-tile pass).
-void launch_attn_bwd_q_class(int cls, const float *qkv, const float *o, const float *dO,
-                             const float *geom, const int *pair_off, const int *nnei, int nloc,
-                             int sel, float shift, float *dqkv, float *astat, float *qside,
-                             hipStream_t s);
+void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
+                             const float *dO, const float *lam, const float *fstat, float *dqkv,
+                             float *astat, float *qside, hipStream_t s);
 // Backward, key tiles: dK, dV and the total dE/dsw, dE/drhat per pair
 // (accumulated onto gw/gr when accumulate != 0).
-void launch_attn_bwd_k_class(int cls, const float *qkv, const float *dO, const float *geom,
-                             const int *pair_off, const int *nnei, int nloc, float shift,
-                             float *dqkv, const float *astat, const float *qside, float *gw,
-                             float *gr, int accumulate, hipStream_t s);
-hipError_t set_attn_bwd_lds_limit();
+void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
+                             const float *lam, float *dqkv, const float *astat,
+                             const float *qside, float *gw, float *gr, int accumulate,
+                             hipStream_t s);
 // Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,
                      const int *nnei, int nloc, int sel, int M, int axis, float *T, float *dmat,
