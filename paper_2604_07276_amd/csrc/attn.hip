@@ -69,14 +69,18 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld
   }
 }
 
+// Row stride of the row-major LDS tiles: 128 features + 4 (with it, eight
+// consecutive lanes reading 16 bytes each from eight consecutive rows touch
+// 32 distinct banks).
+constexpr int kLDR = 132;
+
 // Stage rows [base, base + n) x 128 features of src (row stride ld) into LDS
-// transposed, XT[f][k] with row stride NPAD + 4; rows n..NPAD-1 are zero.
-// Products that contract over neighbours read it with one 16-byte LDS load
+// row-major, X[row][kLDR]; rows n..NPAD-1 are zero.  Products whose A operand
+// runs along the features (Q K^T, dO V^T) read it with one 16-byte LDS load
 // per lane per four MFMA steps.
 template <int NPAD>
-__device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, int base, int n,
-                                        float *XT, int tid) {
-  constexpr int LDT = NPAD + 4;
+__device__ __forceinline__ void stage_rows(const float *__restrict__ src, int ld, int base, int n,
+                                           float *X, int tid) {
   constexpr int THREADS = NPAD / 16 * 64;
   constexpr int ITER = NPAD * 32 / THREADS;  // = 8
   float4 v[ITER];
@@ -92,12 +96,52 @@ __device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, i
   for (int it = 0; it < ITER; ++it) {
     const int idx = tid + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
-    float *d = XT + (4 * c4) * LDT + row;
+    *(float4 *)(X + row * kLDR + 4 * c4) = v[it];
+  }
+}
+
+// Stage rows [base, base + n) x 128 features of src into LDS transposed,
+// XT[f][k] with row stride NPAD + 4; rows n..NPAD-1 are zero.  Products that
+// contract over neighbours read it with one 16-byte LDS load per lane per
+// four MFMA steps.  Wave w stages rows 16w..16w+15; in each step lane l takes
+// row 16w + l%16 and feature quad 4 it + l/16, so the four scalar LDS writes
+// of one float4 hit 64 distinct banks.
+// The load half and the LDS half are separate so that a kernel can issue the
+// loads one phase early (while the previous phase computes) and write LDS
+// after the barrier that frees the buffer.
+template <int NPAD>
+__device__ __forceinline__ void stage_t_load(const float *__restrict__ src, int ld, int base,
+                                             int n, int tid, float4 (&v)[8]) {
+  const int row = (tid >> 6) * 16 + (tid & 15);
+  const int cq = (tid >> 4) & 3;
+  const int rr = row < n ? row : 0;
+  const float *sp = src + (size_t)(base + rr) * ld + 4 * cq;
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    v[it] = *(const float4 *)(sp + 16 * it);
+    if (row >= n) v[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+template <int NPAD>
+__device__ __forceinline__ void stage_t_store(float *XT, int tid, const float4 (&v)[8]) {
+  constexpr int LDT = NPAD + 4;
+  const int row = (tid >> 6) * 16 + (tid & 15);
+  const int cq = (tid >> 4) & 3;
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    float *d = XT + (16 * it + 4 * cq) * LDT + row;
     d[0] = v[it].x;
     d[LDT] = v[it].y;
     d[2 * LDT] = v[it].z;
     d[3 * LDT] = v[it].w;
   }
+}
+template <int NPAD>
+__device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, int base, int n,
+                                        float *XT, int tid) {
+  float4 v[8];
+  stage_t_load<NPAD>(src, ld, base, n, tid, v);
+  stage_t_store<NPAD>(XT, tid, v);
 }
 
 template <int NPAD>
@@ -115,6 +159,7 @@ __device__ __forceinline__ void stage_gate(const float *__restrict__ geom, int b
 
 // acc[ft] += XT^T-tile x bt : contraction over the 16 rows of tile 'tile',
 // XT in LDS (feature-major), bt a 16x16 B operand held in registers.
+// Output lane layout: own row r, features 16 ft + 4 g + v.
 template <int NPAD>
 __device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int g,
                                           const floatx4 &bt, floatx4 (&acc)[8]) {
@@ -132,6 +177,49 @@ __device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int 
   }
 }
 
+// The same contraction with the rows in row-major LDS (X[row][kLDR]): the A
+// operand is read with scalar LDS loads, four rows per lane group.
+__device__ __forceinline__ void accum_rows(const float *X, int tile, int r, int g,
+                                           const floatx4 &bt, floatx4 (&acc)[8]) {
+  const float *xb = X + (tile * 16 + 4 * g) * kLDR + r;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float x[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) x[f][t] = xb[t * kLDR + (4 * h + f) * 16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+  }
+}
+
+// st[kt] (lane: own row r, tile rows 4g + v) = X-rows of tile kt times the
+// wave's own 16 rows b, contracted over the 128 features; X row-major in LDS.
+template <int NT>
+__device__ __forceinline__ void qk_lds(const float *X, int r, int g, const floatx4 (&b)[8],
+                                       floatx4 (&st)[NT]) {
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) st[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float *xb = X + r * kLDR + 4 * g;
+  // one feature chunk at a time (LDS latency is covered by the other
+  // wavefronts on the SIMD); the fence keeps the compiler from hoisting the
+  // loads of later chunks, which would hold many more registers
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    floatx4 a[NT];
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) a[kt] = *(const floatx4 *)(xb + kt * 16 * kLDR + 16 * c);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma4(a[kt][t], b[c][t], st[kt]);
+  }
+}
+
 // The thread index, opaque to the optimiser.  Taken afresh in every
 // iteration of the per-centre loops so that per-lane addresses are
 // recomputed there instead of being hoisted out of the loop and held in
@@ -142,48 +230,10 @@ __device__ __forceinline__ int fresh_tid() {
   return t;
 }
 
-// Keeps the compiler from hoisting the loads of later iterations (which
-// would hold many more registers live than the pipeline needs).
-#define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
-
-// S^T tiles for every key tile: st[kt] (lane: query r, keys 4g + v) from the
-// wave's 16 query rows qv and the key rows read from global memory.  The key
-// rows of feature chunk c+1 are loaded while chunk c is multiplied.
-template <int NT>
-__device__ __forceinline__ void qk_tiles(const float *__restrict__ krows, int ld, int base, int n,
-                                         int ntile, int r, int g, const floatx4 (&qv)[8],
-                                         floatx4 (&st)[NT]) {
-#pragma unroll
-  for (int kt = 0; kt < NT; ++kt) st[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // rows past n read row 0 of the centre and are replaced by zeros; the row
-  // base is uniform, per-lane offsets are 32-bit
-  const float *kb = krows + (size_t)base * ld;
-  int ko[NT];
-#pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
-    const int row = kt * 16 + r;
-    ko[kt] = (row < n ? row : 0) * ld + 4 * g;
-  }
-  auto load = [&](int c, floatx4 (&kv)[NT]) {
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
-      const floatx4 x = *(const floatx4 *)(kb + ko[kt] + 16 * c);
-      kv[kt] = kt * 16 + r < n ? x : floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-  };
-  floatx4 cur[NT], nxt[NT];
-  load(0, cur);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    if (c + 1 < 8) load(c + 1, nxt);
-    SCHED_FENCE();
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma4(cur[kt][t], qv[c][t], st[kt]);
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt) cur[kt] = nxt[kt];
-  }
+// Floats of the staging buffer: NPAD rows x kLDR or 128 features x (NPAD + 4).
+template <int NPAD>
+constexpr int stage_floats() {
+  return NPAD * kLDR > 128 * (NPAD + 4) ? NPAD * kLDR : 128 * (NPAD + 4);
 }
 
 // --------------------------------------------------------------------- forward
@@ -191,10 +241,12 @@ __device__ __forceinline__ void qk_tiles(const float *__restrict__ krows, int ld
 // Centres are processed by a persistent grid: block b takes the centres
 // b, b + gridDim.x, ... of its class list (every centre of a class costs the
 // same padded work, so the static split is balanced).  One wavefront per
-// 16-query tile.  V is staged transposed in LDS for A V.  The scaled dot
-// products lam = q.k/sqrt(d) (row stride kLamLd, all NPAD key columns of
-// every query row) and the softmax statistics (m, 1/Z) of every query are
-// stored for the adjoint, which then does not recompute Q K^T.
+// 16-query tile.  K is staged row-major in LDS for Q K^T, then V transposed
+// for A V; global memory is touched only by the staging steps, the wave's
+// own query rows and the outputs.  The scaled dot products lam = q.k/sqrt(d)
+// (row stride kLamLd, all NPAD key columns of every query row) and the
+// softmax statistics (m, 1/Z) of every query are stored for the adjoint,
+// which then does not recompute Q K^T.
 
 constexpr int kLamLd = kAttnLamLd;
 
@@ -207,7 +259,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;
-  float *VT = (float *)(smem + NPAD);
+  float *buf = (float *)(smem + NPAD);  // K rows, then V^T
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;  // 1/sqrt(128)
   const int cnt = *ccount;
@@ -220,16 +272,20 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
     const int n = nnei[i];
     const int base = pair_off[i];
     const int ntile = (n + 15) >> 4;
+    const int q = wave * 16 + r;
+    const bool qok = q < n;
+    floatx4 qv[8];
+    if (wave < ntile) load_rows(qkv, ld, base, n, q, g, qv);
     stage_gate<NPAD>(geom, base, n, kg, tid);
-    stage_t<NPAD>(qkv + 256, ld, base, n, VT, tid);
+    stage_rows<NPAD>(qkv + 128, ld, base, n, buf, tid);  // K
     __syncthreads();
+    float4 vpre[8];  // V, read while Q K^T and the softmax run
+    stage_t_load<NPAD>(qkv + 256, ld, base, n, tid, vpre);
+
+    floatx4 st[NT];
+    float invz = 0.f;
     if (wave < ntile) {
-      const int q = wave * 16 + r;
-      const bool qok = q < n;
-      floatx4 qv[8];
-      load_rows(qkv, ld, base, n, q, g, qv);
-      floatx4 st[NT];
-      qk_tiles<NT>(qkv + 128, ld, base, n, ntile, r, g, qv, st);
+      qk_lds<NT>(buf, r, g, qv, st);
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) st[kt] *= inv_sqrt_d;
       if (qok) {
@@ -237,9 +293,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
 #pragma unroll
         for (int kt = 0; kt < NT; ++kt) *(floatx4 *)(lp + 16 * kt) = st[kt];
       }
-
-      const float4 gq = kg[q];
-      const float wq = qok ? gq.w : 0.f;
+      const float wq = qok ? kg[q].w : 0.f;
       float mx = -FLT_MAX;
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) {
@@ -264,9 +318,16 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
         }
       }
       z = sum_groups(z) + (float)(sel - n) * expf(-shift - m);
-      const float invz = 1.0f / z;
+      invz = 1.0f / z;
       if (g == 0 && qok) fstat[base + q] = make_float2(m, invz);
+    }
+    __syncthreads();
+    stage_t_store<NPAD>(buf, tid, vpre);  // V^T
+    __syncthreads();
 
+    if (wave < ntile) {
+      const float4 gq = kg[q];
+      const float wq = qok ? gq.w : 0.f;
       floatx4 oacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) oacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -279,7 +340,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
           const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
           at[v] = st[kt][v] * invz * wq * gk.w * c;
         }
-        accum_lds<NPAD>(VT, kt, r, g, at, oacc);
+        accum_lds<NPAD>(buf, kt, r, g, at, oacc);
       }
       if (qok) {
         float *op = out + (size_t)(base + q) * 128 + 4 * g;
@@ -300,11 +361,11 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
 //   X = dL (lam + S) + dH c  -> dw_q += sum_k X w_k, dw_k += sum_q X w_q
 //   Y = dH w_q w_k           -> drhat_q += sum_k Y rhat_k, drhat_k += sum_q Y rhat_q
 // Two kernels per class, both reading lam and (m, 1/Z) stored by the forward.
-// k_attn_bwd_q (wave = query tile): dA, dS, dQ (K^T in LDS) and the
-// query-side sums; it writes (m, 1/Z, D_q) and the query-side sums per pair.
-// k_attn_bwd_k (wave = key tile): dA recomputed key-major, dK (Q^T in LDS)
-// and the key-side sums, then dV from the tile of A kept in registers (dO^T
-// in LDS); it adds both sides into dE/dsw and dE/drhat.
+// k_attn_bwd_q (wave = query tile): dA^T from V staged row-major, then dS,
+// dQ (K^T staged) and the query-side sums; it writes (m, 1/Z, D_q) and the
+// query-side sums per pair.  k_attn_bwd_k (wave = key tile): dA key-major
+// and dV from dO staged row-major, then dK (Q^T staged) and the key-side
+// sums; it adds both sides into dE/dsw and dE/drhat.
 
 template <int NPAD>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_q(
@@ -315,8 +376,8 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     float *__restrict__ dqkv, float4 *__restrict__ astat, float4 *__restrict__ qside) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
-  float4 *kg = smem;                // [NPAD] rhat, sw
-  float *XT = (float *)(kg + NPAD);  // [128][NPAD + 4]
+  float4 *kg = smem;                  // [NPAD] rhat, sw
+  float *buf = (float *)(kg + NPAD);  // V rows, then K^T
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
@@ -329,37 +390,42 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const int n = nnei[i];
     const int base = pair_off[i];
     const int ntile = (n + 15) >> 4;
+    const int q = wave * 16 + r;
+    const bool qok = q < n;
+    floatx4 dov[8], ov[8];
+    if (wave < ntile) {
+      load_rows(dO, 128, base, n, q, g, dov);
+      load_rows(o, 128, base, n, q, g, ov);
+    }
     stage_gate<NPAD>(geom, base, n, kg, tid);
-    stage_t<NPAD>(qkv + 128, ld, base, n, XT, tid);  // K^T
+    stage_rows<NPAD>(qkv + 256, ld, base, n, buf, tid);  // V
+    __syncthreads();
+    float dq = 0.f;
+    if (wave < ntile) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
+              dov[c][3] * ov[c][3];
+      dq = sum_groups(dq);
+    }
+    float4 kpre[8];  // K, read while dA^T is formed
+    stage_t_load<NPAD>(qkv + 128, ld, base, n, tid, kpre);
+
+    floatx4 da[NT];
+    if (wave < ntile) qk_lds<NT>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
+    __syncthreads();
+    stage_t_store<NPAD>(buf, tid, kpre);  // K^T
     __syncthreads();
 
     if (wave < ntile) {
-      const int q = wave * 16 + r;
-      const bool qok = q < n;
       const int qr = qok ? q : 0;
       const float4 gq = kg[q];
       const float wq = qok ? gq.w : 0.f;
-      // lam of this query row, read one key tile ahead of its use
-      const float *lp = lam + (size_t)(base + qr) * kLamLd + 4 * g;
       const float2 fs = fstat[base + qr];
       const float m = fs.x, invz = fs.y;
-
-      floatx4 da[NT];
-      float dq;
-      {
-        floatx4 dov[8], ov[8];
-        load_rows(dO, 128, base, n, q, g, dov);
-        load_rows(o, 128, base, n, q, g, ov);
-        dq = 0.f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
-                dov[c][3] * ov[c][3];
-        dq = sum_groups(dq);
-        qk_tiles<NT>(qkv + 256, ld, base, n, ntile, r, g, dov, da);  // dA^T tiles
-      }
       if (g == 0 && qok) astat[base + q] = make_float4(m, invz, dq, 0.f);
-
+      // lam of this query row, read one key tile ahead of its use
+      const float *lp = lam + (size_t)(base + qr) * kLamLd + 4 * g;
       floatx4 dqacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -390,7 +456,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           drqy += Y * gk.y;
           drqz += Y * gk.z;
         }
-        accum_lds<NPAD>(XT, kt, r, g, ds, dqacc);
+        accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);
         lcur = lnxt;
       }
       dwq = sum_groups(dwq);
@@ -418,9 +484,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     float *__restrict__ gw, float *__restrict__ gr, int accumulate) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
-  float4 *kg = smem;                 // [NPAD] rhat, sw
-  float4 *stats = kg + NPAD;         // [NPAD] m, 1/Z, D_q of each query
-  float *XT = (float *)(stats + NPAD);  // [128][NPAD + 4]
+  float4 *kg = smem;                     // [NPAD] rhat, sw
+  float4 *stats = kg + NPAD;             // [NPAD] m, 1/Z, D_q of each query
+  float *buf = (float *)(stats + NPAD);  // dO rows, then Q^T
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
@@ -433,16 +499,18 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const int n = nnei[i];
     const int base = pair_off[i];
     const int ntile = (n + 15) >> 4;
+    const int kk = wave * 16 + r;
+    const bool kok = kk < n;
+    floatx4 vreg[8];
+    if (wave < ntile) load_rows(qkv + 256, ld, base, n, kk, g, vreg);
     stage_gate<NPAD>(geom, base, n, kg, tid);
     for (int t = tid; t < NPAD; t += NPAD / 16 * 64)
       stats[t] = t < n ? astat[base + t] : make_float4(0.f, 1.f, 0.f, 0.f);
-    stage_t<NPAD>(qkv, ld, base, n, XT, tid);  // Q^T
+    stage_rows<NPAD>(dO, 128, base, n, buf, tid);  // dO
     __syncthreads();
 
-    // ---------------- phase 1: wave = key tile; dK and the key-side sums
-    const int kk = wave * 16 + r;
-    const bool kok = kk < n;
-    floatx4 at[NT];
+    // ---------------- phase 1: dA key-major, dV, dS and the key-side sums
+    floatx4 ds[NT];
     float dwk = 0.f, drkx = 0.f, drky = 0.f, drkz = 0.f;
     if (wave < ntile) {
       const float4 gk = kg[kk];
@@ -459,22 +527,17 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       };
       float lcur[4], lnxt[4];
       lam_tile(0, lcur);
-      // dA key-major: lane holds key r and queries 4g + v of each query tile
       floatx4 dk[NT];
-      {
-        floatx4 vreg[8];
-        load_rows(qkv + 256, ld, base, n, kk, g, vreg);
-        qk_tiles<NT>(dO, 128, base, n, ntile, r, g, vreg, dk);
-      }
-      floatx4 dkacc[8];
+      qk_lds<NT>(buf, r, g, vreg, dk);  // dA: lane (key r, queries 4g + v)
+      floatx4 dvacc[8];
 #pragma unroll
-      for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int qt = 0; qt < NT; ++qt) {
-        at[qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        ds[qt] = floatx4{0.f, 0.f, 0.f, 0.f};
         if (qt >= ntile) continue;
         if (qt + 1 < NT) lam_tile(qt + 1, lnxt);
-        floatx4 ds;
+        floatx4 at;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int qq = qt * 16 + 4 * g + v;
@@ -490,8 +553,8 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           const float dav = dk[qt][v];
           const float dH = dav * p;
           const float dL = p * (dav * h - sq.z);
-          at[qt][v] = p * h;
-          ds[v] = dL * ww * inv_sqrt_d;
+          at[v] = p * h;
+          ds[qt][v] = dL * ww * inv_sqrt_d;
           const float X = dL * (lm + shift) + dH * c;
           const float Y = dH * ww;
           dwk += X * gq.w;
@@ -499,14 +562,15 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           drky += Y * gq.y;
           drkz += Y * gq.z;
         }
-        accum_lds<NPAD>(XT, qt, r, g, ds, dkacc);
+        accum_rows(buf, qt, r, g, at, dvacc);  // dV = A^T dO
 #pragma unroll
         for (int v = 0; v < 4; ++v) lcur[v] = lnxt[v];
+        __builtin_amdgcn_sched_barrier(0);
       }
       if (kok) {
-        float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+        float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
       }
       dwk = sum_groups(dwk);
       drkx = sum_groups(drkx);
@@ -514,21 +578,21 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       drkz = sum_groups(drkz);
     }
     __syncthreads();
-    stage_t<NPAD>(dO, 128, base, n, XT, tid);  // dO^T
+    stage_t<NPAD>(qkv, ld, base, n, buf, tid);  // Q^T
     __syncthreads();
 
-    // ---------------- phase 2: dV = A^T dO
+    // ---------------- phase 2: dK = dS^T Q
     if (wave < ntile) {
-      floatx4 dvacc[8];
+      floatx4 dkacc[8];
 #pragma unroll
-      for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int qt = 0; qt < NT; ++qt)
-        if (qt < ntile) accum_lds<NPAD>(XT, qt, r, g, at[qt], dvacc);
+        if (qt < ntile) accum_lds<NPAD>(buf, qt, r, g, ds[qt], dkacc);
       if (kok) {
-        float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
+        float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
         if (g == 0) {
           const float4 qs = qsbuf[base + kk];
           const size_t p = (size_t)(base + kk);
@@ -763,15 +827,15 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
 // costs one wave of exiting blocks.
 template <int NPAD>
 size_t fwd_lds() {
-  return sizeof(float4) * NPAD + sizeof(float) * 128 * (NPAD + 4);
+  return sizeof(float4) * NPAD + sizeof(float) * stage_floats<NPAD>();
 }
 template <int NPAD>
 size_t bwdq_lds() {
-  return sizeof(float4) * NPAD + sizeof(float) * 128 * (NPAD + 4);
+  return sizeof(float4) * NPAD + sizeof(float) * stage_floats<NPAD>();
 }
 template <int NPAD>
 size_t bwdk_lds() {
-  return sizeof(float4) * 2 * NPAD + sizeof(float) * 128 * (NPAD + 4);
+  return sizeof(float4) * 2 * NPAD + sizeof(float) * stage_floats<NPAD>();
 }
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.
