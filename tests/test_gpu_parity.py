@@ -267,3 +267,31 @@ def test_replication_2x2x1(model):
     dV = np.abs(V4 - 4 * V1).max() / (4 * n)
     say(f"[replication] dE/N={dE:.2e} max|dF|={dF:.2e} dV/N={dV:.2e}")
     assert dE < E_TOL and dF < F_TOL and dV < V_TOL
+
+
+@pytest.mark.parametrize("tag,shape", [
+    # embedding widths that take the unfused paths: per-layer embedding GEMMs
+    # and the stand-alone output-projection + layer-norm GEMM (padded width 64)
+    ("emb16-32-64_attn1", dict(emb=(16, 32, 64), n_attn=1, fit=(120, 120))),
+    # widths 25 -> 50 -> 50: identity residual in the last embedding layer
+    ("emb25-50-50_attn2", dict(emb=(25, 50, 50), n_attn=2, fit=(64, 64, 64))),
+    # no attention layer: the descriptor takes the embedding output directly
+    ("attn0", dict(n_attn=0)),
+])
+def test_parity_other_architectures(tag, shape, tmp_path):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_07276_amd import binding
+    say(f"case: architecture {tag}, 192-atom system")
+    p = str(tmp_path / f"{tag}.bin")
+    synth.make_weights(p, seed=3, shape=synth.ModelShape(**shape))
+    om = orc.load_model(p)
+    m = binding.Model(p, RC, SEL)
+    try:
+        s = synth.parity_system(1)
+        E, F, V, _ = m.compute(s.coords, s.types, s.box, 192, 0)
+        r = orc.compute(om, s.coords, s.types, s.box, 192, 0, RC, SEL)
+        _assert_parity(tag, 192, E, F, V, r)
+    finally:
+        m.close()
