@@ -105,10 +105,24 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
 // fits in LDS (K = KCH*16 <= 128): each workgroup stages its W^T column
 // block [NT*16][K] in LDS once and then walks over row tiles (4 waves x
 // 16*MT rows), so weights are read from L2 once per workgroup instead of once
-// per wavefront.  A wavefront loads the whole K extent of its rows with
-// 16-byte loads up front and reads the weights from LDS with 16-byte LDS
-// loads.  gridDim.x is a multiple of 8 so that the column blocks of one row
-// tile are dispatched to the same XCD (shared L2 for the activations).
+// per wavefront.  A wavefront holds the whole K extent of its rows in
+// registers and loads the rows of its next tile while it multiplies the
+// current one, so the HBM latency of the activations is paid once per
+// launch rather than once per tile.  gridDim.x is a multiple of 8 so that
+// the column blocks of one row tile are dispatched to the same XCD (shared
+// L2 for the activations).
+template <int MT, int KCH>
+__device__ __forceinline__ void load_x_tile(const GemmArgs &a, int row0, int M, int r, int g,
+                                            floatx4 (&x)[MT][KCH]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = row0 + mt * 16 + r;
+    const float *xp = a.X + (size_t)(row < M ? row : 0) * a.ldx + 4 * g;
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) x[mt][c] = *(const floatx4 *)(xp + 16 * c);
+  }
+}
+
 template <int MT, int NT, int KCH, class Epi>
 __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   constexpr int K = KCH * 16;
@@ -130,17 +144,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   }
   __syncthreads();
   const float *wl = wsm + r * LDW + 4 * g;
-  for (int rt = blockIdx.x; rt * 64 * MT < M; rt += gridDim.x) {
-    const int row0 = (rt * 4 + wave) * 16 * MT;
-    if (row0 >= M) continue;
-    floatx4 xr[MT][KCH];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int row = row0 + mt * 16 + r;
-      const float *xp = a.X + (size_t)(row < M ? row : 0) * a.ldx + 4 * g;
-#pragma unroll
-      for (int c = 0; c < KCH; ++c) xr[mt][c] = *(const floatx4 *)(xp + 16 * c);
-    }
+  const int stride = gridDim.x * 64 * MT;  // rows between a wave's consecutive tiles
+  int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  floatx4 xr[MT][KCH], xn[MT][KCH];
+  if (row0 < M) load_x_tile<MT, KCH>(a, row0, M, r, g, xr);
+  for (; row0 < M; row0 += stride) {
+    // the layer-norm epilogue holds more registers: its prefetch waits until
+    // the current tile's activations are dead
+    if constexpr (Epi::kLds == 1)
+      if (row0 + stride < M) load_x_tile<MT, KCH>(a, row0 + stride, M, r, g, xn);
     floatx4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -151,6 +163,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
       floatx4 w[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * LDW + 16 * c);
+      __builtin_amdgcn_sched_barrier(0);  // one chunk of weights live at a time
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -159,13 +172,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
           for (int mt = 0; mt < MT; ++mt)
             acc[mt][nt] = mfma4(w[nt][t], xr[mt][c][t], acc[mt][nt]);
     }
+    if constexpr (Epi::kLds == 2)
+      if (row0 + stride < M) load_x_tile<MT, KCH>(a, row0 + stride, M, r, g, xn);
     epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int c = 0; c < KCH; ++c) xr[mt][c] = xn[mt][c];
   }
 }
 
 // ------------------------------------------------------------------ epilogues
 
 struct EpiLinear {
+  static constexpr int kLds = 1;  // LDS-weight kernel, next tile prefetched before the MFMAs
   const float *bias;
   float *y;
   int ldy;
@@ -195,6 +215,7 @@ struct EpiLinear {
 };
 
 struct EpiTanhRes {
+  static constexpr int kLds = 0;  // streaming kernel only
   const float *bias;
   const int32_t *row_type;
   int bias_ld;
@@ -245,6 +266,7 @@ struct EpiTanhRes {
 
 // Output projection + layer norm + residual (all output columns in one wave).
 struct EpiLNRes {
+  static constexpr int kLds = 2;  // LDS-weight kernel, next tile prefetched after the MFMAs
   const float *bias, *gamma, *beta;
   float eps;
   const float *gin;
@@ -316,6 +338,7 @@ struct EpiLNRes {
 
 // d = acc + residual gradient ; a = d * (1 - t^2)
 struct EpiBwdTanh {
+  static constexpr int kLds = 0;  // streaming kernel only
   const float *res;
   int ldr;
   int res_mode;
@@ -366,6 +389,7 @@ struct EpiBwdTanh {
 
 // dgin = acc + dgout ; then layer-norm backward (mode 0) or tanh backward (mode 1).
 struct EpiQKVBwd {
+  static constexpr int kLds = 0;  // streaming kernel only
   const float *dgout;
   int mode;
   const float *gamma, *xhat, *rstd, *t;
@@ -442,6 +466,7 @@ struct EpiQKVBwd {
 
 // dh1 = acc + residual(dh2); du1 = dh1 * (1 - h1^2); gs = sum_o du1[o] * ws[o]
 struct EpiEmb1Bwd {
+  static constexpr int kLds = 0;  // streaming kernel only
   const float *dh2;
   int ldd2, res_mode, fin;
   const float *h1;
@@ -505,8 +530,21 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   const int ntt = a.Npad / 16;
   const unsigned gy = (unsigned)((ntt + NT - 1) / NT);
   const int row_tiles = (a.Mmax + 64 * MT - 1) / (64 * MT);
-  int gx = (512 + (int)gy - 1) / (int)gy;  // about two workgroups per CU in total
-  gx = (gx + 7) / 8 * 8;
+  // two workgroups per CU are resident (LDS and registers); the grid must not
+  // exceed that, or the blocks past it start only when others have finished
+  // their whole share and the launch takes twice as long
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  int gx = 2 * cus / (int)gy / 8 * 8;
+  if (gx < 8) gx = 8;
   if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
   if (gx <= 0) return;
   const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4);
@@ -520,14 +558,13 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
   const int ntt = a.Npad / 16;
   int nt = ntt < 8 ? ntt : 8;
   if (full_rows && ntt > 8) nt = ntt;  // callers guarantee ntt <= 8 for row reductions
-  // the LDS-resident weight block pays off only when one column block covers
-  // the whole output (measured: 3 column blocks of the 384-wide projection
-  // run 1.5x slower than the streaming kernel)
-  if (a.Mmax >= 65536 && (a.K == 112 || a.K == 128) && ntt <= 8 && (nt == 7 || nt == 8)) {
-    if (nt == 7 && a.K == 112) return launch_lds<Epi, 7, 7>(a, e, s);
-    if (nt == 7 && a.K == 128) return launch_lds<Epi, 7, 8>(a, e, s);
-    if (nt == 8 && a.K == 112) return launch_lds<Epi, 8, 7>(a, e, s);
-    return launch_lds<Epi, 8, 8>(a, e, s);
+  if constexpr (Epi::kLds != 0) {
+    if (a.Mmax >= 65536 && (a.K == 112 || a.K == 128) && (nt == 7 || nt == 8)) {
+      if (nt == 7 && a.K == 112) return launch_lds<Epi, 7, 7>(a, e, s);
+      if (nt == 7 && a.K == 128) return launch_lds<Epi, 7, 8>(a, e, s);
+      if (nt == 8 && a.K == 112) return launch_lds<Epi, 8, 7>(a, e, s);
+      return launch_lds<Epi, 8, 8>(a, e, s);
+    }
   }
   if (a.Mmax >= 65536) dispatch_nt<Epi, 2>(a, e, nt, s);
   else dispatch_nt<Epi, 1>(a, e, nt, s);
