@@ -56,17 +56,14 @@ __device__ __forceinline__ float sum_rows(float v) {  // over the 16 lanes of a 
 }
 
 // Load one 16x128 row tile as the MFMA B operand: lane holds row r,
-// features 16c + 4g + {0..3}.
+// features 16c + 4g + {0..3}.  Rows past n read row 0 of the centre (finite
+// values; every use of such a row is masked), so no load waits on a select.
 __device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld, int base,
                                           int n, int row, int g, floatx4 (&v)[8]) {
-  const bool ok = row < n;
   const float *rb = rows + (size_t)base * ld;
-  const int off = (ok ? row : 0) * ld + 4 * g;
+  const int off = (row < n ? row : 0) * ld + 4 * g;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const floatx4 x = *(const floatx4 *)(rb + off + 16 * c);
-    v[c] = ok ? x : floatx4{0.f, 0.f, 0.f, 0.f};
-  }
+  for (int c = 0; c < 8; ++c) v[c] = *(const floatx4 *)(rb + off + 16 * c);
 }
 
 // Row stride of the row-major LDS tiles: 128 features + 4 (with it, eight
@@ -78,25 +75,33 @@ constexpr int kLDR = 132;
 // row-major, X[row][kLDR]; rows n..NPAD-1 are zero.  Products whose A operand
 // runs along the features (Q K^T, dO V^T) read it with one 16-byte LDS load
 // per lane per four MFMA steps.
+// The loads and the LDS writes are separate steps so that a kernel issues
+// every global load of a phase before it waits for any (a load whose value is
+// consumed at once, or a branch that overwrites it, serialises the latencies).
+// Rows past n read row 0 and are written as zeros (a select at the write).
 template <int NPAD>
-__device__ __forceinline__ void stage_rows(const float *__restrict__ src, int ld, int base, int n,
-                                           float *X, int tid) {
+__device__ __forceinline__ void stage_rows_load(const float *__restrict__ src, int ld, int base,
+                                                int n, int tid, float4 (&v)[8]) {
   constexpr int THREADS = NPAD / 16 * 64;
-  constexpr int ITER = NPAD * 32 / THREADS;  // = 8
-  float4 v[ITER];
+  static_assert(NPAD * 32 / THREADS == 8, "eight float4 per thread");
 #pragma unroll
-  for (int it = 0; it < ITER; ++it) {
+  for (int it = 0; it < 8; ++it) {
     const int idx = tid + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
     const int rr = row < n ? row : 0;
     v[it] = *(const float4 *)(src + (size_t)(base + rr) * ld + 4 * c4);
-    if (row >= n) v[it] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
+}
+template <int NPAD>
+__device__ __forceinline__ void stage_rows_store(float *X, int tid, int n, const float4 (&v)[8]) {
+  constexpr int THREADS = NPAD / 16 * 64;
 #pragma unroll
-  for (int it = 0; it < ITER; ++it) {
+  for (int it = 0; it < 8; ++it) {
     const int idx = tid + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
-    *(float4 *)(X + row * kLDR + 4 * c4) = v[it];
+    const bool ok = row < n;
+    *(float4 *)(X + row * kLDR + 4 * c4) =
+        make_float4(ok ? v[it].x : 0.f, ok ? v[it].y : 0.f, ok ? v[it].z : 0.f, ok ? v[it].w : 0.f);
   }
 }
 
@@ -117,23 +122,22 @@ __device__ __forceinline__ void stage_t_load(const float *__restrict__ src, int 
   const int rr = row < n ? row : 0;
   const float *sp = src + (size_t)(base + rr) * ld + 4 * cq;
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    v[it] = *(const float4 *)(sp + 16 * it);
-    if (row >= n) v[it] = make_float4(0.f, 0.f, 0.f, 0.f);
-  }
+  for (int it = 0; it < 8; ++it) v[it] = *(const float4 *)(sp + 16 * it);
 }
+// rows past n (loaded from row 0) are written as zeros
 template <int NPAD>
-__device__ __forceinline__ void stage_t_store(float *XT, int tid, const float4 (&v)[8]) {
+__device__ __forceinline__ void stage_t_store(float *XT, int tid, int n, const float4 (&v)[8]) {
   constexpr int LDT = NPAD + 4;
   const int row = (tid >> 6) * 16 + (tid & 15);
   const int cq = (tid >> 4) & 3;
+  const bool ok = row < n;
 #pragma unroll
   for (int it = 0; it < 8; ++it) {
     float *d = XT + (16 * it + 4 * cq) * LDT + row;
-    d[0] = v[it].x;
-    d[LDT] = v[it].y;
-    d[2 * LDT] = v[it].z;
-    d[3 * LDT] = v[it].w;
+    d[0] = ok ? v[it].x : 0.f;
+    d[LDT] = ok ? v[it].y : 0.f;
+    d[2 * LDT] = ok ? v[it].z : 0.f;
+    d[3 * LDT] = ok ? v[it].w : 0.f;
   }
 }
 template <int NPAD>
@@ -141,20 +145,23 @@ __device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, i
                                         float *XT, int tid) {
   float4 v[8];
   stage_t_load<NPAD>(src, ld, base, n, tid, v);
-  stage_t_store<NPAD>(XT, tid, v);
+  stage_t_store<NPAD>(XT, tid, n, v);
 }
 
+// Gate record of neighbour t = tid (rhat, sw; zeros past n), for kg[NPAD]:
+// one unconditional load per thread (threads past NPAD read slot 0), written
+// by gate_store.
+__device__ __forceinline__ float4 gate_load(const float *__restrict__ geom, int base, int n,
+                                            int tid) {
+  const int t = tid < n ? tid : 0;
+  const float4 *gp = (const float4 *)(geom + (size_t)(base + t) * kGeom);
+  const float4 a = gp[0], b = gp[1];  // s, rx, ry, rz | sw, r, dsw, -
+  return make_float4(a.y, a.z, a.w, b.x);
+}
 template <int NPAD>
-__device__ __forceinline__ void stage_gate(const float *__restrict__ geom, int base, int n,
-                                           float4 *kg, int tid) {
-  for (int t = tid; t < NPAD; t += NPAD / 16 * 64) {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < n) {
-      const float *gp = geom + (size_t)(base + t) * kGeom;
-      v = make_float4(gp[G_RX], gp[G_RY], gp[G_RZ], gp[G_SW]);
-    }
-    kg[t] = v;
-  }
+__device__ __forceinline__ void gate_store(float4 *kg, int tid, int n, const float4 &v) {
+  const bool ok = tid < n;
+  if (tid < NPAD) kg[tid] = make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
 }
 
 // acc[ft] += XT^T-tile x bt : contraction over the 16 rows of tile 'tile',
@@ -274,10 +281,13 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
     const int ntile = (n + 15) >> 4;
     const int q = wave * 16 + r;
     const bool qok = q < n;
+    float4 sv[8];
+    stage_rows_load<NPAD>(qkv + 128, ld, base, n, tid, sv);  // K
+    const float4 gv = gate_load(geom, base, n, tid);
     floatx4 qv[8];
-    if (wave < ntile) load_rows(qkv, ld, base, n, q, g, qv);
-    stage_gate<NPAD>(geom, base, n, kg, tid);
-    stage_rows<NPAD>(qkv + 128, ld, base, n, buf, tid);  // K
+    load_rows(qkv, ld, base, n, q, g, qv);
+    stage_rows_store<NPAD>(buf, tid, n, sv);
+    gate_store<NPAD>(kg, tid, n, gv);
     __syncthreads();
     float4 vpre[8];  // V, read while Q K^T and the softmax run
     stage_t_load<NPAD>(qkv + 256, ld, base, n, tid, vpre);
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
       if (g == 0 && qok) fstat[base + q] = make_float2(m, invz);
     }
     __syncthreads();
-    stage_t_store<NPAD>(buf, tid, vpre);  // V^T
+    stage_t_store<NPAD>(buf, tid, n, vpre);  // V^T
     __syncthreads();
 
     if (wave < ntile) {
@@ -392,13 +402,14 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const int ntile = (n + 15) >> 4;
     const int q = wave * 16 + r;
     const bool qok = q < n;
+    float4 sv[8];
+    stage_rows_load<NPAD>(qkv + 256, ld, base, n, tid, sv);  // V
+    const float4 gv = gate_load(geom, base, n, tid);
     floatx4 dov[8], ov[8];
-    if (wave < ntile) {
-      load_rows(dO, 128, base, n, q, g, dov);
-      load_rows(o, 128, base, n, q, g, ov);
-    }
-    stage_gate<NPAD>(geom, base, n, kg, tid);
-    stage_rows<NPAD>(qkv + 256, ld, base, n, buf, tid);  // V
+    load_rows(dO, 128, base, n, q, g, dov);
+    load_rows(o, 128, base, n, q, g, ov);
+    stage_rows_store<NPAD>(buf, tid, n, sv);
+    gate_store<NPAD>(kg, tid, n, gv);
     __syncthreads();
     float dq = 0.f;
     if (wave < ntile) {
@@ -414,7 +425,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     floatx4 da[NT];
     if (wave < ntile) qk_lds<NT>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
     __syncthreads();
-    stage_t_store<NPAD>(buf, tid, kpre);  // K^T
+    stage_t_store<NPAD>(buf, tid, n, kpre);  // K^T
     __syncthreads();
 
     if (wave < ntile) {
@@ -501,12 +512,15 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const int ntile = (n + 15) >> 4;
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
+    float4 sv[8];
+    stage_rows_load<NPAD>(dO, 128, base, n, tid, sv);  // dO
+    const float4 gv = gate_load(geom, base, n, tid);
+    const float4 av = astat[base + (tid < n ? tid : 0)];
     floatx4 vreg[8];
-    if (wave < ntile) load_rows(qkv + 256, ld, base, n, kk, g, vreg);
-    stage_gate<NPAD>(geom, base, n, kg, tid);
-    for (int t = tid; t < NPAD; t += NPAD / 16 * 64)
-      stats[t] = t < n ? astat[base + t] : make_float4(0.f, 1.f, 0.f, 0.f);
-    stage_rows<NPAD>(dO, 128, base, n, buf, tid);  // dO
+    load_rows(qkv + 256, ld, base, n, kk, g, vreg);
+    stage_rows_store<NPAD>(buf, tid, n, sv);
+    gate_store<NPAD>(kg, tid, n, gv);
+    if (tid < NPAD) stats[tid] = tid < n ? av : make_float4(0.f, 1.f, 0.f, 0.f);
     __syncthreads();
 
     // ---------------- phase 1: dA key-major, dV, dS and the key-side sums
