@@ -34,14 +34,20 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
+template <class Epi, int NT>
+__device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs);
+
 template <int MT, int NT, class Epi>
 __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
+  __shared__ float cs[Epi::kCols * NT * 16];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
-  if (row0 >= M) return;
   const int nt0 = blockIdx.y * NT;
+  stage_cols<Epi, NT>(epi, nt0, a.Npad, cs);
+  __syncthreads();
+  if (row0 >= M) return;
   const int ntt = a.Npad / 16;
   const int r = lane & 15;
   const int g = lane >> 4;
@@ -98,7 +104,7 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) wv[nt] = wn[nt];
   }
-  epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
+  epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
 }
 
 // Persistent variant for the large pair-batched products whose weight tile
@@ -142,6 +148,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
     if (n < a.Npad) v = *(const float4 *)(a.Wt + (size_t)n * a.K + 4 * c4);
     *(float4 *)(wsm + row * LDW + 4 * c4) = v;
   }
+  float *cs = wsm + NT * 16 * LDW;  // [Epi::kCols][NT * 16]
+  stage_cols<Epi, NT>(epi, nt0, a.Npad, cs);
   __syncthreads();
   const float *wl = wsm + r * LDW + 4 * g;
   const int stride = gridDim.x * 64 * MT;  // rows between a wave's consecutive tiles
@@ -174,7 +182,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
     }
     if constexpr (Epi::kLds == 2)
       if (row0 + stride < M) load_x_tile<MT, KCH>(a, row0 + stride, M, r, g, xn);
-    epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M);
+    epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -183,16 +191,31 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
 }
 
 // ------------------------------------------------------------------ epilogues
+//
+// Every epilogue issues all the global loads of a 16-row tile (clamped to
+// valid rows and columns) before it uses any of them, and masks with selects:
+// a load inside a branch, or a value used right after its load, makes the
+// wavefront wait for that load alone, and a few dozen such waits cost more
+// than the MFMAs of the tile.  Per-column vectors (bias, gamma, ...) are
+// staged in LDS once per block: Epi::kCols of them over the block's NT*16
+// columns, a null pointer staging zeros.  Optional row operands that a mode
+// does not use read the zero table instead of branching around the load.
+
+constexpr int kMaxCols = 3;
+constexpr int kZeros = 4096;
+__device__ float g_zeros[kZeros];  // zero-initialised, never written
 
 struct EpiLinear {
   static constexpr int kLds = 1;  // LDS-weight kernel, next tile prefetched before the MFMAs
+  static constexpr int kCols = 1;
   const float *bias;
   float *y;
   int ldy;
   int Nreal;
+  __device__ __forceinline__ const float *col(int) const { return bias; }
   template <int MT, int NT>
-  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
-                        int M) const {
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -201,21 +224,22 @@ struct EpiLinear {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (nt0 + nt >= ntt) continue;
+        const floatx4 b = *(const floatx4 *)(cs + nt * 16 + 4 * g);
         const int n0 = (nt0 + nt) * 16 + 4 * g;
         floatx4 o;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int n = n0 + v;
-          o[v] = n < Nreal ? acc[mt][nt][v] + (bias ? bias[n] : 0.f) : 0.f;
-        }
+        for (int v = 0; v < 4; ++v) o[v] = n0 + v < Nreal ? acc[mt][nt][v] + b[v] : 0.f;
         *(floatx4 *)(y + (size_t)row * ldy + n0) = o;
       }
     }
   }
 };
 
+// y = tanh(acc + b) + res ; the bias is per column, or per row type when
+// row_type is set (bias [ntypes][bias_ld], read from global memory).
 struct EpiTanhRes {
   static constexpr int kLds = 0;  // streaming kernel only
+  static constexpr int kCols = 1;
   const float *bias;
   const int32_t *row_type;
   int bias_ld;
@@ -228,15 +252,41 @@ struct EpiTanhRes {
   float *tout;
   int ldt;
   int Nreal;
+  __device__ __forceinline__ const float *col(int) const { return row_type ? nullptr : bias; }
   template <int MT, int NT>
-  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
-                        int M) const {
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
+    const bool dbl = res_mode == RES_DOUBLE;
+    const float *rp = (res_mode == RES_IDENT || dbl) ? res : g_zeros;
+    const int rld = (res_mode == RES_IDENT || dbl) ? ldr : 0;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
-      if (row >= M) continue;
-      const float *b = bias + (row_type ? (size_t)row_type[row] * bias_ld : 0);
+      const bool ok = row < M;
+      const size_t rr = (size_t)(ok ? row : 0);
+      floatx4 bl[NT];
+      float rv[NT][4];
+      if (row_type) {
+        const float *bp = bias + (size_t)row_type[rr] * bias_ld;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+          bl[nt] = *(const floatx4 *)(bp + tile * 16 + 4 * g);
+        }
+      } else {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bl[nt] = *(const floatx4 *)(cs + nt * 16 + 4 * g);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = (nt0 + nt) * 16 + 4 * g + v;
+          const int nn = n < Nreal ? n : 0;
+          rv[nt][v] = rp[rr * rld + (dbl ? nn % res_fin : nn)];
+        }
+      if (!ok) continue;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (nt0 + nt >= ntt) continue;
@@ -244,21 +294,13 @@ struct EpiTanhRes {
         floatx4 o, tv;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int n = n0 + v;
-          if (n < Nreal) {
-            const float t = tanhf(acc[mt][nt][v] + b[n]);
-            float rr = 0.f;
-            if (res_mode == RES_IDENT) rr = res[(size_t)row * ldr + n];
-            else if (res_mode == RES_DOUBLE) rr = res[(size_t)row * ldr + n % res_fin];
-            o[v] = t + rr;
-            tv[v] = t;
-          } else {
-            o[v] = 0.f;
-            tv[v] = 0.f;
-          }
+          const bool in = n0 + v < Nreal;
+          const float t = tanhf(acc[mt][nt][v] + bl[nt][v]);
+          o[v] = in ? t + rv[nt][v] : 0.f;
+          tv[v] = in ? t : 0.f;
         }
-        *(floatx4 *)(y + (size_t)row * ldy + n0) = o;
-        if (tout) *(floatx4 *)(tout + (size_t)row * ldt + n0) = tv;
+        *(floatx4 *)(y + rr * ldy + n0) = o;
+        if (tout) *(floatx4 *)(tout + rr * ldt + n0) = tv;
       }
     }
   }
@@ -267,31 +309,43 @@ struct EpiTanhRes {
 // Output projection + layer norm + residual (all output columns in one wave).
 struct EpiLNRes {
   static constexpr int kLds = 2;  // LDS-weight kernel, next tile prefetched after the MFMAs
+  static constexpr int kCols = 3;
   const float *bias, *gamma, *beta;
   float eps;
   const float *gin;
   int ld;  // row stride of gin, gout, xhat (= Npad)
   float *gout, *xhat, *rstd;
   int Nreal;
+  __device__ __forceinline__ const float *col(int k) const {
+    return k == 0 ? bias : (k == 1 ? gamma : beta);
+  }
   template <int MT, int NT>
-  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
-                        int M) const {
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
     const float invn = 1.0f / (float)Nreal;
+    constexpr int CW = NT * 16;  // staged columns per vector
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
       const bool ok = row < M;
+      const size_t rb = (size_t)(ok ? row : 0) * ld;
+      floatx4 gi[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int tile = nt < ntt ? nt : 0;
+        gi[nt] = *(const floatx4 *)(gin + rb + tile * 16 + 4 * g);
+      }
       float s1 = 0.f;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
+        const floatx4 b = *(const floatx4 *)(cs + nt * 16 + 4 * g);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          if (nt < ntt && n < Nreal) {
-            acc[mt][nt][v] += bias[n];
-            s1 += acc[mt][nt][v];
-          }
+          const bool in = nt < ntt && n < Nreal;
+          acc[mt][nt][v] = in ? acc[mt][nt][v] + b[v] : 0.f;
+          s1 += acc[mt][nt][v];
         }
       }
       const float mean = row_sum16(s1) * invn;
@@ -301,10 +355,8 @@ struct EpiLNRes {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          if (nt < ntt && n < Nreal) {
-            const float c = acc[mt][nt][v] - mean;
-            s2 += c * c;
-          }
+          const float c = acc[mt][nt][v] - mean;
+          s2 += (nt < ntt && n < Nreal) ? c * c : 0.f;
         }
       }
       const float var = row_sum16(s2) * invn;
@@ -315,30 +367,28 @@ struct EpiLNRes {
       for (int nt = 0; nt < NT; ++nt) {
         if (nt >= ntt) continue;
         const int n0 = nt * 16 + 4 * g;
-        const floatx4 gi = *(const floatx4 *)(gin + (size_t)row * ld + n0);
+        const floatx4 gm = *(const floatx4 *)(cs + CW + n0);
+        const floatx4 bt = *(const floatx4 *)(cs + 2 * CW + n0);
         floatx4 go, xh;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int n = n0 + v;
-          if (n < Nreal) {
-            const float x = (acc[mt][nt][v] - mean) * rs;
-            xh[v] = x;
-            go[v] = gi[v] + gamma[n] * x + beta[n];
-          } else {
-            xh[v] = 0.f;
-            go[v] = 0.f;
-          }
+          const bool in = n0 + v < Nreal;
+          const float x = (acc[mt][nt][v] - mean) * rs;
+          xh[v] = in ? x : 0.f;
+          go[v] = in ? gi[nt][v] + gm[v] * x + bt[v] : 0.f;
         }
-        *(floatx4 *)(gout + (size_t)row * ld + n0) = go;
-        *(floatx4 *)(xhat + (size_t)row * ld + n0) = xh;
+        *(floatx4 *)(gout + rb + n0) = go;
+        *(floatx4 *)(xhat + rb + n0) = xh;
       }
     }
   }
 };
 
-// d = acc + residual gradient ; a = d * (1 - t^2)
+// d = acc + residual gradient ; a = d * (1 - t^2).  The residual is a row
+// operand (RES_IDENT, RES_FOLD) or a column vector (RES_BCAST).
 struct EpiBwdTanh {
   static constexpr int kLds = 0;  // streaming kernel only
+  static constexpr int kCols = 1;
   const float *res;
   int ldr;
   int res_mode;
@@ -350,114 +400,121 @@ struct EpiBwdTanh {
   float *aout;
   int lda;
   int Nreal;
+  __device__ __forceinline__ const float *col(int) const {
+    return res_mode == RES_BCAST ? res : nullptr;
+  }
   template <int MT, int NT>
-  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
-                        int M) const {
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
+    const bool rowres = res_mode == RES_IDENT || res_mode == RES_FOLD;
+    const float *rp = rowres ? res : g_zeros;
+    const int rld = rowres ? ldr : 0;
+    const int fold = res_mode == RES_FOLD ? res_fin : 0;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
-      if (row >= M) continue;
+      const bool ok = row < M;
+      const size_t rr = (size_t)(ok ? row : 0);
+      floatx4 tt[NT];
+      float r1[NT][4], r2[NT][4];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+        tt[nt] = *(const floatx4 *)(t + rr * ldt + tile * 16 + 4 * g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = tile * 16 + 4 * g + v;
+          const int nn = n < Nreal ? n : 0;
+          r1[nt][v] = rp[rr * rld + nn];
+          r2[nt][v] = rp[rr * rld + nn + fold];  // = r1 unless folding; masked at use
+        }
+      }
+      if (!ok) continue;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (nt0 + nt >= ntt) continue;
         const int n0 = (nt0 + nt) * 16 + 4 * g;
+        const floatx4 bc = *(const floatx4 *)(cs + nt * 16 + 4 * g);
         floatx4 dv, av;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int n = n0 + v;
-          if (n < Nreal) {
-            float x = acc[mt][nt][v];
-            if (res_mode == RES_IDENT) x += res[(size_t)row * ldr + n];
-            else if (res_mode == RES_BCAST) x += res[n];
-            else if (res_mode == RES_FOLD)
-              x += res[(size_t)row * ldr + n] + res[(size_t)row * ldr + n + res_fin];
-            const float tt = t[(size_t)row * ldt + n];
-            dv[v] = x;
-            av[v] = x * (1.0f - tt * tt);
-          } else {
-            dv[v] = 0.f;
-            av[v] = 0.f;
-          }
+          const bool in = n0 + v < Nreal;
+          const float x = acc[mt][nt][v] + r1[nt][v] + (fold ? r2[nt][v] : 0.f) + bc[v];
+          dv[v] = in ? x : 0.f;
+          av[v] = in ? x * (1.0f - tt[nt][v] * tt[nt][v]) : 0.f;
         }
-        if (d) *(floatx4 *)(d + (size_t)row * ldd + n0) = dv;
-        *(floatx4 *)(aout + (size_t)row * lda + n0) = av;
+        if (d) *(floatx4 *)(d + rr * ldd + n0) = dv;
+        *(floatx4 *)(aout + rr * lda + n0) = av;
       }
     }
   }
 };
 
-// dgin = acc + dgout ; then layer-norm backward (mode 0) or tanh backward (mode 1).
+// dgin = acc + dgout ; then layer-norm backward (mode 0), tanh backward
+// (mode 1) or nothing (mode 2).
 struct EpiQKVBwd {
   static constexpr int kLds = 0;  // streaming kernel only
+  static constexpr int kCols = 1;
   const float *dgout;
   int mode;
   const float *gamma, *xhat, *rstd, *t;
   int ld;
   float *dgin, *dnext;
   int Nreal;
+  __device__ __forceinline__ const float *col(int) const { return mode == 0 ? gamma : nullptr; }
   template <int MT, int NT>
-  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
-                        int M) const {
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
     const float invn = 1.0f / (float)Nreal;
+    // second row operand: xhat (mode 0) or t (mode 1); mode 2 rereads dgout
+    const float *aux = mode == 0 ? xhat : (mode == 1 ? t : dgout);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
       const bool ok = row < M;
       const size_t rb = (size_t)(ok ? row : 0) * ld;
+      floatx4 go[NT], ax[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int tile = nt < ntt ? nt : 0;
+        go[nt] = *(const floatx4 *)(dgout + rb + tile * 16 + 4 * g);
+        ax[nt] = *(const floatx4 *)(aux + rb + tile * 16 + 4 * g);
+      }
+      const float rs = *(mode == 0 ? rstd + (ok ? row : 0) : g_zeros);
       float s1 = 0.f, s2 = 0.f;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        if (nt >= ntt) continue;
-        const int n0 = nt * 16 + 4 * g;
-        const floatx4 go = *(const floatx4 *)(dgout + rb + n0);
-        floatx4 xh = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (mode == 0) xh = *(const floatx4 *)(xhat + rb + n0);
+        const floatx4 gm = *(const floatx4 *)(cs + nt * 16 + 4 * g);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int n = n0 + v;
-          if (n < Nreal) {
-            acc[mt][nt][v] += go[v];
-            if (mode == 0) {
-              const float dx = gamma[n] * acc[mt][nt][v];
-              s1 += dx;
-              s2 += dx * xh[v];
-            }
-          } else {
-            acc[mt][nt][v] = 0.f;
-          }
+          const int n = nt * 16 + 4 * g + v;
+          const bool in = nt < ntt && n < Nreal;
+          acc[mt][nt][v] = in ? acc[mt][nt][v] + go[nt][v] : 0.f;
+          const float dx = gm[v] * acc[mt][nt][v];
+          s1 += dx;
+          s2 += dx * ax[nt][v];
         }
       }
-      float m1 = 0.f, m2 = 0.f, rs = 0.f;
-      if (mode == 0) {
-        m1 = row_sum16(s1) * invn;
-        m2 = row_sum16(s2) * invn;
-        rs = ok ? rstd[row] : 0.f;
-      }
+      const float m1 = row_sum16(s1) * invn;
+      const float m2 = row_sum16(s2) * invn;
       if (!ok) continue;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         if (nt >= ntt) continue;
         const int n0 = nt * 16 + 4 * g;
-        floatx4 dn;
-        if (mode == 2) {
-          *(floatx4 *)(dgin + rb + n0) = acc[mt][nt];
-          continue;
-        }
-        if (mode == 0) {
-          const floatx4 xh = *(const floatx4 *)(xhat + rb + n0);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int n = n0 + v;
-            dn[v] = n < Nreal ? rs * (gamma[n] * acc[mt][nt][v] - m1 - xh[v] * m2) : 0.f;
-          }
-        } else {
-          const floatx4 tt = *(const floatx4 *)(t + rb + n0);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) dn[v] = acc[mt][nt][v] * (1.0f - tt[v] * tt[v]);
-        }
         *(floatx4 *)(dgin + rb + n0) = acc[mt][nt];
+        if (mode == 2) continue;
+        const floatx4 gm = *(const floatx4 *)(cs + n0);
+        floatx4 dn;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool in = n0 + v < Nreal;
+          const float ln = rs * (gm[v] * acc[mt][nt][v] - m1 - ax[nt][v] * m2);
+          const float th = acc[mt][nt][v] * (1.0f - ax[nt][v] * ax[nt][v]);
+          dn[v] = in ? (mode == 0 ? ln : th) : 0.f;
+        }
         *(floatx4 *)(dnext + rb + n0) = dn;
       }
     }
@@ -467,6 +524,7 @@ struct EpiQKVBwd {
 // dh1 = acc + residual(dh2); du1 = dh1 * (1 - h1^2); gs = sum_o du1[o] * ws[o]
 struct EpiEmb1Bwd {
   static constexpr int kLds = 0;  // streaming kernel only
+  static constexpr int kCols = 1;
   const float *dh2;
   int ldd2, res_mode, fin;
   const float *h1;
@@ -474,29 +532,41 @@ struct EpiEmb1Bwd {
   const float *ws;
   float *gs;
   int Nreal;
+  __device__ __forceinline__ const float *col(int) const { return ws; }
   template <int MT, int NT>
-  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt, int lane,
-                        int M) const {
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
+    const bool rowres = res_mode == RES_IDENT || res_mode == RES_FOLD;
+    const float *rp = rowres ? dh2 : g_zeros;
+    const int rld = rowres ? ldd2 : 0;
+    const int fold = res_mode == RES_FOLD ? fin : 0;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
       const bool ok = row < M;
       const size_t rr = (size_t)(ok ? row : 0);
-      float s = 0.f;
+      float hv[NT][4], r1[NT][4], r2[NT][4];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        if (nt >= ntt) continue;
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          if (n < Nreal) {
-            float d = acc[mt][nt][v];
-            if (res_mode == RES_IDENT) d += dh2[rr * ldd2 + n];
-            else if (res_mode == RES_FOLD) d += dh2[rr * ldd2 + n] + dh2[rr * ldd2 + n + fin];
-            const float h = h1[rr * ldh1 + n];
-            s += d * (1.0f - h * h) * ws[n];
-          }
+          const int nn = (nt < ntt && n < Nreal) ? n : 0;
+          hv[nt][v] = h1[rr * ldh1 + nn];
+          r1[nt][v] = rp[rr * rld + nn];
+          r2[nt][v] = rp[rr * rld + nn + fold];  // = r1 unless folding; masked at use
+        }
+      float s = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const floatx4 wv = *(const floatx4 *)(cs + nt * 16 + 4 * g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          const float dd = acc[mt][nt][v] + r1[nt][v] + (fold ? r2[nt][v] : 0.f);
+          const float term = dd * (1.0f - hv[nt][v] * hv[nt][v]) * wv[v];
+          s += (nt < ntt && n < Nreal) ? term : 0.f;
         }
       }
       s = row_sum16(s);
@@ -504,6 +574,19 @@ struct EpiEmb1Bwd {
     }
   }
 };
+
+// Stage the epilogue's column vectors for the block's column tiles into LDS:
+// cs[k][j] = col(k)[nt0 * 16 + j] for j < NT * 16 (zero past Npad or for a
+// null vector).  Called by every thread of the block, followed by a barrier.
+template <class Epi, int NT>
+__device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs) {
+  for (int idx = threadIdx.x; idx < Epi::kCols * NT * 16; idx += blockDim.x) {
+    const int k = idx / (NT * 16), j = idx % (NT * 16);
+    const int n = nt0 * 16 + j;
+    const float *p = e.col(k);
+    cs[idx] = (p != nullptr && n < npad) ? p[n] : 0.f;
+  }
+}
 
 template <class Epi, int MT>
 void dispatch_nt(const GemmArgs &a, const Epi &e, int nt, hipStream_t s) {
@@ -547,7 +630,7 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   if (gx < 8) gx = 8;
   if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
   if (gx <= 0) return;
-  const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4);
+  const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4 + Epi::kCols);
   hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi>), dim3(gx, gy), dim3(256), lds, s, a, e);
 }
 
