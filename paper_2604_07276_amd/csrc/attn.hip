@@ -720,12 +720,14 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
   __shared__ float Ts[4][128];
   __shared__ float dTs[4][128];
   __shared__ float part[16][16][4];
+  __shared__ float gam[128];  // gamma of the layer norm (ln_mode 0), zeros past M
   const int i = blockIdx.x;
   const int n = nnei[i];
   const int base = pair_off[i];
   const int tid = threadIdx.x;
   if (tid < 128) {
     for (int c = 0; c < 4; ++c) Ts[c][tid] = tid < M ? T[(size_t)i * 4 * M + c * M + tid] : 0.f;
+    gam[tid] = (ln_mode == 0 && tid < M) ? gamma[tid] : 0.f;
   }
   __syncthreads();
   const float *dr = dD + (size_t)i * ldd;
@@ -776,33 +778,42 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
   __syncthreads();
   const int grp = tid >> 4, li = tid & 15;
   const float invm = 1.0f / (float)M;
+  // Every global load of a pair is issued before any of its values is used
+  // and is unconditional: feature indices are clamped to the row (columns
+  // past M hold zeros), operands a mode does not use are read from G.
+  const float *xsrc = ln_mode == 0 ? xhat : G;
+  const float *tsrc = ln_mode == 1 ? temb : G;
   for (int j = grp; j < n; j += 16) {
     const size_t p = (size_t)(base + j);
-    const float *gp = geom + p * kGeom;
-    const float s = gp[G_S];
-    const float R0 = s, R1 = s * gp[G_RX], R2 = s * gp[G_RY], R3 = s * gp[G_RZ];
-    float dg[KF], xh[KF];
+    const float4 gq = *(const float4 *)(geom + p * kGeom);  // s, rx, ry, rz
+    float gm[KF], xv[KF], tv[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+      const int m = li + 16 * k;
+      const int mc = m < ldg ? m : 0;
+      gm[k] = G[p * ldg + mc];
+      xv[k] = xsrc[p * ldg + mc];
+      tv[k] = tsrc[p * ldg + mc];
+    }
+    const float rs = (ln_mode == 0 ? rstd : geom)[p];
+    const float R0 = gq.x, R1 = gq.x * gq.y, R2 = gq.x * gq.z, R3 = gq.x * gq.w;
+    float dg[KF];
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
       const int m = li + 16 * k;
-      dg[k] = 0.f;
-      xh[k] = 0.f;
-      if (m < M) {
-        const float gm = G[p * ldg + m];
-        const float v = R0 * dTs[0][m] + R1 * dTs[1][m] + R2 * dTs[2][m] + R3 * dTs[3][m];
-        dg[k] = v;
-        a0 += gm * dTs[0][m];
-        a1 += gm * dTs[1][m];
-        a2 += gm * dTs[2][m];
-        a3 += gm * dTs[3][m];
-        if (ln_mode == 0) {
-          xh[k] = xhat[p * ldg + m];
-          const float dx = gamma[m] * v;
-          s1 += dx;
-          s2 += dx * xh[k];
-        }
-      }
+      const int mc = m < 128 ? m : 0;
+      const bool in = m < M;
+      const float v = R0 * dTs[0][mc] + R1 * dTs[1][mc] + R2 * dTs[2][mc] + R3 * dTs[3][mc];
+      const float gmv = in ? gm[k] : 0.f;
+      dg[k] = in ? v : 0.f;
+      a0 += gmv * dTs[0][mc];
+      a1 += gmv * dTs[1][mc];
+      a2 += gmv * dTs[2][mc];
+      a3 += gmv * dTs[3][mc];
+      const float dx = gam[mc] * dg[k];
+      s1 += dx;
+      s2 += in ? dx * xv[k] : 0.f;
     }
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1) {
@@ -813,20 +824,14 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
       s1 += __shfl_xor(s1, off);
       s2 += __shfl_xor(s2, off);
     }
-    const float rs = ln_mode == 0 ? rstd[p] : 0.f;
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
       const int m = li + 16 * k;
       if (m < ldg) {
-        float nx = 0.f;
-        if (m < M) {
-          if (ln_mode == 0) {
-            nx = rs * (gamma[m] * dg[k] - s1 * invm - xh[k] * s2 * invm);
-          } else if (ln_mode == 1) {
-            const float t = temb[p * ldg + m];
-            nx = dg[k] * (1.0f - t * t);
-          }
-        }
+        const int mc = m < 128 ? m : 0;
+        const float ln = rs * (gam[mc] * dg[k] - s1 * invm - xv[k] * s2 * invm);
+        const float th = dg[k] * (1.0f - tv[k] * tv[k]);
+        const float nx = m < M ? (ln_mode == 0 ? ln : th) : 0.f;
         dG[p * ldg + m] = dg[k];
         if (ln_mode != 2) dnext[p * ldg + m] = nx;
       }

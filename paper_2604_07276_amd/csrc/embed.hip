@@ -48,17 +48,25 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
 }
 
 // value of the residual term for output column n: x[n] (identity), x[n mod fin]
-// (doubling) or 0, read from the wave's LDS copy of its rows.
+// (doubling) or 0, read from the wave's LDS copy of its rows.  The reads are
+// unconditional (in-row indices) and the mode picks with selects.
 __device__ __forceinline__ float res_fwd(const float *rowp, int mode, int fin, int n) {
-  if (mode == RES_IDENT) return rowp[n];
-  if (mode == RES_DOUBLE) return rowp[n % fin];
-  return 0.f;
+  const float v = rowp[mode == RES_DOUBLE ? n % fin : n];
+  return mode == RES_NONE ? 0.f : v;
 }
 // gradient flowing back through the residual into input column k
 __device__ __forceinline__ float res_bwd(const float *rowp, int mode, int fin, int fout, int k) {
-  if (mode == RES_IDENT) return rowp[k];
-  if (mode == RES_DOUBLE) return rowp[k] + (k + fin < fout ? rowp[k + fin] : 0.f);
-  return 0.f;
+  const bool two = mode == RES_DOUBLE && k + fin < fout;
+  const float v1 = rowp[k];
+  const float v2 = rowp[two ? k + fin : k];
+  return mode == RES_NONE ? 0.f : v1 + (two ? v2 : 0.f);
+}
+
+// Block-shared copies of the small per-column vectors (biases, ws): staged
+// once per block, so that no global load sits inside the per-element code.
+template <int N>
+__device__ __forceinline__ void stage_vec(const float *__restrict__ src, float *dst) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) dst[i] = src[i];
 }
 
 struct EmbArgs {
@@ -76,9 +84,13 @@ template <int C0, int C1, int C2>
 __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   __shared__ float xs[4][MT * 16][LD1 + 1];  // per wave: rows of h1 then h2
+  __shared__ float b2s[LD1], b3s[LD2];
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  stage_vec<LD1>(a.b2, b2s);
+  stage_vec<LD2>(a.b3, b3s);
+  __syncthreads();
   if (row0 >= P) return;
   const int r = lane & 15, g = lane >> 4;
   float(*xw)[LD1 + 1] = xs[wave];
@@ -89,12 +101,15 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
     const int row = row0 + mt * 16 + r;
     const int rr = row < P ? row : 0;
 #pragma unroll
-    for (int c = 0; c < C0; ++c) {
+    for (int c = 0; c < C0; ++c)
       x0[mt][c] = *(const floatx4 *)(a.h1 + (size_t)rr * LD0 + 16 * c + 4 * g);
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int c = 0; c < C0; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
-    }
-  }
   floatx4 acc1[MT][C1];
   layer<C0, C1>(a.W2t, r, g, x0, acc1);
   __builtin_amdgcn_wave_barrier();
@@ -106,10 +121,8 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int n = nt * 16 + 4 * g + v;
-        float h = 0.f;
-        if (n < a.n1)
-          h = tanhf(acc1[mt][nt][v] + a.b2[n]) + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
-        x1[mt][nt][v] = h;
+        const float h = tanhf(acc1[mt][nt][v] + b2s[n]) + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
+        x1[mt][nt][v] = n < a.n1 ? h : 0.f;
       }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -131,9 +144,8 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int n = nt * 16 + 4 * g + v;
-        o[v] = n < a.n2 ? tanhf(acc2[mt][nt][v] + a.b3[n]) +
-                              res_fwd(xw[mt * 16 + r], a.res3, a.n1, n)
-                        : 0.f;
+        const float h = tanhf(acc2[mt][nt][v] + b3s[n]) + res_fwd(xw[mt * 16 + r], a.res3, a.n1, n);
+        o[v] = n < a.n2 ? h : 0.f;
       }
       *(floatx4 *)(G0 + (size_t)row * LD2 + nt * 16 + 4 * g) = o;
     }
@@ -145,9 +157,14 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
                                                     float *__restrict__ gs) {
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   __shared__ float xs[4][MT * 16][LD2 + 1];  // per wave: h1, h2, dG0, dh2 rows in turn
+  __shared__ float b2s[LD1], b3s[LD2], wss[LD0];
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  stage_vec<LD1>(a.b2, b2s);
+  stage_vec<LD2>(a.b3, b3s);
+  stage_vec<LD0>(a.ws, wss);
+  __syncthreads();
   if (row0 >= P) return;
   const int r = lane & 15, g = lane >> 4;
   float(*xw)[LD2 + 1] = xs[wave];
@@ -159,12 +176,15 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
     const int row = row0 + mt * 16 + r;
     const int rr = row < P ? row : 0;
 #pragma unroll
-    for (int c = 0; c < C0; ++c) {
+    for (int c = 0; c < C0; ++c)
       x0[mt][c] = *(const floatx4 *)(a.h1 + (size_t)rr * LD0 + 16 * c + 4 * g);
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int c = 0; c < C0; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
-    }
-  }
   floatx4 t1[MT][C1], x1[MT][C1];
   {
     floatx4 acc1[MT][C1];
@@ -177,13 +197,10 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          float t = 0.f, h = 0.f;
-          if (n < a.n1) {
-            t = tanhf(acc1[mt][nt][v] + a.b2[n]);
-            h = t + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
-          }
-          t1[mt][nt][v] = t;
-          x1[mt][nt][v] = h;
+          const float t = tanhf(acc1[mt][nt][v] + b2s[n]);
+          const float h = t + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
+          t1[mt][nt][v] = n < a.n1 ? t : 0.f;
+          x1[mt][nt][v] = n < a.n1 ? h : 0.f;
         }
   }
   floatx4 d2[MT][C2];  // tanh output of layer 3, then dE/du3
@@ -197,7 +214,8 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          d2[mt][nt][v] = n < a.n2 ? tanhf(acc2[mt][nt][v] + a.b3[n]) : 0.f;
+          const float t = tanhf(acc2[mt][nt][v] + b3s[n]);
+          d2[mt][nt][v] = n < a.n2 ? t : 0.f;
         }
   }
   // ---- adjoint: du3 = dG0 (1 - t3^2); dG0 rows also go to LDS for the residual
@@ -206,14 +224,17 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   for (int mt = 0; mt < MT; ++mt) {
     const int row = row0 + mt * 16 + r;
     const int rr = row < P ? row : 0;
+    floatx4 gv[C2];  // all loads of the tile row before any use
+#pragma unroll
+    for (int nt = 0; nt < C2; ++nt)
+      gv[nt] = *(const floatx4 *)(dG0 + (size_t)rr * LD2 + nt * 16 + 4 * g);
 #pragma unroll
     for (int nt = 0; nt < C2; ++nt) {
-      const floatx4 gv = *(const floatx4 *)(dG0 + (size_t)rr * LD2 + nt * 16 + 4 * g);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        xw[mt * 16 + r][nt * 16 + 4 * g + v] = gv[v];
+        xw[mt * 16 + r][nt * 16 + 4 * g + v] = gv[nt][v];
         const float t = d2[mt][nt][v];
-        d2[mt][nt][v] = gv[v] * (1.0f - t * t);
+        d2[mt][nt][v] = gv[nt][v] * (1.0f - t * t);
       }
     }
   }
@@ -230,8 +251,8 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = nt * 16 + 4 * g + v;
-          float d = 0.f;
-          if (k < a.n1) d = acc[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res3, a.n1, a.n2, k);
+          const float dd = acc[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res3, a.n1, a.n2, k);
+          const float d = k < a.n1 ? dd : 0.f;
           acc[mt][nt][v] = d;  // dh2
           const float t = t1[mt][nt][v];
           du2[mt][nt][v] = d * (1.0f - t * t);
@@ -256,11 +277,10 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int k = nt * 16 + 4 * g + v;
-        if (k < a.n0) {
-          const float d = acc0[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res2, a.n0, a.n1, k);
-          const float h = x0[mt][nt][v];
-          s += d * (1.0f - h * h) * a.ws[k];
-        }
+        const float d = acc0[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res2, a.n0, a.n1, k);
+        const float h = x0[mt][nt][v];
+        const float term = d * (1.0f - h * h) * wss[k];
+        s += k < a.n0 ? term : 0.f;
       }
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
