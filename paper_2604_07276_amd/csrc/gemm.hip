@@ -43,14 +43,15 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
   const int nt0 = blockIdx.y * NT;
   stage_cols<Epi, NT>(epi, nt0, a.Npad, cs);
   __syncthreads();
-  if (row0 >= M) return;
   const int ntt = a.Npad / 16;
   const int r = lane & 15;
   const int g = lane >> 4;
+  // persistent over row tiles: the grid is sized to the resident capacity
+  // (launch gaps and the tail of short-lived waves otherwise cost ~40%)
+  for (int row0 = (blockIdx.x * 4 + wave) * 16 * MT; row0 < M; row0 += gridDim.x * 64 * MT) {
 
   floatx4 acc[MT][NT];
 #pragma unroll
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
     for (int nt = 0; nt < NT; ++nt) wv[nt] = wn[nt];
   }
   epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
+  }
 }
 
 // Persistent variant for the large pair-batched products whose weight tile
@@ -588,22 +590,54 @@ __device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs) {
   }
 }
 
+int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Grid of the streaming kernel: one block per 4*16*MT rows, capped at the
+// number of blocks the device holds at once (the kernel loops over tiles).
+template <int MT, int NT, class Epi>
+void launch_stream(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gemm<MT, NT, Epi>, 256, 0) !=
+            hipSuccess ||
+        nb <= 0)
+      nb = 2;
+    per_cu = nb;
+  }
+  const long tiles = (a.Mmax + 64 * MT - 1) / (64 * MT);
+  long cap = (long)per_cu * cu_count() / (long)gy;
+  if (cap < 1) cap = 1;
+  const unsigned gx = (unsigned)(tiles < cap ? tiles : cap);
+  if (gx == 0) return;
+  hipLaunchKernelGGL((k_gemm<MT, NT, Epi>), dim3(gx, gy), dim3(256), 0, s, a, e);
+}
+
 template <class Epi, int MT>
 void dispatch_nt(const GemmArgs &a, const Epi &e, int nt, hipStream_t s) {
   const int ntt = a.Npad / 16;
-  const unsigned gx = (unsigned)((a.Mmax + 64 * MT - 1) / (64 * MT));
   const unsigned gy = (unsigned)((ntt + nt - 1) / nt);
-  if (gx == 0) return;
-  dim3 grid(gx, gy), block(256);
   switch (nt) {
-    case 1: hipLaunchKernelGGL((k_gemm<MT, 1, Epi>), grid, block, 0, s, a, e); break;
-    case 2: hipLaunchKernelGGL((k_gemm<MT, 2, Epi>), grid, block, 0, s, a, e); break;
-    case 3: hipLaunchKernelGGL((k_gemm<MT, 3, Epi>), grid, block, 0, s, a, e); break;
-    case 4: hipLaunchKernelGGL((k_gemm<MT, 4, Epi>), grid, block, 0, s, a, e); break;
-    case 5: hipLaunchKernelGGL((k_gemm<MT, 5, Epi>), grid, block, 0, s, a, e); break;
-    case 6: hipLaunchKernelGGL((k_gemm<MT, 6, Epi>), grid, block, 0, s, a, e); break;
-    case 7: hipLaunchKernelGGL((k_gemm<MT, 7, Epi>), grid, block, 0, s, a, e); break;
-    default: hipLaunchKernelGGL((k_gemm<MT, 8, Epi>), grid, block, 0, s, a, e); break;
+    case 1: launch_stream<MT, 1>(a, e, gy, s); break;
+    case 2: launch_stream<MT, 2>(a, e, gy, s); break;
+    case 3: launch_stream<MT, 3>(a, e, gy, s); break;
+    case 4: launch_stream<MT, 4>(a, e, gy, s); break;
+    case 5: launch_stream<MT, 5>(a, e, gy, s); break;
+    case 6: launch_stream<MT, 6>(a, e, gy, s); break;
+    case 7: launch_stream<MT, 7>(a, e, gy, s); break;
+    default: launch_stream<MT, 8>(a, e, gy, s); break;
   }
 }
 
@@ -616,17 +650,7 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   // two workgroups per CU are resident (LDS and registers); the grid must not
   // exceed that, or the blocks past it start only when others have finished
   // their whole share and the launch takes twice as long
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        n > 0)
-      cus = n;
-    else
-      cus = 256;
-  }
-  int gx = 2 * cus / (int)gy / 8 * 8;
+  int gx = 2 * cu_count() / (int)gy / 8 * 8;
   if (gx < 8) gx = 8;
   if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
   if (gx <= 0) return;
