@@ -13,8 +13,11 @@ Prints one JSON line on stdout; a per-kernel table goes to stderr.
 """
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import tempfile
 import time
@@ -72,6 +75,34 @@ def flop_model(nnei: np.ndarray, shape) -> dict:
     return out
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_protein15668_fp32_step.md")
+
+
+def source_hash() -> str:
+    """Hash of the library sources; HBM counters are only valid for the build they came from."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_07276_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".cpp", ".h")):
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-kernel calibrated), or None if absent or taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"bench-traffic: kernel=(\S+) source=(\S+) fetch_bytes=(\d+) write_bytes=(\d+)",
+                  text)
+    if not m or m.group(1) != kernel or m.group(2) != source_hash():
+        return None
+    return int(m.group(3)), int(m.group(4))
+
+
 def cpu_baseline(weights_path, sysm, budget_s: float) -> dict:
     """The FP64 CPU oracle on a bounded sample of the same frame."""
     import torch
@@ -104,6 +135,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--host-api-steps", type=int, default=10,
+                    help="steps of the host-memory entry point to time (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (calibrates "
                          "hardware byte counters against a known transfer) and exit")
@@ -154,16 +187,17 @@ def main():
         step(k)
     model.sync()
     torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record(stream)
+    # one event per step boundary on the step's stream: total and per-step times
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
     for k in range(args.steps):
         step(k)
-    t_end.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     model.sync()
-    ms_total = t_start.elapsed_time(t_end)
+    ms_total = evs[0].elapsed_time(evs[-1])
     ms_step = ms_total / args.steps
+    per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
     value = n * args.steps / (ms_total / 1e3)
     E_last = float(e.cpu()[0])
     F_last = f.cpu().numpy()
@@ -202,14 +236,29 @@ def main():
         avg_s = ms / cnt * 1e-3
         per_launch = flops[dom][0] / flops[dom][1]
         achieved = per_launch / avg_s / 1e12
+        tr = measured_traffic(dom)
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+                    "traffic": None if tr is None else tr[0] + tr[1],
+                    "traffic_fetch_bytes": None if tr is None else tr[0],
+                    "traffic_write_bytes": None if tr is None else tr[1],
+                    "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if tr else None,
                     "avg_launch_ms": round(ms / cnt, 4),
                     "flop_per_launch": per_launch,
                     "step_algorithmic_tflop": round(step_flops / 1e12, 4),
                     "step_frac": round(step_flops / (ms_step * 1e-3) / 1e12
                                        / FP32_MFMA_PEAK_TFLOPS, 4)}
+
+    # host-memory entry point (PCIe copies included): context only, never `value`
+    host_ms = None
+    if args.host_api_steps > 0:
+        coords0 = frames[0]
+        model.compute(coords0, sysm.types, box, n, 0)
+        t0 = time.perf_counter()
+        for k in range(args.host_api_steps):
+            model.compute(frames[k % N_FRAMES], sysm.types, box, n, 0)
+        host_ms = (time.perf_counter() - t0) * 1e3 / args.host_api_steps
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -223,6 +272,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_p10_p50_p90": [round(float(np.percentile(per_step, q)), 4)
+                                    for q in (10, 50, 90)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -237,6 +288,7 @@ def main():
                    "precision": "fp32"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "host_api_ms_per_step": None if host_ms is None else round(host_ms, 3),
     }
     print(json.dumps(out), flush=True)
     model.close()
