@@ -127,6 +127,20 @@ int dp_forward_device(dp_model *m, const double *d_coords, const int32_t *d_type
 int dp_backward_device(dp_model *m, const double *d_atom_weight, double *d_grad_coords,
                        double *d_virial, void *hip_stream);
 
+/* Precision of the matrix-core products.  The paper's model runs in FP32
+ * only (Sec. IV-B); the BF16 mode is an extension of this library.
+ *   DP_PREC_FP32  FP32 operands (default).
+ *   DP_PREC_BF16  every product of the embedding net, the attention blocks
+ *                 (Q K^T, A V, projections and their adjoints) and the
+ *                 fitting net takes BF16 operands rounded to nearest even,
+ *                 with FP32 accumulation; geometry, switch, descriptor,
+ *                 softmax, layer norms and activations stay FP32, energy,
+ *                 force and virial reductions FP64.
+ * Applies to the steps enqueued after the call; waits for the handle's last
+ * step.  Returns DP_ERR_ARG for any other value. */
+enum dp_precision { DP_PREC_FP32 = 0, DP_PREC_BF16 = 1 };
+int dp_set_precision(dp_model *m, int precision);
+
 /* Wait for the handle's last step and return its device-side status. */
 int dp_sync(dp_model *m);
 

@@ -23,8 +23,10 @@ STATUS_NAMES = {
     -5: "DP_ERR_WEIGHTS", -6: "DP_ERR_DEVICE", -7: "DP_ERR_OOM",
 }
 EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
-            "dp_backward_device", "dp_sync", "dp_debug_nlist", "dp_set_timing", "dp_kernel_times",
-            "dp_model_info", "dp_destroy", "dp_last_error")
+            "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist", "dp_set_timing",
+            "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error")
+PREC_FP32 = 0
+PREC_BF16 = 1
 
 _lib = None
 
@@ -51,6 +53,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_compute_device.argtypes = [P, P, P, P, I, I, P, P, P, P, P]
     lib.dp_forward_device.argtypes = [P, P, P, P, I, I, P, P, P]
     lib.dp_backward_device.argtypes = [P, P, P, P, P]
+    lib.dp_set_precision.argtypes = [P, I]
     lib.dp_sync.argtypes = [P]
     lib.dp_debug_nlist.argtypes = [P, P, P]
     lib.dp_set_timing.argtypes = [P, I]
@@ -61,8 +64,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_last_error.argtypes = []
     lib.dp_last_error.restype = ctypes.c_char_p
     for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
-                 "dp_backward_device", "dp_sync", "dp_debug_nlist", "dp_set_timing",
-                 "dp_kernel_times", "dp_model_info"):
+                 "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist",
+                 "dp_set_timing", "dp_kernel_times", "dp_model_info"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -162,6 +165,11 @@ class Model:
         sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(_lib.dp_backward_device(self._h, _ptr(atom_weight), _ptr(grad_coords),
                                        _ptr(virial), sp))
+
+    def set_precision(self, precision: int):
+        """Operand precision of the matrix-core products (dp_set_precision):
+        PREC_FP32 (default) or PREC_BF16 (BF16 operands, FP32 accumulation)."""
+        _check(_lib.dp_set_precision(self._h, int(precision)))
 
     def sync(self):
         """Wait for the last step; raises on a device-side error (overflow, bad type)."""

@@ -37,6 +37,18 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 precision mode (template flag BF): one v_mfma_f32_16x16x16_bf16 per
+// 16x16 tile and four consecutive k values per lane, the same four values
+// the FP32 path feeds to four 16x16x4 steps; operands rounded to BF16 in
+// registers, accumulation in FP32.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x4 to_bf16(const floatx4 &v) {
+  return __builtin_convertvector(v, bf16x4);
+}
+__device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ float sum_groups(float v) {  // over lanes sharing lane%16
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
@@ -167,45 +179,58 @@ __device__ __forceinline__ void gate_store(float4 *kg, int tid, int n, const flo
 // acc[ft] += XT^T-tile x bt : contraction over the 16 rows of tile 'tile',
 // XT in LDS (feature-major), bt a 16x16 B operand held in registers.
 // Output lane layout: own row r, features 16 ft + 4 g + v.
-template <int NPAD>
+template <int NPAD, bool BF>
 __device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int g,
                                           const floatx4 &bt, floatx4 (&acc)[8]) {
   constexpr int LDT = NPAD + 4;
+  const bf16x4 btb = to_bf16(bt);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // two halves of the features: 16 operand registers
     floatx4 x[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
       x[f] = *(const floatx4 *)(XT + ((4 * h + f) * 16 + r) * LDT + tile * 16 + 4 * g);
+    if constexpr (BF) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma_bf16(to_bf16(x[f]), btb, acc[4 * h + f]);
+    } else {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+    }
   }
 }
 
 // The same contraction with the rows in row-major LDS (X[row][kLDR]): the A
 // operand is read with scalar LDS loads, four rows per lane group.
+template <bool BF>
 __device__ __forceinline__ void accum_rows(const float *X, int tile, int r, int g,
                                            const floatx4 &bt, floatx4 (&acc)[8]) {
   const float *xb = X + (tile * 16 + 4 * g) * kLDR + r;
+  const bf16x4 btb = to_bf16(bt);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    float x[4][4];
+    floatx4 x[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
       for (int t = 0; t < 4; ++t) x[f][t] = xb[t * kLDR + (4 * h + f) * 16];
+    if constexpr (BF) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma_bf16(to_bf16(x[f]), btb, acc[4 * h + f]);
+    } else {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+    }
   }
 }
 
 // st[kt] (lane: own row r, tile rows 4g + v) = X-rows of tile kt times the
 // wave's own 16 rows b, contracted over the 128 features; X row-major in LDS.
-template <int NT>
+template <int NT, bool BF>
 __device__ __forceinline__ void qk_lds(const float *X, int r, int g, const floatx4 (&b)[8],
                                        floatx4 (&st)[NT]) {
 #pragma unroll
@@ -220,10 +245,16 @@ __device__ __forceinline__ void qk_lds(const float *X, int r, int g, const float
 #pragma unroll
     for (int kt = 0; kt < NT; ++kt) a[kt] = *(const floatx4 *)(xb + kt * 16 * kLDR + 16 * c);
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (BF) {
+      const bf16x4 bb = to_bf16(b[c]);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma_bf16(to_bf16(a[kt]), bb, st[kt]);
+    } else {
 #pragma unroll
-      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma4(a[kt][t], b[c][t], st[kt]);
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) st[kt] = mfma4(a[kt][t], b[c][t], st[kt]);
+    }
   }
 }
 
@@ -257,7 +288,7 @@ constexpr int stage_floats() {
 
 constexpr int kLamLd = kAttnLamLd;
 
-template <int NPAD>
+template <int NPAD, bool BF>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) void k_attn_fwd(
     const float *__restrict__ qkv, const float *__restrict__ geom,
     const int *__restrict__ pair_off, const int *__restrict__ nnei,
@@ -295,7 +326,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
     floatx4 st[NT];
     float invz = 0.f;
     if (wave < ntile) {
-      qk_lds<NT>(buf, r, g, qv, st);
+      qk_lds<NT, BF>(buf, r, g, qv, st);
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) st[kt] *= inv_sqrt_d;
       if (qok) {
@@ -350,7 +381,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
           const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
           at[v] = st[kt][v] * invz * wq * gk.w * c;
         }
-        accum_lds<NPAD>(buf, kt, r, g, at, oacc);
+        accum_lds<NPAD, BF>(buf, kt, r, g, at, oacc);
       }
       if (qok) {
         float *op = out + (size_t)(base + q) * 128 + 4 * g;
@@ -377,7 +408,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
 // and dV from dO staged row-major, then dK (Q^T staged) and the key-side
 // sums; it adds both sides into dE/dsw and dE/drhat.
 
-template <int NPAD>
+template <int NPAD, bool BF>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_q(
     const float *__restrict__ qkv, const float *__restrict__ o, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
@@ -423,7 +454,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     stage_t_load<NPAD>(qkv + 128, ld, base, n, tid, kpre);
 
     floatx4 da[NT];
-    if (wave < ntile) qk_lds<NT>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
+    if (wave < ntile) qk_lds<NT, BF>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
     __syncthreads();
     stage_t_store<NPAD>(buf, tid, n, kpre);  // K^T
     __syncthreads();
@@ -467,7 +498,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           drqy += Y * gk.y;
           drqz += Y * gk.z;
         }
-        accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);
+        accum_lds<NPAD, BF>(buf, kt, r, g, ds, dqacc);
         lcur = lnxt;
       }
       dwq = sum_groups(dwq);
@@ -485,7 +516,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
   }
 }
 
-template <int NPAD>
+template <int NPAD, bool BF>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_k(
     const float *__restrict__ qkv, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
@@ -542,7 +573,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       float lcur[4], lnxt[4];
       lam_tile(0, lcur);
       floatx4 dk[NT];
-      qk_lds<NT>(buf, r, g, vreg, dk);  // dA: lane (key r, queries 4g + v)
+      qk_lds<NT, BF>(buf, r, g, vreg, dk);  // dA: lane (key r, queries 4g + v)
       floatx4 dvacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -576,7 +607,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           drky += Y * gq.y;
           drkz += Y * gq.z;
         }
-        accum_rows(buf, qt, r, g, at, dvacc);  // dV = A^T dO
+        accum_rows<BF>(buf, qt, r, g, at, dvacc);  // dV = A^T dO
 #pragma unroll
         for (int v = 0; v < 4; ++v) lcur[v] = lnxt[v];
         __builtin_amdgcn_sched_barrier(0);
@@ -602,7 +633,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int qt = 0; qt < NT; ++qt)
-        if (qt < ntile) accum_lds<NPAD>(buf, qt, r, g, ds[qt], dkacc);
+        if (qt < ntile) accum_lds<NPAD, BF>(buf, qt, r, g, ds[qt], dkacc);
       if (kok) {
         float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
 #pragma unroll
@@ -859,7 +890,7 @@ size_t bwdk_lds() {
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.
 constexpr int kMaxDevices = 64;
-int g_grid[kMaxDevices][3][4];
+int g_grid[kMaxDevices][6][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16
 
 int grid_for(int kind, int cls) {
   int dev = 0;
@@ -877,26 +908,29 @@ hipError_t occupancy_grid(K kernel, int threads, size_t lds, int cus, int *out) 
   return hipSuccess;
 }
 
-template <int NPAD>
+template <int NPAD, bool BF>
 hipError_t prepare_class(int dev, int cus, int cls) {
   const int th = NPAD / 16 * 64;
+  const int k0 = BF ? 3 : 0;  // grid table rows: fp32 fwd, bwd_q, bwd_k, then bf16
   hipError_t e = hipSuccess;
   if (NPAD > 64) {
-    e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD>,
+    e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD, BF>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<NPAD>());
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_attn_bwd_q<NPAD>,
+      e = hipFuncSetAttribute((const void *)k_attn_bwd_q<NPAD, BF>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdq_lds<NPAD>());
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void *)k_attn_bwd_k<NPAD>,
+      e = hipFuncSetAttribute((const void *)k_attn_bwd_k<NPAD, BF>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdk_lds<NPAD>());
   }
   if (e == hipSuccess)
-    e = occupancy_grid(k_attn_fwd<NPAD>, th, fwd_lds<NPAD>(), cus, &g_grid[dev][0][cls]);
+    e = occupancy_grid(k_attn_fwd<NPAD, BF>, th, fwd_lds<NPAD>(), cus, &g_grid[dev][k0][cls]);
   if (e == hipSuccess)
-    e = occupancy_grid(k_attn_bwd_q<NPAD>, th, bwdq_lds<NPAD>(), cus, &g_grid[dev][1][cls]);
+    e = occupancy_grid(k_attn_bwd_q<NPAD, BF>, th, bwdq_lds<NPAD>(), cus,
+                       &g_grid[dev][k0 + 1][cls]);
   if (e == hipSuccess)
-    e = occupancy_grid(k_attn_bwd_k<NPAD>, th, bwdk_lds<NPAD>(), cus, &g_grid[dev][2][cls]);
+    e = occupancy_grid(k_attn_bwd_k<NPAD, BF>, th, bwdk_lds<NPAD>(), cus,
+                       &g_grid[dev][k0 + 2][cls]);
   return e;
 }
 
@@ -912,10 +946,14 @@ hipError_t attn_prepare() {
   if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  if (e == hipSuccess) e = prepare_class<32>(dev, cus, 0);
-  if (e == hipSuccess) e = prepare_class<64>(dev, cus, 1);
-  if (e == hipSuccess) e = prepare_class<96>(dev, cus, 2);
-  if (e == hipSuccess) e = prepare_class<128>(dev, cus, 3);
+  if (e == hipSuccess) e = prepare_class<32, false>(dev, cus, 0);
+  if (e == hipSuccess) e = prepare_class<64, false>(dev, cus, 1);
+  if (e == hipSuccess) e = prepare_class<96, false>(dev, cus, 2);
+  if (e == hipSuccess) e = prepare_class<128, false>(dev, cus, 3);
+  if (e == hipSuccess) e = prepare_class<32, true>(dev, cus, 0);
+  if (e == hipSuccess) e = prepare_class<64, true>(dev, cus, 1);
+  if (e == hipSuccess) e = prepare_class<96, true>(dev, cus, 2);
+  if (e == hipSuccess) e = prepare_class<128, true>(dev, cus, 3);
   return e;
 }
 
@@ -925,20 +963,29 @@ void launch_attn_classes(const int *nnei, int nloc, int *ccount, int *clist, hip
                      ccount, clist);
 }
 
-#define ATTN_CLASS_SWITCH(cls, CALL) \
-  switch (cls) {                     \
-    case 0: { constexpr int NP = 32; CALL; } break;  \
-    case 1: { constexpr int NP = 64; CALL; } break;  \
-    case 2: { constexpr int NP = 96; CALL; } break;  \
-    default: { constexpr int NP = 128; CALL; } break; \
+// class (compile-time NP) and precision (compile-time BFV) dispatch
+#define ATTN_CLASS_SWITCH1(cls, ...)                           \
+  switch (cls) {                                               \
+    case 0: { constexpr int NP = 32; __VA_ARGS__; } break;     \
+    case 1: { constexpr int NP = 64; __VA_ARGS__; } break;     \
+    case 2: { constexpr int NP = 96; __VA_ARGS__; } break;     \
+    default: { constexpr int NP = 128; __VA_ARGS__; } break;   \
+  }
+#define ATTN_CLASS_SWITCH(cls, ...)                            \
+  if (a.bf16) {                                                \
+    constexpr bool BFV = true;                                 \
+    ATTN_CLASS_SWITCH1(cls, __VA_ARGS__)                       \
+  } else {                                                     \
+    constexpr bool BFV = false;                                \
+    ATTN_CLASS_SWITCH1(cls, __VA_ARGS__)                       \
   }
 
 void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *out, float *lam,
                            float *fstat, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(0, cls));
-  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL(k_attn_fwd<NP>, grid, dim3(NP / 16 * 64),
+  const dim3 grid(grid_for(a.bf16 ? 3 : 0, cls));
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_fwd<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             fwd_lds<NP>(), s, qkv, a.geom, a.pair_off, a.nnei,
                                             cl, cc, a.sel, a.shift, out, lam, (float2 *)fstat));
 }
@@ -948,8 +995,8 @@ void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const
                              float *astat, float *qside, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(1, cls));
-  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL(k_attn_bwd_q<NP>, grid, dim3(NP / 16 * 64),
+  const dim3 grid(grid_for(a.bf16 ? 4 : 1, cls));
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_bwd_q<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             bwdq_lds<NP>(), s, qkv, o, dO, a.geom, a.pair_off,
                                             a.nnei, cl, cc, a.sel, a.shift, lam,
                                             (const float2 *)fstat, dqkv, (float4 *)astat,
@@ -962,8 +1009,8 @@ void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const
                              hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(2, cls));
-  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL(k_attn_bwd_k<NP>, grid, dim3(NP / 16 * 64),
+  const dim3 grid(grid_for(a.bf16 ? 5 : 2, cls));
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_bwd_k<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             bwdk_lds<NP>(), s, qkv, dO, a.geom, a.pair_off,
                                             a.nnei, cl, cc, a.shift, lam, dqkv,
                                             (const float4 *)astat, (const float4 *)qside, gw, gr,

@@ -108,6 +108,7 @@ struct Timer {
 struct dp_model {
   // hyper-parameters
   int ntypes = 0, tebd = 0, axis = 0, n_attn = 0, dattn = 0, M = 0, sel = 0;
+  int bf16 = 0;  // precision of the matrix-core operands (dp_set_precision)
   std::vector<int> emb, fit;
   double rcut = 0, rcut_smth = 0, shift = 0, ln_eps = 0;
   int device = 0;
@@ -678,27 +679,27 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   if (emb_fused) {
     el = EmbLaunch{w.h[0], m->embl[1].Wt, m->embl[1].b, m->embl[2].Wt, m->embl[2].b,
                    m->embl[1].Wb, m->embl[2].Wb, m->ws, m->emb[0], m->emb[1], m->emb[2],
-                   m->embl[1].res, m->embl[2].res, Pptr, Pmax};
+                   m->embl[1].res, m->embl[2].res, Pptr, Pmax, m->bf16};
     RUN("emb_fwd", launch_emb_fwd(el, w.h[2], s));
   } else {
     for (int l = 1; l < ne; ++l) {
       const Linear &L = m->embl[l];
-      GemmArgs a{w.h[l - 1], L.ldin, L.Wt, L.ldin, L.ldout, L.fout, Pptr, Pmax};
+      GemmArgs a{w.h[l - 1], L.ldin, L.Wt, L.ldin, L.ldout, L.fout, Pptr, Pmax, m->bf16};
       RUN("emb_fwd", gemm_tanh_res(a, L.b, nullptr, 0, w.h[l - 1], L.ldin, L.res, L.fin, w.h[l],
                                    L.ldout, w.te[l], L.ldout, s));
     }
   }
   // attention layers
   const int D = m->dattn, ldM = m->ldM;
-  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift};
+  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift, m->bf16};
   for (int a = 0; a < na; ++a) {
     const auto &A = m->attn[a];
-    GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax};
+    GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16};
     RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnFwdName[cls],
           launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
-    GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax};
+    GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16};
     RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
                                     w.G[a + 1], w.xhat[a], w.rstd[a], s));
   }
@@ -707,13 +708,13 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
                                   m->axis, w.T, w.dmat, s));
   {
     const Linear &L = m->fitl[0];
-    GemmArgs a{w.dmat, m->ldD, L.Wt, m->ldD, L.ldout, L.fout, nullptr, nloc};
+    GemmArgs a{w.dmat, m->ldD, L.Wt, m->ldD, L.ldout, L.fout, nullptr, nloc, m->bf16};
     RUN("fit_fwd", gemm_tanh_res(a, m->fb0, d_types, L.ldout, nullptr, 0, RES_NONE, 0, w.z[0],
                                  L.ldout, w.tf[0], L.ldout, s));
   }
   for (int l = 1; l < nf; ++l) {
     const Linear &L = m->fitl[l];
-    GemmArgs a{w.z[l - 1], L.ldin, L.Wt, L.ldin, L.ldout, L.fout, nullptr, nloc};
+    GemmArgs a{w.z[l - 1], L.ldin, L.Wt, L.ldin, L.ldout, L.fout, nullptr, nloc, m->bf16};
     RUN("fit_fwd", gemm_tanh_res(a, L.b, nullptr, 0, w.z[l - 1], L.ldin, L.res, L.fin, w.z[l],
                                  L.ldout, w.tf[l], L.ldout, s));
   }
@@ -744,17 +745,17 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
   const int D = m->dattn, ldM = m->ldM;
-  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift};
+  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift, m->bf16};
   const bool emb_fused = ne == 3 && emb_fused_supported(m->lde[0], m->lde[1], m->lde[2]);
   EmbLaunch el{};
   if (emb_fused)
     el = EmbLaunch{w.h[0], m->embl[1].Wt, m->embl[1].b, m->embl[2].Wt, m->embl[2].b,
                    m->embl[1].Wb, m->embl[2].Wb, m->ws, m->emb[0], m->emb[1], m->emb[2],
-                   m->embl[1].res, m->embl[2].res, Pptr, Pmax};
+                   m->embl[1].res, m->embl[2].res, Pptr, Pmax, m->bf16};
   // fitting adjoint: fa[l] = dz_l * (1 - t_l^2) ; dz_{l-1} = fa[l] W_l^T + res^T(dz_l)
   for (int l = nf - 1; l >= 1; --l) {
     const Linear &L = m->fitl[l];
-    GemmArgs a{w.fa[l], L.ldout, L.Wb, L.ldout, L.ldin, L.fin, nullptr, nloc};
+    GemmArgs a{w.fa[l], L.ldout, L.Wb, L.ldout, L.ldin, L.fin, nullptr, nloc, m->bf16};
     int mode = RES_NONE;
     const float *res = nullptr;
     if (l == nf - 1) {
@@ -771,7 +772,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   }
   {
     const Linear &L = m->fitl[0];
-    GemmArgs a{w.fa[0], L.ldout, L.Wb, L.ldout, m->ldD, m->M * m->axis, nullptr, nloc};
+    GemmArgs a{w.fa[0], L.ldout, L.Wb, L.ldout, m->ldD, m->M * m->axis, nullptr, nloc, m->bf16};
     RUN("fit_bwd", gemm_linear(a, nullptr, w.dD, m->ldD, s));
   }
   // descriptor adjoint -> dG of the last layer, plus the next layer-norm / tanh seed
@@ -797,7 +798,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   }
   for (int a = na - 1; a >= 0; --a) {
     const auto &A = m->attn[a];
-    GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax};
+    GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnBwdQName[cls],
@@ -807,7 +808,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       RUN(kAttnBwdKName[cls],
           launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dqkv, w.astat, w.qside,
                                   w.gw, w.gr, a != na - 1, s));
-    GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax};
+    GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax, m->bf16};
     const int mode = a > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = a > 0 ? m->attn[a - 1].gamma : nullptr;
     const float *xh = a > 0 ? w.xhat[a - 1] : nullptr;
@@ -821,7 +822,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   w.dh[ne - 1] = dG_cur;
   for (int l = ne - 1; l >= 1 && !emb_fused; --l) {
     const Linear &L = m->embl[l];
-    GemmArgs a{w.du[l], L.ldout, L.Wb, L.ldout, L.ldin, L.fin, Pptr, Pmax};
+    GemmArgs a{w.du[l], L.ldout, L.Wb, L.ldout, L.ldin, L.fin, Pptr, Pmax, m->bf16};
     const int mode = L.res == RES_IDENT ? RES_IDENT : (L.res == RES_DOUBLE ? RES_FOLD : RES_NONE);
     if (l >= 2) {
       RUN("emb_bwd", gemm_bwd_tanh(a, w.dh[l], L.ldout, mode, L.fin, w.te[l - 1], L.ldin,
@@ -1101,6 +1102,16 @@ int dp_debug_nlist(dp_model *m, int32_t *nlist, int32_t *nnei) {
                       hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(nnei, m->w.nnei, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
   }
+  return DP_OK;
+}
+
+int dp_set_precision(dp_model *m, int precision) {
+  if (!m) return fail(DP_ERR_ARG, "model handle is NULL");
+  if (precision != DP_PREC_FP32 && precision != DP_PREC_BF16)
+    return fail(DP_ERR_ARG, "unknown precision %d", precision);
+  if (m->last) (void)hipStreamSynchronize(m->last);
+  m->bf16 = precision == DP_PREC_BF16;
+  m->fwd.valid = false;  // a pending adjoint must come from a forward in the new mode
   return DP_OK;
 }
 

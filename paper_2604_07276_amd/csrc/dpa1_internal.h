@@ -71,6 +71,7 @@ struct GemmArgs {
   int Nreal;
   const int *Mptr;
   int Mmax;       // grid sizing bound
+  int bf16;       // 1: BF16 matrix-core operands (FP32 accumulate), 0: FP32
 };
 
 enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_FOLD = 4 };
@@ -116,6 +117,7 @@ struct EmbLaunch {
   int res2, res3;         // residual rules (RES_NONE / RES_IDENT / RES_DOUBLE)
   const int *Pptr;        // number of pairs (device)
   int Pmax;
+  int bf16;               // 1: BF16 matrix-core operands (FP32 accumulate)
 };
 bool emb_fused_supported(int ld0, int ld1, int ld2);
 void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s);
@@ -143,6 +145,7 @@ struct AttnArgs {
   const int *pair_off, *nnei, *clist, *ccount;
   int nloc, sel;
   float shift;
+  int bf16;  // 1: BF16 matrix-core operands (FP32 accumulate)
 };
 // Forward: O = (P o H) V per centre; stores lam = QK^T/sqrt(d) per pair row
 // ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).

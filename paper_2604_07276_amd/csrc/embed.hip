@@ -24,8 +24,15 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 precision mode: one v_mfma_f32_16x16x16_bf16 per 16-wide k chunk
+// (four consecutive k per lane, as in the FP32 steps), FP32 accumulation.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x4 to_bf16(const floatx4 &v) {
+  return __builtin_convertvector(v, bf16x4);
+}
+
 // acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k]  (W row-major [NTILE*16][KCH*16])
-template <int KCH, int NTILE>
+template <int KCH, int NTILE, bool BF>
 __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
                                       const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
 #pragma unroll
@@ -38,12 +45,25 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt)
       w[nt] = *(const floatx4 *)(W + (size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * g);
+    if constexpr (BF) {
+      bf16x4 xb[MT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(x[mt][c]);
 #pragma unroll
-      for (int nt = 0; nt < NTILE; ++nt)
+      for (int nt = 0; nt < NTILE; ++nt) {
+        const bf16x4 wb = to_bf16(w[nt]);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(w[nt][t], x[mt][c][t], acc[mt][nt]);
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb, xb[mt], acc[mt][nt], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(w[nt][t], x[mt][c][t], acc[mt][nt]);
+    }
   }
 }
 
@@ -80,7 +100,7 @@ struct EmbArgs {
   const int *Pptr;
 };
 
-template <int C0, int C1, int C2>
+template <int C0, int C1, int C2, bool BF>
 __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   __shared__ float xs[4][MT * 16][LD1 + 1];  // per wave: rows of h1 then h2
@@ -111,7 +131,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
   floatx4 acc1[MT][C1];
-  layer<C0, C1>(a.W2t, r, g, x0, acc1);
+  layer<C0, C1, BF>(a.W2t, r, g, x0, acc1);
   __builtin_amdgcn_wave_barrier();
   floatx4 x1[MT][C1];
 #pragma unroll
@@ -132,7 +152,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
   floatx4 acc2[MT][C2];
-  layer<C1, C2>(a.W3t, r, g, x1, acc2);
+  layer<C1, C2, BF>(a.W3t, r, g, x1, acc2);
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
@@ -152,7 +172,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
   }
 }
 
-template <int C0, int C1, int C2>
+template <int C0, int C1, int C2, bool BF>
 __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__restrict__ dG0,
                                                     float *__restrict__ gs) {
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
@@ -188,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   floatx4 t1[MT][C1], x1[MT][C1];
   {
     floatx4 acc1[MT][C1];
-    layer<C0, C1>(a.W2t, r, g, x0, acc1);
+    layer<C0, C1, BF>(a.W2t, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -206,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   floatx4 d2[MT][C2];  // tanh output of layer 3, then dE/du3
   {
     floatx4 acc2[MT][C2];
-    layer<C1, C2>(a.W3t, r, g, x1, acc2);
+    layer<C1, C2, BF>(a.W3t, r, g, x1, acc2);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -243,7 +263,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   floatx4 du2[MT][C1];
   {
     floatx4 acc[MT][C1];
-    layer<C2, C1>(a.W3b, r, g, d2, acc);
+    layer<C2, C1, BF>(a.W3b, r, g, d2, acc);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -268,7 +288,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   }
   // dh1 = du2 W2^T + res^T(dh2) ; du1 = dh1 (1 - h1^2) ; gs = du1 . ws
   floatx4 acc0[MT][C0];
-  layer<C1, C0>(a.W2b, r, g, du2, acc0);
+  layer<C1, C0, BF>(a.W2b, r, g, du2, acc0);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     float s = 0.f;
@@ -309,7 +329,10 @@ void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
             e.Pptr};
   const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_emb_fwd<2, 4, 7>), dim3(blocks), dim3(256), 0, s, a, G0);
+  if (e.bf16)
+    hipLaunchKernelGGL((k_emb_fwd<2, 4, 7, true>), dim3(blocks), dim3(256), 0, s, a, G0);
+  else
+    hipLaunchKernelGGL((k_emb_fwd<2, 4, 7, false>), dim3(blocks), dim3(256), 0, s, a, G0);
 }
 
 void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t s) {
@@ -317,7 +340,10 @@ void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t
             e.Pptr};
   const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_emb_bwd<2, 4, 7>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+  if (e.bf16)
+    hipLaunchKernelGGL((k_emb_bwd<2, 4, 7, true>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+  else
+    hipLaunchKernelGGL((k_emb_bwd<2, 4, 7, false>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
 }
 
 }  // namespace dpa1

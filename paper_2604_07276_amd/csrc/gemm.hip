@@ -27,6 +27,19 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 precision mode: one v_mfma_f32_16x16x16_bf16 takes a whole 16-wide k
+// chunk (lane l holds k = 4 (l / 16) + 0..3 of row l % 16, the same
+// four consecutive values the FP32 path feeds to four 16x16x4 steps);
+// operands are rounded to BF16 (nearest even) in registers, accumulation
+// stays FP32.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x4 to_bf16(const floatx4 &v) {
+  return __builtin_convertvector(v, bf16x4);
+}
+__device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ float row_sum16(float v) {
   // sum over the four lane groups that share (lane % 16)
   v += __shfl_xor(v, 16);
@@ -37,7 +50,7 @@ __device__ __forceinline__ float row_sum16(float v) {
 template <class Epi, int NT>
 __device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs);
 
-template <int MT, int NT, class Epi>
+template <int MT, int NT, class Epi, bool BF>
 __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   __shared__ float cs[Epi::kCols * NT * 16];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
@@ -47,11 +60,15 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
   stage_cols<Epi, NT>(epi, nt0, a.Npad, cs);
   __syncthreads();
   const int ntt = a.Npad / 16;
-  const int r = lane & 15;
-  const int g = lane >> 4;
   // persistent over row tiles: the grid is sized to the resident capacity
   // (launch gaps and the tail of short-lived waves otherwise cost ~40%)
   for (int row0 = (blockIdx.x * 4 + wave) * 16 * MT; row0 < M; row0 += gridDim.x * 64 * MT) {
+  // per-lane offsets are recomputed in every iteration from an index the
+  // optimiser cannot see through, instead of being held across the loop
+  int lane_it = lane;
+  asm volatile("" : "+v"(lane_it));
+  const int r = lane_it & 15;
+  const int g = lane_it >> 4;
 
   floatx4 acc[MT][NT];
 #pragma unroll
@@ -94,12 +111,24 @@ __global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
     __builtin_amdgcn_sched_barrier(0);
     // Tiles past the last column tile (nt0 + nt >= ntt) multiply a duplicate of
     // tile 0 and are never stored: no branch inside the MFMA sequence.
+    if constexpr (BF) {
+      bf16x4 xb[MT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(xv[mt]);
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x4 wb = to_bf16(wv[nt]);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
+        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(wb, xb[mt], acc[mt][nt]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
 #pragma unroll
@@ -131,7 +160,7 @@ __device__ __forceinline__ void load_x_tile(const GemmArgs &a, int row0, int M, 
   }
 }
 
-template <int MT, int NT, int KCH, class Epi>
+template <int MT, int NT, int KCH, class Epi, bool BF>
 __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   constexpr int K = KCH * 16;
   constexpr int LDW = K + 4;
@@ -174,13 +203,25 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * LDW + 16 * c);
       __builtin_amdgcn_sched_barrier(0);  // one chunk of weights live at a time
+      if constexpr (BF) {
+        bf16x4 xb[MT];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+        for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(xr[mt][c]);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf16x4 wb = to_bf16(w[nt]);
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            acc[mt][nt] = mfma4(w[nt][t], xr[mt][c][t], acc[mt][nt]);
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(wb, xb[mt], acc[mt][nt]);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+              acc[mt][nt] = mfma4(w[nt][t], xr[mt][c][t], acc[mt][nt]);
+      }
     }
     if constexpr (Epi::kLds == 2)
       if (row0 + stride < M) load_x_tile<MT, KCH>(a, row0 + stride, M, r, g, xn);
@@ -259,16 +300,12 @@ struct EpiTanhRes {
   __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
                                         int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
-    const bool dbl = res_mode == RES_DOUBLE;
-    const float *rp = (res_mode == RES_IDENT || dbl) ? res : g_zeros;
-    const int rld = (res_mode == RES_IDENT || dbl) ? ldr : 0;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
       const bool ok = row < M;
       const size_t rr = (size_t)(ok ? row : 0);
-      floatx4 bl[NT];
-      float rv[NT][4];
+      floatx4 bl[NT], rv[NT];
       if (row_type) {
         const float *bp = bias + (size_t)row_type[rr] * bias_ld;
 #pragma unroll
@@ -280,14 +317,26 @@ struct EpiTanhRes {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) bl[nt] = *(const floatx4 *)(cs + nt * 16 + 4 * g);
       }
+      // residual: 16-byte loads for the identity rule, scalar ones for the
+      // doubling rule (uniform branch; every load is issued before any use)
+      if (res_mode == RES_IDENT) {
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int n = (nt0 + nt) * 16 + 4 * g + v;
-          const int nn = n < Nreal ? n : 0;
-          rv[nt][v] = rp[rr * rld + (dbl ? nn % res_fin : nn)];
+        for (int nt = 0; nt < NT; ++nt) {
+          const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+          rv[nt] = *(const floatx4 *)(res + rr * ldr + tile * 16 + 4 * g);
         }
+      } else if (res_mode == RES_DOUBLE) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = (nt0 + nt) * 16 + 4 * g + v;
+            rv[nt][v] = res[rr * ldr + (n < Nreal ? n : 0) % res_fin];
+          }
+      } else {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) rv[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
       if (!ok) continue;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -409,28 +458,37 @@ struct EpiBwdTanh {
   __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
                                         int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
-    const bool rowres = res_mode == RES_IDENT || res_mode == RES_FOLD;
-    const float *rp = rowres ? res : g_zeros;
-    const int rld = rowres ? ldr : 0;
-    const int fold = res_mode == RES_FOLD ? res_fin : 0;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
       const bool ok = row < M;
       const size_t rr = (size_t)(ok ? row : 0);
-      floatx4 tt[NT];
-      float r1[NT][4], r2[NT][4];
+      floatx4 tt[NT], rv[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
         tt[nt] = *(const floatx4 *)(t + rr * ldt + tile * 16 + 4 * g);
+      }
+      // row residual gradient: 16-byte loads for the identity rule, scalar
+      // pairs for the folded doubling rule (uniform branch)
+      if (res_mode == RES_IDENT) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int n = tile * 16 + 4 * g + v;
-          const int nn = n < Nreal ? n : 0;
-          r1[nt][v] = rp[rr * rld + nn];
-          r2[nt][v] = rp[rr * rld + nn + fold];  // = r1 unless folding; masked at use
+        for (int nt = 0; nt < NT; ++nt) {
+          const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+          rv[nt] = *(const floatx4 *)(res + rr * ldr + tile * 16 + 4 * g);
         }
+      } else if (res_mode == RES_FOLD) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = (nt0 + nt) * 16 + 4 * g + v;
+            const int nn = n < Nreal ? n : 0;
+            rv[nt][v] = res[rr * ldr + nn] + res[rr * ldr + nn + res_fin];
+          }
+      } else {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) rv[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
       if (!ok) continue;
 #pragma unroll
@@ -442,7 +500,7 @@ struct EpiBwdTanh {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const bool in = n0 + v < Nreal;
-          const float x = acc[mt][nt][v] + r1[nt][v] + (fold ? r2[nt][v] : 0.f) + bc[v];
+          const float x = acc[mt][nt][v] + rv[nt][v] + bc[v];
           dv[v] = in ? x : 0.f;
           av[v] = in ? x * (1.0f - tt[nt][v] * tt[nt][v]) : 0.f;
         }
@@ -606,12 +664,12 @@ int cu_count() {
 
 // Grid of the streaming kernel: one block per 4*16*MT rows, capped at the
 // number of blocks the device holds at once (the kernel loops over tiles).
-template <int MT, int NT, class Epi>
-void launch_stream(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) {
+template <int MT, int NT, class Epi, bool BF>
+void launch_stream_p(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gemm<MT, NT, Epi>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gemm<MT, NT, Epi, BF>, 256, 0) !=
             hipSuccess ||
         nb <= 0)
       nb = 2;
@@ -622,7 +680,12 @@ void launch_stream(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) 
   if (cap < 1) cap = 1;
   const unsigned gx = (unsigned)(tiles < cap ? tiles : cap);
   if (gx == 0) return;
-  hipLaunchKernelGGL((k_gemm<MT, NT, Epi>), dim3(gx, gy), dim3(256), 0, s, a, e);
+  hipLaunchKernelGGL((k_gemm<MT, NT, Epi, BF>), dim3(gx, gy), dim3(256), 0, s, a, e);
+}
+template <int MT, int NT, class Epi>
+void launch_stream(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) {
+  if (a.bf16) launch_stream_p<MT, NT, Epi, true>(a, e, gy, s);
+  else launch_stream_p<MT, NT, Epi, false>(a, e, gy, s);
 }
 
 template <class Epi, int MT>
@@ -655,7 +718,10 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
   if (gx <= 0) return;
   const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4 + Epi::kCols);
-  hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi>), dim3(gx, gy), dim3(256), lds, s, a, e);
+  if (a.bf16)
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, true>), dim3(gx, gy), dim3(256), lds, s, a, e);
+  else
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, false>), dim3(gx, gy), dim3(256), lds, s, a, e);
 }
 
 // Rows per wave: two 16-row tiles for the large pair-batched products,

@@ -59,6 +59,7 @@ def test_calls_with_null_handle_fail_cleanly():
     lib = binding.load_library()
     assert lib.dp_compute(None, None, None, None, 0, 0, None, None, None, None) == -1
     assert lib.dp_sync(None) == -1
+    assert lib.dp_set_precision(None, 0) == -1
     assert lib.dp_debug_nlist(None, None, None) == -1
     lib.dp_destroy(None)
 
