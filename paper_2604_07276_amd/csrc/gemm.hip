@@ -51,7 +51,7 @@ template <class Epi, int NT>
 __device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs);
 
 template <int MT, int NT, class Epi, bool BF>
-__global__ __launch_bounds__(256, 3) void k_gemm(GemmArgs a, Epi epi) {
+__global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi epi) {
   __shared__ float cs[Epi::kCols * NT * 16];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
   const int wave = threadIdx.x >> 6;
@@ -739,7 +739,10 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
       return launch_lds<Epi, 8, 8>(a, e, s);
     }
   }
-  if (a.Mmax >= 65536) dispatch_nt<Epi, 2>(a, e, nt, s);
+  // the long-K adjoint of the QKV projection: 64-row tiles halve the weight
+  // reads per row (two waves per SIMD, 238 registers, no spills)
+  if (a.Mmax >= 65536 && full_rows && Epi::kLds == 0 && a.K >= 256) dispatch_nt<Epi, 4>(a, e, nt, s);
+  else if (a.Mmax >= 65536) dispatch_nt<Epi, 2>(a, e, nt, s);
   else dispatch_nt<Epi, 1>(a, e, nt, s);
 }
 

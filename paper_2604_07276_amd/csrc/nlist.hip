@@ -214,51 +214,67 @@ __global__ __launch_bounds__(kWave *kNlistWaves) void k_nlist(
 }
 
 // One thread per (centre, slot).  Geometry in FP64, stored as FP32.
-__global__ void k_env_embed1(const double *__restrict__ x, const int32_t *__restrict__ types,
-                             CellGrid g, int nloc, int sel, double rcut, double rs,
-                             const int *__restrict__ nlist, const int *__restrict__ nnei,
-                             const int *__restrict__ pair_off,
-                             const float *__restrict__ type_table,
-                             const float *__restrict__ ws, int ntypes, int n1, int ld1,
-                             float *__restrict__ geom, float *__restrict__ h1) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)nloc * sel) return;
-  const int i = (int)(t / sel);
-  const int s = (int)(t % sel);
-  if (s >= nnei[i]) return;
-  const int j = nlist[(size_t)i * sel + s];
-  const int p = pair_off[i] + s;
-  double d[3];
-  pair_vec(x, i, j, g, d);
-  const double r = sqrt(norm2(d));
-  double sw, dsw;
-  if (r < rs) {
-    sw = 1.0;
-    dsw = 0.0;
-  } else if (r < rcut) {
-    const double inv = 1.0 / (rcut - rs);
-    const double u = (r - rs) * inv;
-    // sw = u^3 (-6u^2 + 15u - 10) + 1 ; dsw/dr = -30 u^2 (u - 1)^2 / (rcut - rs)
-    sw = u * u * u * (-6.0 * u * u + 15.0 * u - 10.0) + 1.0;
-    dsw = -30.0 * u * u * (u - 1.0) * (u - 1.0) * inv;
-  } else {
-    sw = 0.0;
-    dsw = 0.0;
+// One wavefront per centre: lane l handles slots l, l + 64 of the centre's
+// list, so the pair records (contiguous per centre) are written by
+// consecutive lanes, and each lane writes its h1 row with 16-byte stores.
+// The type-pair table and ws are staged in LDS once per block (when they
+// fit), so no global load sits inside the per-element loop.
+constexpr int kEnvWaves = 4;
+constexpr int kEnvTable = 8192;  // floats of type table staged in LDS
+
+__global__ __launch_bounds__(kEnvWaves * 64) void k_env_embed1(
+    const double *__restrict__ x, const int32_t *__restrict__ types, CellGrid g, int nloc,
+    int sel, double rcut, double rs, const int *__restrict__ nlist, const int *__restrict__ nnei,
+    const int *__restrict__ pair_off, const float *__restrict__ type_table,
+    const float *__restrict__ ws, int ntypes, int n1, int ld1, float *__restrict__ geom,
+    float *__restrict__ h1) {
+  __shared__ float tab_s[kEnvTable];
+  __shared__ float ws_s[128];
+  const int tsize = ntypes * ntypes * ld1;
+  const bool staged = tsize <= kEnvTable && ld1 <= 128;
+  if (staged) {
+    for (int k = threadIdx.x; k < tsize; k += blockDim.x) tab_s[k] = type_table[k];
+    for (int k = threadIdx.x; k < ld1; k += blockDim.x) ws_s[k] = ws[k];
   }
-  const double sv = sw / r;
-  float *gp = geom + (size_t)p * kGeom;
-  gp[G_S] = (float)sv;
-  gp[G_RX] = (float)(d[0] / r);
-  gp[G_RY] = (float)(d[1] / r);
-  gp[G_RZ] = (float)(d[2] / r);
-  gp[G_SW] = (float)sw;
-  gp[G_R] = (float)r;
-  gp[G_DSW] = (float)dsw;
-  gp[7] = 0.0f;
-  const float s32 = (float)sv;
-  const float *tt = type_table + ((size_t)types[j] * ntypes + types[i]) * ld1;
-  float *hp = h1 + (size_t)p * ld1;
-  for (int o = 0; o < ld1; ++o) hp[o] = o < n1 ? tanhf(tt[o] + ws[o] * s32) : 0.0f;
+  __syncthreads();
+  const float *tab = staged ? tab_s : type_table;
+  const float *wsv = staged ? ws_s : ws;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kEnvWaves + wave;
+  if (i >= nloc) return;
+  const int n = nnei[i];
+  const int base = pair_off[i];
+  const int ti = types[i];
+  const double inv = 1.0 / (rcut - rs);
+  for (int sl = lane; sl < n; sl += 64) {
+    const int j = nlist[(size_t)i * sel + sl];
+    const int tj = types[j];
+    const int p = base + sl;
+    double d[3];
+    pair_vec(x, i, j, g, d);
+    const double r = sqrt(norm2(d));
+    // sw = u^3 (-6u^2 + 15u - 10) + 1 on [rs, rcut); dsw/dr = -30 u^2 (u - 1)^2 / (rcut - rs)
+    const double u = (r - rs) * inv;
+    const double swm = u * u * u * (-6.0 * u * u + 15.0 * u - 10.0) + 1.0;
+    const double dswm = -30.0 * u * u * (u - 1.0) * (u - 1.0) * inv;
+    const double sw = r < rs ? 1.0 : (r < rcut ? swm : 0.0);
+    const double dsw = (r < rs || r >= rcut) ? 0.0 : dswm;
+    const double sv = sw / r;
+    float4 *gp = (float4 *)(geom + (size_t)p * kGeom);
+    gp[0] = make_float4((float)sv, (float)(d[0] / r), (float)(d[1] / r), (float)(d[2] / r));
+    gp[1] = make_float4((float)sw, (float)r, (float)dsw, 0.0f);
+    const float s32 = (float)sv;
+    const float *tt = tab + ((size_t)tj * ntypes + ti) * ld1;
+    float4 *hp = (float4 *)(h1 + (size_t)p * ld1);
+    for (int o = 0; o < ld1; o += 4) {
+      float4 v;
+      v.x = o + 0 < n1 ? tanhf(tt[o + 0] + wsv[o + 0] * s32) : 0.0f;
+      v.y = o + 1 < n1 ? tanhf(tt[o + 1] + wsv[o + 1] * s32) : 0.0f;
+      v.z = o + 2 < n1 ? tanhf(tt[o + 2] + wsv[o + 2] * s32) : 0.0f;
+      v.w = o + 3 < n1 ? tanhf(tt[o + 3] + wsv[o + 3] * s32) : 0.0f;
+      hp[o >> 2] = v;
+    }
+  }
 }
 
 }  // namespace
@@ -304,7 +320,7 @@ void launch_env_embed1(const double *coords, const int32_t *types, CellGrid grid
                        const int *pair_off, const float *type_table, const float *ws, int ntypes,
                        int n1, int ld1, float *geom, float *h1, hipStream_t s) {
   if (nloc <= 0) return;
-  hipLaunchKernelGGL(k_env_embed1, dim3(nblk((long)nloc * sel, 256)), dim3(256), 0, s, coords,
+  hipLaunchKernelGGL(k_env_embed1, dim3(nblk(nloc, kEnvWaves)), dim3(kEnvWaves * 64), 0, s, coords,
                      types, grid, nloc, sel, rcut, rcut_smth, nlist, nnei, pair_off, type_table,
                      ws, ntypes, n1, ld1, geom, h1);
 }
