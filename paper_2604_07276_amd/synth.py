@@ -73,6 +73,10 @@ class ModelShape:
     ln_eps: float = 1e-5
 
 
+# Distilled student (DP-SE-style: no attention), 86,318 parameters with 5 types.
+STUDENT_SHAPE = ModelShape(emb=(16, 32, 64), axis=8, n_attn=0, fit=(128, 128))
+
+
 def _streams(seed: int):
     """Four independent PCG64 streams: geometry, types, weights, perturbation."""
     ss = np.random.SeedSequence(seed).spawn(4)
@@ -226,6 +230,17 @@ def perturbed_frames(base: System, n_frames: int, sigma: float = 0.01) -> np.nda
             x = np.mod(x + rng.normal(0.0, sigma, size=x.shape), L)
         out[f] = x
     return out
+
+
+def noisy_frame(base: System, index: int, sigma: float = 0.05) -> np.ndarray:
+    """Frame ``index`` of an independent-noise ensemble: base positions plus
+    N(0, sigma^2) per component, wrapped into the box.  Each frame has its own
+    seeded stream, so any subset can be drawn in any order."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([base.seed, 7, index])))
+    x = base.coords + rng.normal(0.0, sigma, size=base.coords.shape)
+    if base.box is not None:
+        x = np.mod(x, np.diag(base.box))
+    return x
 
 
 def slab_partition(coords: np.ndarray, box_len: float, n_slabs: int, index: int,
