@@ -124,7 +124,7 @@ def loss_and_grad(model: OracleModel, frames, types, box, e_label, f_label, rcut
 def loss_value(model: OracleModel, frames, types, box, e_label, f_label, rcut: float, sel: int,
                pref_e: float, pref_f: float) -> float:
     L, _, _ = batch_loss(model, frames, types, box, e_label, f_label, rcut, sel, pref_e, pref_f)
-    return float(L)
+    return float(L.detach())
 
 
 def labels(model: OracleModel, frames, types, box, rcut: float, sel: int):

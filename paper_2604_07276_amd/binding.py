@@ -24,11 +24,21 @@ STATUS_NAMES = {
 }
 EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
             "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist", "dp_set_timing",
-            "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error")
+            "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error",
+            # student trainer (include/dpa1_train.h)
+            "dp_train_create", "dp_train_gradient", "dp_train_step", "dp_train_params",
+            "dp_train_save", "dp_train_destroy", "dp_force_error")
 PREC_FP32 = 0
 PREC_BF16 = 1
 
 _lib = None
+
+
+class TrainOptions(ctypes.Structure):
+    """dp_train_options of include/dpa1_train.h."""
+    _fields_ = [("pref_e", ctypes.c_double), ("pref_f", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("precision", ctypes.c_int)]
 
 
 class DPError(RuntimeError):
@@ -63,9 +73,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_destroy.restype = None
     lib.dp_last_error.argtypes = []
     lib.dp_last_error.restype = ctypes.c_char_p
+    lib.dp_train_create.argtypes = [ctypes.c_char_p, D, I, ctypes.POINTER(TrainOptions),
+                                    ctypes.POINTER(P)]
+    lib.dp_train_gradient.argtypes = [P, P, P, P, I, I, P, P, P, P, P]
+    lib.dp_train_step.argtypes = [P, P, P, P, I, I, P, P, D, P, P]
+    lib.dp_train_params.argtypes = [P, P, P]
+    lib.dp_train_save.argtypes = [P, ctypes.c_char_p]
+    lib.dp_train_destroy.argtypes = [P]
+    lib.dp_train_destroy.restype = None
+    lib.dp_force_error.argtypes = [P, P, I, P, P]
     for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
                  "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist",
-                 "dp_set_timing", "dp_kernel_times", "dp_model_info"):
+                 "dp_set_timing", "dp_kernel_times", "dp_model_info", "dp_train_create",
+                 "dp_train_gradient", "dp_train_step", "dp_train_params", "dp_train_save",
+                 "dp_force_error"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -195,3 +216,81 @@ class Model:
             nm = names.raw[48 * k:48 * (k + 1)].split(b"\0", 1)[0].decode()
             out[nm] = (int(counts[k]), float(ms[k]))
         return out
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+class Trainer:
+    """Student trainer (include/dpa1_train.h): exact energy+force loss gradient and Adam.
+
+    frames (float64 [B, N, 3]), types (int32 [N]), e_label (float64 [B]) and
+    f_label (float64 [B, N, 3]) are torch CUDA tensors; box is host data or None.
+    """
+
+    def __init__(self, weights_path: str, rcut: float, sel: int, pref_e: float = 1.0,
+                 pref_f: float = 100.0, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, precision: int = PREC_FP32):
+        lib = load_library()
+        opt = TrainOptions(pref_e, pref_f, beta1, beta2, eps, precision)
+        h = ctypes.c_void_p()
+        _check(lib.dp_train_create(weights_path.encode(), float(rcut), int(sel), ctypes.byref(opt),
+                                   ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int32()
+        _check(lib.dp_train_params(h, None, ctypes.byref(n)))
+        self.nparams = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dp_train_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gradient(self, frames, types, box, e_label, f_label, stream=None):
+        """(loss [3] = (L, L_e, L_f), grad [nparams] FP64 in weights-file order)."""
+        B, N = int(frames.shape[0]), int(frames.shape[1])
+        boxa = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        loss = np.zeros(3)
+        grad = np.zeros(self.nparams)
+        _check(_lib.dp_train_gradient(self._h, _ptr(frames), _ptr(types), _ptr(boxa), N, B,
+                                      _ptr(e_label), _ptr(f_label), loss.ctypes.data,
+                                      grad.ctypes.data, _stream_ptr(stream)))
+        return loss, grad
+
+    def step(self, frames, types, box, e_label, f_label, lr: float, stream=None):
+        """One Adam step; returns the loss [3] of the batch before the update."""
+        B, N = int(frames.shape[0]), int(frames.shape[1])
+        boxa = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
+        loss = np.zeros(3)
+        _check(_lib.dp_train_step(self._h, _ptr(frames), _ptr(types), _ptr(boxa), N, B,
+                                  _ptr(e_label), _ptr(f_label), float(lr), loss.ctypes.data,
+                                  _stream_ptr(stream)))
+        return loss
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.nparams)
+        n = ctypes.c_int32()
+        _check(_lib.dp_train_params(self._h, out.ctypes.data, ctypes.byref(n)))
+        return out
+
+    def save(self, path: str):
+        _check(_lib.dp_train_save(self._h, path.encode()))
+
+
+def force_error(a, b, stream=None):
+    """(RMSE, max abs error) between two [N, 3] float64 device force arrays (dp_force_error)."""
+    load_library()
+    out = np.zeros(2)
+    _check(_lib.dp_force_error(_ptr(a), _ptr(b), int(a.shape[0]), out.ctypes.data,
+                               _stream_ptr(stream)))
+    return float(out[0]), float(out[1])

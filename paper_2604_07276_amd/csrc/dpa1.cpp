@@ -23,14 +23,15 @@
 
 #include "dpa1.h"
 #include "dpa1_internal.h"
+#include "dpa1_model.h"
 
 using namespace dpa1;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const char *fmt, ...) {
+int dpa1::fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -39,140 +40,6 @@ int fail(int code, const char *fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return fail(e_ == hipErrorOutOfMemory ? DP_ERR_OOM : DP_ERR_DEVICE, "%s: %s (%s)", \
-                  #expr, hipGetErrorString(e_), __func__);                                 \
-  } while (0)
-
-struct Linear {  // one dense layer, FP32, padded
-  int fin = 0, fout = 0, ldin = 0, ldout = 0;
-  int res = RES_NONE;  // residual rule of the forward layer
-  float *Wt = nullptr;  // [ldout][ldin]  (forward operand)
-  float *Wb = nullptr;  // [ldin][ldout]  (backward operand)
-  float *b = nullptr;   // [ldout]
-};
-
-int residual_rule(int fin, int fout) {
-  if (fout == fin) return RES_IDENT;
-  if (fout == 2 * fin) return RES_DOUBLE;
-  return RES_NONE;
-}
-
-struct Timer {
-  bool enabled = false;
-  struct Pending {
-    std::string name;
-    hipEvent_t a, b;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> pool;
-  std::map<std::string, std::pair<int64_t, double>> totals;
-  hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-  void collect() {
-    for (auto &p : pending) {
-      float ms = 0.f;
-      (void)hipEventSynchronize(p.b);
-      (void)hipEventElapsedTime(&ms, p.a, p.b);
-      auto &t = totals[p.name];
-      t.first += 1;
-      t.second += ms;
-      pool.push_back(p.a);
-      pool.push_back(p.b);
-    }
-    pending.clear();
-  }
-  ~Timer() {
-    for (auto &p : pending) {
-      (void)hipEventDestroy(p.a);
-      (void)hipEventDestroy(p.b);
-    }
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-};
-
-}  // namespace
-
-struct dp_model {
-  // hyper-parameters
-  int ntypes = 0, tebd = 0, axis = 0, n_attn = 0, dattn = 0, M = 0, sel = 0;
-  int bf16 = 0;  // precision of the matrix-core operands (dp_set_precision)
-  std::vector<int> emb, fit;
-  double rcut = 0, rcut_smth = 0, shift = 0, ln_eps = 0;
-  int device = 0;
-  // padded widths
-  std::vector<int> lde;  // embedding outputs
-  std::vector<int> ldf;  // fitting outputs
-  int ldM = 0, ldD = 0;
-  // weights
-  float *type_table = nullptr;  // [ntypes][ntypes][lde[0]]
-  float *ws = nullptr;          // [lde[0]]
-  std::vector<Linear> embl;     // layers 1..n_emb-1 (index l)
-  struct Attn {
-    float *Wt_qkv, *Wb_qkv, *b_qkv, *Wt_o, *Wb_o, *b_o, *gamma, *beta;
-  };
-  std::vector<Attn> attn;
-  std::vector<Linear> fitl;     // layer 0 uses per-type bias fb0
-  float *fb0 = nullptr;         // [ntypes][ldf[0]]
-  float *w_out = nullptr;       // [ldf.back()]
-  float b_out = 0.f;
-  float *ebias = nullptr;       // [ntypes]
-  std::vector<void *> weight_allocs;
-  // workspace
-  void *arena = nullptr;
-  size_t arena_bytes = 0;
-  int cap_nloc = -1, cap_nall = -1, cap_ncell = -1;
-  struct WS {
-    double *coords, *out_e, *out_f, *out_v, *out_ae, *vir_part;
-    int32_t *types, *types_safe;
-    int *atom_cell, *cell_count, *cell_start, *cell_fill, *cell_atoms, *nlist, *nnei, *pair_off;
-    float *geom;
-    std::vector<float *> h, te;        // embedding outputs / tanh parts
-    std::vector<float *> qkv, o, xhat, rstd, G;  // per attention layer (G[a] input of layer a)
-    std::vector<float *> lam, fstat;   // per attention layer: scaled logits, (m, 1/Z)
-    int *ccount, *clist;               // attention class counts [4] and lists [4][nloc]
-    float *T, *dmat, *e;
-    std::vector<float *> z, tf;        // fitting outputs / tanh parts
-    std::vector<float *> fa, fdz;      // fitting backward a_l and dz_l
-    float *dD, *dGa, *dGb, *dY, *dO, *dqkv, *dRt, *gw, *gr, *gs, *g, *astat, *qside;
-    std::vector<float *> du, dh;       // embedding backward
-  } w;
-  DevFlags *flags = nullptr;       // device
-  DevFlags *flags_host = nullptr;  // pinned
-  double *bbox = nullptr;          // device [6]: bounding box for open boundaries
-  hipStream_t own = nullptr;
-  hipStream_t last = nullptr;
-  bool have_step = false;
-  int last_nloc = 0;
-  struct FwdState {
-    const double *coords;  // caller's device coordinates of the last forward
-    CellGrid grid;
-    int nloc, nall;
-    bool valid;
-  } fwd{};
-  Timer timer;
-
-  ~dp_model() {
-    if (arena) (void)hipFree(arena);
-    for (void *p : weight_allocs) (void)hipFree(p);
-    if (flags) (void)hipFree(flags);
-    if (bbox) (void)hipFree(bbox);
-    if (flags_host) (void)hipHostFree(flags_host);
-    if (own) (void)hipStreamDestroy(own);
-  }
-};
 
 namespace {
 
@@ -205,10 +72,14 @@ struct Reader {
   }
 };
 
+// Uploads h to a new device array, or overwrites *out in place when it is set
+// (a weights refresh keeps every array and its size).
 int upload(dp_model *m, const std::vector<float> &h, float **out) {
-  void *p = nullptr;
-  HIP_TRY(hipMalloc(&p, std::max<size_t>(h.size(), 1) * sizeof(float)));
-  m->weight_allocs.push_back(p);
+  void *p = *out;
+  if (!p) {
+    HIP_TRY(hipMalloc(&p, std::max<size_t>(h.size(), 1) * sizeof(float)));
+    m->weight_allocs.push_back(p);
+  }
   HIP_TRY(hipMemcpy(p, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
   *out = (float *)p;
   return DP_OK;
@@ -237,16 +108,11 @@ int make_linear(dp_model *m, const std::vector<double> &W, const std::vector<dou
   return upload(m, bb, &L.b);
 }
 
-int load_weights(dp_model *m, const char *path) {
-  FILE *f = fopen(path, "rb");
-  if (!f) return fail(DP_ERR_WEIGHTS, "cannot open weights file '%s'", path);
-  std::vector<char> buf;
-  char tmp[1 << 16];
-  size_t n;
-  while ((n = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + n);
-  fclose(f);
+}  // namespace
+
+int dpa1::load_weights_image(dp_model *m, const std::vector<char> &buf, bool refresh) {
   if (buf.size() < 8 || memcmp(buf.data(), "DPA1WTS\0", 8) != 0)
-    return fail(DP_ERR_WEIGHTS, "'%s' is not a DPA-1 weights file", path);
+    return fail(DP_ERR_WEIGHTS, "not a DPA-1 weights image");
   Reader rd{buf, 8};
   const uint32_t version = rd.get<uint32_t>();
   const uint32_t n_int = rd.get<uint32_t>();
@@ -259,6 +125,13 @@ int load_weights(dp_model *m, const char *path) {
   std::vector<double> dbls(n_dbl);
   for (auto &v : dbls) v = rd.get<double>();
   if (!rd.ok) return fail(DP_ERR_WEIGHTS, "truncated header");
+  if (refresh) {
+    std::vector<int> cur = {m->ntypes, m->tebd, m->axis, m->n_attn, m->dattn,
+                            (int)m->emb.size(), (int)m->fit.size()};
+    cur.insert(cur.end(), m->emb.begin(), m->emb.end());
+    cur.insert(cur.end(), m->fit.begin(), m->fit.end());
+    if (cur != ints) return fail(DP_ERR_WEIGHTS, "weights image shape differs from the model");
+  }
   m->ntypes = ints[0];
   m->tebd = ints[1];
   m->axis = ints[2];
@@ -296,6 +169,8 @@ int load_weights(dp_model *m, const char *path) {
   if (!(m->ln_eps >= 0) || !std::isfinite(m->shift) || !(m->rcut_smth >= 0))
     return fail(DP_ERR_WEIGHTS, "bad scalar parameters");
 
+  m->lde.clear();
+  m->ldf.clear();
   for (int w : m->emb) m->lde.push_back(pad16(w));
   for (int w : m->fit) m->ldf.push_back(pad16(w));
   m->ldM = pad16(m->M);
@@ -341,7 +216,7 @@ int load_weights(dp_model *m, const char *path) {
     std::vector<double> Wo = rd.arr((size_t)D * Mw), bo = rd.arr(Mw);
     std::vector<double> ga = rd.arr(Mw), be = rd.arr(Mw);
     if (!rd.ok) return fail(DP_ERR_WEIGHTS, "truncated weights");
-    dp_model::Attn at{};
+    dp_model::Attn at = refresh ? m->attn[a] : dp_model::Attn{};
     std::vector<float> wt((size_t)3 * D * ldM, 0.f), wb((size_t)ldM * 3 * D, 0.f),
         bqkv(3 * D, 0.f);
     const std::vector<double> *Ws[3] = {&Wq, &Wk, &Wv};
@@ -373,7 +248,10 @@ int load_weights(dp_model *m, const char *path) {
         (rc = upload(m, wbo, &at.Wb_o)) || (rc = upload(m, bov, &at.b_o)) ||
         (rc = upload(m, gav, &at.gamma)) || (rc = upload(m, bev, &at.beta)))
       return rc;
-    m->attn.push_back(at);
+    if (refresh)
+      m->attn[a] = at;
+    else
+      m->attn.push_back(at);
   }
   m->fitl.resize(n_fit);
   {
@@ -416,6 +294,21 @@ int load_weights(dp_model *m, const char *path) {
     if ((rc = upload(m, ebv, &m->ebias))) return rc;
   }
   return DP_OK;
+}
+
+namespace {
+
+int load_weights(dp_model *m, const char *path) {
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(DP_ERR_WEIGHTS, "cannot open weights file '%s'", path);
+  std::vector<char> buf;
+  char tmp[1 << 16];
+  size_t n;
+  while ((n = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + n);
+  fclose(f);
+  if (buf.size() < 8 || memcmp(buf.data(), "DPA1WTS\0", 8) != 0)
+    return fail(DP_ERR_WEIGHTS, "'%s' is not a DPA-1 weights file", path);
+  return load_weights_image(m, buf, false);
 }
 
 // ------------------------------------------------------------------- workspace

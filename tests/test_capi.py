@@ -1,5 +1,5 @@
 """C ABI checks that need no GPU: the library loads, exports every function
-declared in include/dpa1.h, and rejects bad arguments before touching a device."""
+declared in include/*.h, and rejects bad arguments before touching a device."""
 
 import ctypes
 import os
@@ -13,9 +13,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "dpa1.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dp_\w+)\s*\(", src, flags=re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dp_\w+)\s*\(", src,
+                                flags=re.M))
+    return sorted(names)
 
 
 def test_header_lists_the_abi():
@@ -70,3 +76,24 @@ def test_create_without_device_reports_device_error(weights_path):
         pytest.skip("a GPU is present")
     rc, msg = _create(weights_path)
     assert rc == -6, msg
+
+
+def test_trainer_calls_reject_bad_arguments(weights_path):
+    lib = binding.load_library()
+    h = ctypes.c_void_p()
+    assert lib.dp_train_create(weights_path.encode(), 6.0, 120, None, ctypes.byref(h)) == -1
+    opt = binding.TrainOptions(1.0, 100.0, 1.5, 0.999, 1e-8, 0)  # beta1 out of range
+    assert lib.dp_train_create(weights_path.encode(), 6.0, 120, ctypes.byref(opt),
+                               ctypes.byref(h)) == -1
+    opt = binding.TrainOptions(1.0, 100.0, 0.9, 0.999, 1e-8, 5)  # unknown precision
+    assert lib.dp_train_create(weights_path.encode(), 6.0, 120, ctypes.byref(opt),
+                               ctypes.byref(h)) == -1
+    n = ctypes.c_int32()
+    assert lib.dp_train_params(None, None, ctypes.byref(n)) == -1
+    assert lib.dp_train_save(None, b"x") == -1
+    assert lib.dp_train_gradient(None, None, None, None, 1, 1, None, None, None, None,
+                                 None) == -1
+    lib.dp_train_destroy(None)
+    out = (ctypes.c_double * 2)()
+    assert lib.dp_force_error(None, None, -1, out, None) == -1
+    assert lib.dp_force_error(None, None, 0, out, None) == 0 and out[0] == 0.0

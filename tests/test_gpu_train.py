@@ -1,0 +1,169 @@
+"""Student trainer on the GPU against the training oracle.
+
+The exact loss gradient (energy and force terms, the force term through the
+second derivatives of the energy) is compared tensor by tensor with the FP64
+double-backward oracle; Adam with the oracle's Adam fed the same gradient;
+and a short run must reduce the loss of a realisable target.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dpa1_oracle as orc
+from oracle import train_oracle as tro
+from paper_2604_07276_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RC = 6.0
+SEL = 120
+PE, PF = 1.0, 100.0
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def student_path(tmp_path_factory):
+    p = tmp_path_factory.mktemp("student") / "student_seed1.bin"
+    synth.make_weights(str(p), seed=1, shape=synth.STUDENT_SHAPE)
+    return str(p)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    base = synth.parity_system(0)
+    frames = np.stack([synth.noisy_frame(base, k, 0.05) for k in range(2)])
+    rng = np.random.default_rng(21)
+    e_lab = rng.normal(0.0, 1.0, size=2)
+    f_lab = rng.normal(0.0, 0.05, size=frames.shape)
+    return base, frames, e_lab, f_lab
+
+
+_ORACLE = {}
+
+
+def oracle_grad(student_path, batch, pe, pf):
+    """Oracle loss and gradient for the prefactors (pe, pf), computed once per pair."""
+    if (pe, pf) not in _ORACLE:
+        base, frames, e_lab, f_lab = batch
+        model = orc.load_model(student_path)
+        loss, grads = tro.loss_and_grad(model, frames, base.types, base.box, e_lab, f_lab, RC,
+                                        SEL, pe, pf)
+        _ORACLE[(pe, pf)] = (loss, tro.flatten(model, grads), model)
+    return _ORACLE[(pe, pf)]
+
+
+def _device_batch(torch, base, frames, e_lab, f_lab):
+    dev = torch.device("cuda:0")
+    return (torch.tensor(frames, device=dev), torch.tensor(base.types, device=dev),
+            torch.tensor(e_lab, device=dev), torch.tensor(f_lab, device=dev))
+
+
+def _per_tensor(model, flat_a, flat_b):
+    out, off = {}, 0
+    for k in tro.param_names(model):
+        n = model.t[k].numel()
+        a, b = flat_a[off:off + n], flat_b[off:off + n]
+        out[k] = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        off += n
+    return out
+
+
+# (pe, pf): both terms, the force term alone (second derivatives only), the energy term alone
+@pytest.mark.parametrize("pe,pf", [(PE, PF), (0.0, PF), (PE, 0.0)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 5e-2)])
+def test_gradient_matches_oracle(student_path, batch, precision, tol, pe, pf):
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base, frames, e_lab, f_lab = batch
+    (L, le, lf), g_ref, model = oracle_grad(student_path, batch, pe, pf)
+    prec = binding.PREC_FP32 if precision == "fp32" else binding.PREC_BF16
+    print(f"trainer gradient parity {precision} pe={pe} pf={pf}: 192 atoms x 2 frames",
+          flush=True)
+    tr = binding.Trainer(student_path, RC, SEL, pref_e=pe, pref_f=pf, precision=prec)
+    assert tr.nparams == 86318
+    x, t, el, fl = _device_batch(torch, base, frames, e_lab, f_lab)
+    loss, g = tr.gradient(x, t, base.box, el, fl)
+    tr.close()
+    rl = 1e-5 if precision == "fp32" else 2e-2
+    assert loss[0] == pytest.approx(L, rel=rl, abs=1e-14)
+    assert loss[1] == pytest.approx(le, rel=10 * rl, abs=1e-14)
+    assert loss[2] == pytest.approx(lf, rel=rl, abs=1e-14)
+    rel = _per_tensor(model, g, g_ref)
+    bad = {k: v for k, v in rel.items() if not v <= tol}
+    assert not bad, bad
+    cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
+    assert cos > (1 - 1e-8 if precision == "fp32" else 0.999)
+
+
+def test_gradient_is_deterministic(student_path, batch):
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base, frames, e_lab, f_lab = batch
+    x, t, el, fl = _device_batch(torch, base, frames, e_lab, f_lab)
+    tr = binding.Trainer(student_path, RC, SEL, pref_e=PE, pref_f=PF)
+    l1, g1 = tr.gradient(x, t, base.box, el, fl)
+    l2, g2 = tr.gradient(x, t, base.box, el, fl)
+    tr.close()
+    assert np.array_equal(g1, g2) and np.array_equal(l1, l2)
+
+
+def test_adam_steps_match_oracle_adam(student_path, batch):
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base, frames, e_lab, f_lab = batch
+    x, t, el, fl = _device_batch(torch, base, frames, e_lab, f_lab)
+    tr = binding.Trainer(student_path, RC, SEL, pref_e=PE, pref_f=PF)
+    theta = tr.params()
+    st = tro.adam_init(tr.nparams)
+    for lr in (1e-3, 5e-4):
+        _, g = tr.gradient(x, t, base.box, el, fl)
+        tr.step(x, t, base.box, el, fl, lr)
+        # the master weights are FP32: round the reference after each update
+        theta = tro.adam_step(theta, g, st, lr, 0.9, 0.999, 1e-8).astype(np.float32)
+        theta = theta.astype(np.float64)
+        np.testing.assert_allclose(tr.params(), theta, rtol=0, atol=2e-6)
+    tr.close()
+
+
+def test_training_reduces_loss_on_realisable_target(student_path, batch, tmp_path):
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base, frames, _, _ = batch
+    # target: the same architecture with other weights (labels from the library's inference)
+    tgt = str(tmp_path / "target.bin")
+    synth.make_weights(tgt, seed=7, shape=synth.STUDENT_SHAPE)
+    m = binding.Model(tgt, RC, SEL)
+    e_lab, f_lab = [], []
+    for fr in frames:
+        E, F, _, _ = m.compute(fr, base.types, base.box, len(fr), 0)
+        e_lab.append(E)
+        f_lab.append(F)
+    m.close()
+    x, t, el, fl = _device_batch(torch, base, frames, np.array(e_lab), np.stack(f_lab))
+    tr = binding.Trainer(student_path, RC, SEL, pref_e=PE, pref_f=PF)
+    losses = [tr.step(x, t, base.box, el, fl, 2e-3)[0] for _ in range(30)]
+    out = str(tmp_path / "trained.bin")
+    tr.save(out)
+    params = tr.params()
+    tr.close()
+    print("loss", losses[0], "->", losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    saved = tro.flatten(orc.load_model(out))
+    assert np.array_equal(saved, params)
+
+
+def test_force_error_helper():
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(1001, 3))
+    b = a + rng.normal(0, 1e-2, size=a.shape)
+    rmse, mx = binding.force_error(torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda"))
+    assert rmse == pytest.approx(np.sqrt(np.mean((a - b) ** 2)), rel=1e-12)
+    assert mx == np.max(np.abs(a - b))
