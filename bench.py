@@ -9,6 +9,12 @@ on the host and uploaded before timing; step k evaluates frame k mod 100.
 One step = neighbour-list rebuild + forward + input-gradient adjoint + forces
 + virial (dp_compute_device on device-resident inputs).
 
+The JSON line also carries the BF16 mode on the same frames and the
+distilled-student leg: a DP-SE-style student is trained on teacher-labelled
+noisy frames (a bounded run, sizes in the arguments), then serves held-out
+frames with the teacher auditing it; its atom-steps/s is reported next to its
+held-out force RMSE and the teacher's force scale.
+
 Prints one JSON line on stdout; a per-kernel table goes to stderr.
 """
 
@@ -165,6 +171,12 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--host-api-steps", type=int, default=10,
                     help="steps of the host-memory entry point to time (0: skip)")
+    ap.add_argument("--student-steps", type=int, default=200,
+                    help="training steps of the distilled student leg (0: skip the leg)")
+    ap.add_argument("--student-frames", type=int, default=256,
+                    help="teacher-labelled training frames of the student leg")
+    ap.add_argument("--student-eval", type=int, default=32,
+                    help="held-out frames served by the audited student")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one device-to-device copy of this many MiB (calibrates "
                          "hardware byte counters against a known transfer) and exit")
@@ -295,6 +307,26 @@ def main():
     bf16_ms = b0.elapsed_time(b1) / args.steps
     model.set_precision(binding.PREC_FP32)
 
+    # distilled student: teacher labels, training, audited serving of held-out frames
+    student_out = None
+    if args.student_steps > 0:
+        from paper_2604_07276_amd import student as student_mod
+        st = student_mod.run(n_train=args.student_frames, n_eval=args.student_eval,
+                             steps=args.student_steps)
+        thr = st["throughput"]
+        student_out = {
+            "value": thr["student_atom_steps_per_s"], "unit": "atom-steps/s",
+            "ms_per_step": thr["student_ms_per_step"],
+            "dtype": "bf16 matrix-core operands, f32 accumulate, f64 reductions",
+            "vs_fp32": round(ms_step / thr["student_ms_per_step"], 3),
+            "model": st["student"],
+            "force_rmse_eV_per_A": st["held_out"]["force_rmse_eV_per_A"],
+            "force_max_abs_err_eV_per_A": st["held_out"]["force_max_abs_err_eV_per_A"],
+            "teacher_force_rms_eV_per_A": st["held_out"]["teacher_force_rms_eV_per_A"],
+            "relative_force_rmse": st["held_out"]["relative_force_rmse"],
+            "energy_mae_eV_per_atom": st["held_out"]["energy_mae_eV_per_atom"],
+            "training": st["training"], "serving": st["serving"]}
+
     # host-memory entry point (PCIe copies included): context only, never `value`
     host_ms = None
     if args.host_api_steps > 0:
@@ -345,6 +377,7 @@ def main():
                  "dtype": "bf16 matrix-core operands, f32 accumulate, f64 reductions",
                  "vs_fp32": round(ms_step / bf16_ms, 3)},
         "accuracy_vs_oracle": accuracy,
+        "student": student_out,
     }
     print(json.dumps(out), flush=True)
     model.close()

@@ -47,14 +47,14 @@ struct dp_trainer {
   // capacity-sized buffers
   void *arena = nullptr;
   int cap_n = 0, cap_frames = 0;
-  size_t Pcap = 0;
+  size_t Pcap = 0, ldr = 0;
   double *Fst = nullptr, *Est = nullptr, *vir = nullptr, *sq_part = nullptr, *le = nullptr;
   float *a_dev = nullptr;
   float4 *delta = nullptr;
   float *Td = nullptr, *Xd = nullptr, *Zd1 = nullptr, *Yd1 = nullptr, *Zd2 = nullptr,
         *WoR = nullptr, *Zb2 = nullptr, *Yb1 = nullptr, *Zb1 = nullptr, *Db = nullptr;
   float *X3 = nullptr, *Z3 = nullptr, *X2 = nullptr, *Z2 = nullptr, *Z1 = nullptr,
-        *WS1 = nullptr;
+        *WS1 = nullptr, *HB2 = nullptr;
   int *grp = nullptr;
   float *part = nullptr;
   size_t part_cap = 0;
@@ -120,7 +120,10 @@ int ensure_buffers(dp_trainer *t, int n, int nframes) {
   if (n <= t->cap_n && nframes <= t->cap_frames) return DP_OK;
   const int cn = std::max(n, t->cap_n), cf = std::max(nframes, t->cap_frames);
   dp_model *m = t->m;
-  const size_t P = (size_t)cn * m->sel;
+  const size_t P = ((size_t)cn * m->sel + 15) / 16 * 16;
+  // feature-major pair operands: primal rows [0, P), tangent rows [P, 2 P), and one
+  // 16-row step of slack read (masked) past the last row
+  const size_t ldr = 2 * P + 16;
   const int ldD = m->ldD, ldf0 = m->ldf[0], ldf1 = m->ldf[1];
   const int nsq = tr_seed_blocks(cn);
   // per-centre GEMM operands keep one 16-row tile of slack
@@ -141,10 +144,12 @@ int ensure_buffers(dp_trainer *t, int n, int nframes) {
                oWoR = take(sizeof(float) * r1 * ldf1), oZb2 = take(sizeof(float) * r2 * ldf1),
                oYb1 = take(sizeof(float) * r2 * ldf0), oZb1 = take(sizeof(float) * r2 * ldf0),
                oDb = take(sizeof(float) * r2 * ldD),
-               oX3 = take(sizeof(float) * 2 * P * kTrN2), oZ3 = take(sizeof(float) * 2 * P * kTrN3),
-               oX2 = take(sizeof(float) * 2 * P * kTrN1), oZ2 = take(sizeof(float) * 2 * P * kTrN2),
-               oZ1 = take(sizeof(float) * P * kTrN1), oWS1 = take(sizeof(float) * P * kTrN1),
-               oGrp = take(sizeof(int) * P);
+               oX3 = take(sizeof(float) * ldr * kTrN2), oZ3 = take(sizeof(float) * ldr * kTrN3),
+               oX2 = take(sizeof(float) * ldr * kTrN1), oZ2 = take(sizeof(float) * ldr * kTrN2),
+               oZ1 = take(sizeof(float) * ldr * kTrN1), oWS1 = take(sizeof(float) * ldr * kTrN1),
+               oHB2 = take(sizeof(float) * ldr * kTrN2), oGrp = take(sizeof(int) * (P + 16));
+  if (ldr * kTrN3 >= ((size_t)1 << 32))
+    return fail(DP_ERR_ARG, "natoms * sel = %zu pair rows exceed the trainer's limit", P);
   const size_t part_cap = (size_t)1 << 22;
   const size_t oPart = take(sizeof(float) * part_cap);
   if (t->arena) {
@@ -178,10 +183,12 @@ int ensure_buffers(dp_trainer *t, int n, int nframes) {
   t->Z2 = (float *)(b + oZ2);
   t->Z1 = (float *)(b + oZ1);
   t->WS1 = (float *)(b + oWS1);
+  t->HB2 = (float *)(b + oHB2);
   t->grp = (int *)(b + oGrp);
   t->part = (float *)(b + oPart);
   t->part_cap = part_cap;
   t->Pcap = P;
+  t->ldr = ldr;
   t->cap_n = cn;
   t->cap_frames = cf;
   return DP_OK;
@@ -201,7 +208,8 @@ int batch_gradient(dp_trainer *t, const double *d_frames, const int32_t *d_types
   const float cf = (float)(2.0 * pf / (3.0 * N * B));
   const double ca = 2.0 * pe / ((double)N * N * B), cl = pe / ((double)N * N * B);
   const int nsq = tr_seed_blocks(N);
-  const size_t Pcap = (size_t)N * m->sel;
+  // pair-row stride of the feature-major operands: the tangent rows start at Pst
+  const size_t Pst = ((size_t)N * m->sel + 15) / 16 * 16;
   launch_fill_f64(t->acc, t->acc_n, s);
   for (int f = 0; f < B; ++f) {
     const double *xf = d_frames + (size_t)3 * N * f;
@@ -224,9 +232,9 @@ int batch_gradient(dp_trainer *t, const double *d_frames, const int32_t *d_types
     pa.inv_sel = 1.0f / (float)m->sel;
     pa.table = m->type_table;
     pa.ws = m->ws;
-    pa.W2 = m->embl[1].Wb;
+    pa.W2t = m->embl[1].Wt;
     pa.b2 = m->embl[1].b;
-    pa.W3 = m->embl[2].Wb;
+    pa.W3t = m->embl[2].Wt;
     pa.b3 = m->embl[2].b;
     pa.ntypes = T;
     pa.T = w.T;
@@ -247,22 +255,23 @@ int batch_gradient(dp_trainer *t, const double *d_frames, const int32_t *d_types
     gemm_linear(GemmArgs{t->Zb1, ldf0, L0.Wb, ldf0, ldD, m->M * m->axis, nullptr, 2 * N, bf},
                 nullptr, t->Db, ldD, s);
     // descriptor and embedding net
-    launch_tr_pair_rev(pa, t->delta, t->Td, t->Db, ldD, Pcap, t->X3, t->Z3, t->X2, t->Z2, t->Z1,
-                       t->WS1, t->grp, s);
+    const size_t ldr = t->ldr;
+    launch_tr_pair_rev(pa, t->delta, t->Td, t->Db, ldD, Pst, ldr, t->X3, t->Z3, t->X2, t->Z2,
+                       t->Z1, t->WS1, t->HB2, t->grp, s);
     const int *Pdev = w.pair_off + N;
-    const int Pmax = (int)Pcap;
-    tr_wgrad(t->X3, t->X3 + Pcap * kTrN2, kTrN2, t->Z3, t->Z3 + Pcap * kTrN3, kTrN3, kTrN2, kTrN3,
-             Pdev, Pmax, bf, t->part, t->part_cap, t->acc + t->o_W3, s);
-    tr_wgrad(t->X2, t->X2 + Pcap * kTrN1, kTrN1, t->Z2, t->Z2 + Pcap * kTrN2, kTrN2, kTrN1, kTrN2,
-             Pdev, Pmax, bf, t->part, t->part_cap, t->acc + t->o_W2, s);
-    tr_colsum(t->Z3, kTrN3, kTrN3, Pdev, Pmax, nullptr, 1, t->part, t->part_cap,
-              t->acc + t->o_b3, s);
-    tr_colsum(t->Z2, kTrN2, kTrN2, Pdev, Pmax, nullptr, 1, t->part, t->part_cap,
-              t->acc + t->o_b2, s);
-    tr_colsum(t->Z1, kTrN1, kTrN1, Pdev, Pmax, t->grp, T * T, t->part, t->part_cap,
-              t->acc + t->o_tab, s);
-    tr_colsum(t->WS1, kTrN1, kTrN1, Pdev, Pmax, nullptr, 1, t->part, t->part_cap,
-              t->acc + t->o_ws, s);
+    const int Pmax = (int)Pst;
+    tr_wgrad_fm(t->X3, t->Z3, ldr, Pst, kTrN2, kTrN3, Pdev, Pmax, bf, t->part, t->part_cap,
+                t->acc + t->o_W3, s);
+    tr_wgrad_fm(t->X2, t->Z2, ldr, Pst, kTrN1, kTrN2, Pdev, Pmax, bf, t->part, t->part_cap,
+                t->acc + t->o_W2, s);
+    tr_colsum_fm(t->Z3, ldr, kTrN3, Pdev, Pmax, nullptr, 1, t->part, t->part_cap,
+                 t->acc + t->o_b3, s);
+    tr_colsum_fm(t->Z2, ldr, kTrN2, Pdev, Pmax, nullptr, 1, t->part, t->part_cap,
+                 t->acc + t->o_b2, s);
+    tr_colsum_fm(t->Z1, ldr, kTrN1, Pdev, Pmax, t->grp, T * T, t->part, t->part_cap,
+                 t->acc + t->o_tab, s);
+    tr_colsum_fm(t->WS1, ldr, kTrN1, Pdev, Pmax, nullptr, 1, t->part, t->part_cap,
+                 t->acc + t->o_ws, s);
     tr_wgrad(w.z[0], t->Yd1, ldf0, t->Zb2, t->Zb2 + (size_t)N * ldf1, ldf1, H0, H1, nullptr, N,
              bf, t->part, t->part_cap, t->acc + t->o_W1f, s);
     tr_colsum(t->Zb2, ldf1, H1, nullptr, N, nullptr, 1, t->part, t->part_cap, t->acc + t->o_b1f,

@@ -24,6 +24,11 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;          // centres per 256-thread block
 constexpr int kGS = kTrN3 + 1;     // LDS row stride of per-pair G rows
 
+// Weights are read through the constant address space: the loads are then
+// scalar (uniform, never written by the kernel) and the weights live in SGPRs.
+typedef const float __attribute__((address_space(4))) *cfp;
+__device__ __forceinline__ float wc(const float *p, int i) { return ((cfp)p)[i]; }
+
 __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __syncthreads();
@@ -106,9 +111,9 @@ __device__ __forceinline__ void emb_l1(const TrainPairArgs &a, int tj, int ti, f
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int o = 4 * q + u;
-      const float t = tanhf(fmaf(a.ws[o], s, zz[u]));
+      const float t = tanhf(fmaf(wc(a.ws, o), s, zz[u]));
       h1[o] = t;
-      h1d[o] = (1.0f - t * t) * a.ws[o];
+      h1d[o] = (1.0f - t * t) * wc(a.ws, o);
     }
   }
 }
@@ -120,11 +125,11 @@ __device__ __forceinline__ void emb_l2(const TrainPairArgs &a, const float h1[kT
                                        float h2d[kTrN2]) {
 #pragma unroll
   for (int o = 0; o < kTrN2; ++o) {
-    float z = a.b2[o], zd = 0.f;
+    float z = wc(a.b2, o), zd = 0.f;
 #pragma unroll
     for (int k = 0; k < kTrN1; ++k) {
-      z = fmaf(a.W2[k * kTrN2 + o], h1[k], z);
-      zd = fmaf(a.W2[k * kTrN2 + o], h1d[k], zd);
+      z = fmaf(wc(a.W2t, o * kTrN1 + k), h1[k], z);
+      zd = fmaf(wc(a.W2t, o * kTrN1 + k), h1d[k], zd);
     }
     const float t = tanhf(z);
     h2[o] = t + h1[o % kTrN1];
@@ -184,11 +189,11 @@ __global__ __launch_bounds__(256) void k_tr_tangent(TrainPairArgs a,
       emb_l2(a, h1, h1d, h2, h2d);
 #pragma unroll 4
       for (int o = 0; o < kTrN3; ++o) {
-        float z = a.b3[o], zd = 0.f;
+        float z = wc(a.b3, o), zd = 0.f;
 #pragma unroll
         for (int k = 0; k < kTrN2; ++k) {
-          z = fmaf(a.W3[k * kTrN3 + o], h2[k], z);
-          zd = fmaf(a.W3[k * kTrN3 + o], h2d[k], zd);
+          z = fmaf(wc(a.W3t, o * kTrN2 + k), h2[k], z);
+          zd = fmaf(wc(a.W3t, o * kTrN2 + k), h2d[k], zd);
         }
         const float t = tanhf(z);
         sG[w][lane * kGS + o] = t + h2[o % kTrN2];
@@ -292,9 +297,8 @@ __global__ void k_tr_fit_l0(const float *__restrict__ t1, const float *__restric
 // and of its s-derivative, writing the rows of the weight gradients.
 __global__ __launch_bounds__(256) void k_tr_pair_rev(
     TrainPairArgs a, const float4 *__restrict__ delta, const float *__restrict__ Td,
-    const float *__restrict__ Db, int ldD, size_t Pcap, float *__restrict__ X3,
-    float *__restrict__ Z3, float *__restrict__ X2, float *__restrict__ Z2,
-    float *__restrict__ Z1, float *__restrict__ WS1, int *__restrict__ grp) {
+    const float *__restrict__ Db, int ldD, size_t Pcap, size_t ldr, float *__restrict__ X3,
+    float *__restrict__ Z3, float *__restrict__ HB2, int *__restrict__ grp) {
   __shared__ float sT[kWaves][4 * 64], sTd[kWaves][4 * 64];
   __shared__ float sDb[kWaves][64 * 16], sDdb[kWaves][64 * 16];
   __shared__ float sTb[kWaves][4 * 64], sTdb[kWaves][4 * 64];
@@ -348,6 +352,7 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev(
   lds_fence();
   // --- pairs
   const float4 di = delta[ic];
+  const unsigned ld32 = (unsigned)ldr, pc32 = (unsigned)Pcap;
   const int nch = block_chunks(a.nnei, a.nloc);
   for (int ch = 0; ch < nch; ++ch) {
     const int p = ch * 64 + lane;
@@ -364,68 +369,120 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev(
     float h1[kTrN1], h1d[kTrN1], h2[kTrN2], h2d[kTrN2];
     emb_l1(a, tj, ti, pt.s, h1, h1d);
     emb_l2(a, h1, h1d, h2, h2d);
+    // feature-major stores: 32-bit offsets advanced one feature row at a time
+    // (the host keeps 64 * ldr below 2^32)
     {
-      float4 *xp = (float4 *)(X3 + q * kTrN2);
-      float4 *xt = (float4 *)(X3 + (Pcap + q) * kTrN2);
+      unsigned off = (unsigned)q;
 #pragma unroll
-      for (int k = 0; k < kTrN2 / 4; ++k) {
-        xp[k] = make_float4(h2[4 * k], h2[4 * k + 1], h2[4 * k + 2], h2[4 * k + 3]);
-        xt[k] = make_float4(h2d[4 * k], h2d[4 * k + 1], h2d[4 * k + 2], h2d[4 * k + 3]);
-      }
-      float4 *yp = (float4 *)(X2 + q * kTrN1);
-      float4 *yt = (float4 *)(X2 + (Pcap + q) * kTrN1);
-#pragma unroll
-      for (int k = 0; k < kTrN1 / 4; ++k) {
-        yp[k] = make_float4(h1[4 * k], h1[4 * k + 1], h1[4 * k + 2], h1[4 * k + 3]);
-        yt[k] = make_float4(h1d[4 * k], h1d[4 * k + 1], h1d[4 * k + 2], h1d[4 * k + 3]);
+      for (int k = 0; k < kTrN2; ++k) {
+        X3[off] = h2[k];
+        X3[off + pc32] = h2d[k];
+        off += ld32;
       }
     }
     // third layer (doubling residual) in reverse
     float hb2[kTrN2], hb2d[kTrN2];
 #pragma unroll
     for (int k = 0; k < kTrN2; ++k) hb2[k] = hb2d[k] = 0.f;
+    unsigned zoff = (unsigned)q;
 #pragma unroll 1
-    for (int o4 = 0; o4 < kTrN3; o4 += 4) {
-      float zbv[4], zbdv[4];
+    for (int o = 0; o < kTrN3; ++o) {
+      float Gb = 0.f, Gdb = 0.f;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int o = o4 + u;
-        float Gb = 0.f, Gdb = 0.f;
+      for (int c = 0; c < 4; ++c) {
+        const float b1v = sTb[w][c * 64 + o], b2v = sTdb[w][c * 64 + o];
+        Gb = fmaf(pt.Rt[c], b1v, fmaf(pt.Rd[c], b2v, Gb));
+        Gdb = fmaf(pt.Rt[c], b2v, Gdb);
+      }
+      Gdb *= pt.sdot;
+      float z = wc(a.b3, o), zd = 0.f;
+#pragma unroll
+      for (int k = 0; k < kTrN2; ++k) {
+        z = fmaf(wc(a.W3t, o * kTrN2 + k), h2[k], z);
+        zd = fmaf(wc(a.W3t, o * kTrN2 + k), h2d[k], zd);
+      }
+      const float t = tanhf(z), g = 1.0f - t * t;
+      const float zbd = g * Gdb;
+      const float zb = g * (Gb - 2.0f * t * zd * Gdb);
+#pragma unroll
+      for (int k = 0; k < kTrN2; ++k) {
+        hb2[k] = fmaf(wc(a.W3t, o * kTrN2 + k), zb, hb2[k]);
+        hb2d[k] = fmaf(wc(a.W3t, o * kTrN2 + k), zbd, hb2d[k]);
+      }
+      Z3[zoff] = zb;
+      Z3[zoff + pc32] = zbd;
+      zoff += ld32;
+    }
+    // the [h2, h2] residual: G-bar[k] and G-bar[k + 32] both feed h2[k]
+#pragma unroll
+    for (int k = 0; k < kTrN2; ++k) {
+      float gb = 0.f, gdb = 0.f;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int o = k + hh * kTrN2;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const float b1v = sTb[w][c * 64 + o], b2v = sTdb[w][c * 64 + o];
-          Gb = fmaf(pt.Rt[c], b1v, fmaf(pt.Rd[c], b2v, Gb));
-          Gdb = fmaf(pt.Rt[c], b2v, Gdb);
-        }
-        Gdb *= pt.sdot;
-        float z = a.b3[o], zd = 0.f;
-#pragma unroll
-        for (int k = 0; k < kTrN2; ++k) {
-          z = fmaf(a.W3[k * kTrN3 + o], h2[k], z);
-          zd = fmaf(a.W3[k * kTrN3 + o], h2d[k], zd);
-        }
-        const float t = tanhf(z), g = 1.0f - t * t;
-        const float zbd = g * Gdb;
-        const float zb = g * (Gb - 2.0f * t * zd * Gdb);
-#pragma unroll
-        for (int k = 0; k < kTrN2; ++k) {
-          hb2[k] = fmaf(a.W3[k * kTrN3 + o], zb, hb2[k]);
-          hb2d[k] = fmaf(a.W3[k * kTrN3 + o], zbd, hb2d[k]);
-        }
-        zbv[u] = zb;
-        zbdv[u] = zbd;
-        // the [h2, h2] residual: o and o + 32 both feed h2[o % 32]
-        if (o < kTrN2) {
-          hb2[o] += Gb;
-          hb2d[o] += Gdb;
-        } else {
-          hb2[o - kTrN2] += Gb;
-          hb2d[o - kTrN2] += Gdb;
+          gb = fmaf(pt.Rt[c], b1v, fmaf(pt.Rd[c], b2v, gb));
+          gdb = fmaf(pt.Rt[c], b2v, gdb);
         }
       }
-      *(float4 *)(Z3 + q * kTrN3 + o4) = make_float4(zbv[0], zbv[1], zbv[2], zbv[3]);
-      *(float4 *)(Z3 + (Pcap + q) * kTrN3 + o4) = make_float4(zbdv[0], zbdv[1], zbdv[2], zbdv[3]);
+      hb2[k] += gb;
+      hb2d[k] = fmaf(gdb, pt.sdot, hb2d[k]);
     }
+    {
+      unsigned off = (unsigned)q;
+#pragma unroll
+      for (int k = 0; k < kTrN2; ++k) {
+        HB2[off] = hb2[k];
+        HB2[off + pc32] = hb2d[k];
+        off += ld32;
+      }
+    }
+    grp[q] = tj * a.ntypes + ti;
+  }
+}
+
+
+// Second and first embedding layers in reverse, one lane per pair (flat over
+// the pair rows): from h2-bar, h2'-bar of the per-centre sweep, recomputing
+// h1, h1' from s and the pair's types.
+__global__ __launch_bounds__(256) void k_tr_pair_rev2(TrainPairArgs a, const int *__restrict__ Pdev,
+                                                      size_t Pcap, size_t ldr,
+                                                      const float *__restrict__ HB2,
+                                                      const int *__restrict__ grp,
+                                                      float *__restrict__ X2, float *__restrict__ Z2,
+                                                      float *__restrict__ Z1,
+                                                      float *__restrict__ WS1) {
+  const int P = Pdev[0];
+  const unsigned ld32 = (unsigned)ldr, pc32 = (unsigned)Pcap;
+  for (int qi = blockIdx.x * 256 + threadIdx.x; qi < P; qi += gridDim.x * 256) {
+    const unsigned q = (unsigned)qi;
+    const float s = a.geom[(size_t)q * kGeom + G_S];
+    const int g = grp[q];
+    const int tj = g / a.ntypes, ti = g - tj * a.ntypes;
+    float hb2[kTrN2], hb2d[kTrN2];
+    {
+      unsigned off = q;
+#pragma unroll
+      for (int k = 0; k < kTrN2; ++k) {
+        hb2[k] = HB2[off];
+        hb2d[k] = HB2[off + pc32];
+        off += ld32;
+      }
+    }
+    float h1[kTrN1], h1d[kTrN1];
+    emb_l1(a, tj, ti, s, h1, h1d);
+    {
+      unsigned off = q;
+#pragma unroll
+      for (int k = 0; k < kTrN1; ++k) {
+        X2[off] = h1[k];
+        X2[off + pc32] = h1d[k];
+        off += ld32;
+      }
+    }
+    const PairTangent pt{s};
     // second layer (doubling residual) in reverse
     float hb1[kTrN1], hb1d[kTrN1];
 #pragma unroll
@@ -436,27 +493,31 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev(
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int o = o4 + u;
-        float z = a.b2[o], zd = 0.f;
+        float z = wc(a.b2, o), zd = 0.f;
 #pragma unroll
         for (int k = 0; k < kTrN1; ++k) {
-          z = fmaf(a.W2[k * kTrN2 + o], h1[k], z);
-          zd = fmaf(a.W2[k * kTrN2 + o], h1d[k], zd);
+          z = fmaf(wc(a.W2t, o * kTrN1 + k), h1[k], z);
+          zd = fmaf(wc(a.W2t, o * kTrN1 + k), h1d[k], zd);
         }
         const float t = tanhf(z), g = 1.0f - t * t;
         const float zbd = g * hb2d[o];
         const float zb = g * (hb2[o] - 2.0f * t * zd * hb2d[o]);
 #pragma unroll
         for (int k = 0; k < kTrN1; ++k) {
-          hb1[k] = fmaf(a.W2[k * kTrN2 + o], zb, hb1[k]);
-          hb1d[k] = fmaf(a.W2[k * kTrN2 + o], zbd, hb1d[k]);
+          hb1[k] = fmaf(wc(a.W2t, o * kTrN1 + k), zb, hb1[k]);
+          hb1d[k] = fmaf(wc(a.W2t, o * kTrN1 + k), zbd, hb1d[k]);
         }
         hb1[o % kTrN1] += hb2[o];
         hb1d[o % kTrN1] += hb2d[o];
         zbv[u] = zb;
         zbdv[u] = zbd;
       }
-      *(float4 *)(Z2 + q * kTrN2 + o4) = make_float4(zbv[0], zbv[1], zbv[2], zbv[3]);
-      *(float4 *)(Z2 + (Pcap + q) * kTrN2 + o4) = make_float4(zbdv[0], zbdv[1], zbdv[2], zbdv[3]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned off = (unsigned)(o4 + u) * ld32 + (unsigned)q;
+        Z2[off] = zbv[u];
+        Z2[off + pc32] = zbdv[u];
+      }
     }
     // first layer: h1' = (1 - h1^2) ws
 #pragma unroll
@@ -466,15 +527,18 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev(
       for (int u = 0; u < 4; ++u) {
         const int o = o4 + u;
         const float g = 1.0f - h1[o] * h1[o];
-        const float gbar = a.ws[o] * hb1d[o];
+        const float gbar = wc(a.ws, o) * hb1d[o];
         const float zb = g * (hb1[o] - 2.0f * h1[o] * gbar);
         zbv[u] = zb;
         wsv[u] = fmaf(pt.s, zb, g * hb1d[o]);
       }
-      *(float4 *)(Z1 + q * kTrN1 + o4) = make_float4(zbv[0], zbv[1], zbv[2], zbv[3]);
-      *(float4 *)(WS1 + q * kTrN1 + o4) = make_float4(wsv[0], wsv[1], wsv[2], wsv[3]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned off = (unsigned)(o4 + u) * ld32 + (unsigned)q;
+        Z1[off] = zbv[u];
+        WS1[off] = wsv[u];
+      }
     }
-    grp[q] = tj * a.ntypes + ti;
   }
 }
 
@@ -483,13 +547,16 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev(
 // part[blk][kin_pad][nout_pad] = sum over the block's rows of X^T Z for both
 // segments.  Block = 4 waves over one 16KT x 16NT output tile group; each
 // wave takes every 4th group of rows, the four waves are summed in LDS.
-template <int KT, int NT, bool BF>
+// ONEHOT: the X operand is not read but generated, X[r][k] = (group[r] == k)
+// (group == nullptr: X[r][k] = (k == 0)), so the product sums Z by group.
+template <int KT, int NT, bool BF, bool ONEHOT>
 __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
                                                const float *__restrict__ X2, int ldx,
                                                const float *__restrict__ Z1,
                                                const float *__restrict__ Z2, int ldz, int kin,
                                                int nout, const int *__restrict__ rows_dev,
                                                int rows_max, int rows_per_block,
+                                               const int32_t *__restrict__ group,
                                                float *__restrict__ part, int kin_pad,
                                                int nout_pad) {
   __shared__ float red[4][KT * NT * 256];
@@ -505,7 +572,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
     for (int nt = 0; nt < NT; ++nt) acc[kt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int col = lane & 15, quad = lane >> 4;
   constexpr int RG = BF ? 16 : 4;  // rows per matrix-core step
-  for (int seg = 0; seg < 2; ++seg) {
+  const int nseg = (ONEHOT || X2 == nullptr) ? 1 : 2;
+  for (int seg = 0; seg < nseg; ++seg) {
     const float *X = seg ? X2 : X1;
     const float *Z = seg ? Z2 : Z1;
     for (int rg = r0 + w * RG; rg < r1; rg += 4 * RG) {
@@ -514,11 +582,17 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
         const bool rv = r < r1;
         const size_t rr = (size_t)(rv ? r : r0);
         float xv[KT], zv[NT];
+        if constexpr (ONEHOT) {
+          const int gr = group ? group[rr] : 0;
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) {
-          const int c = k0 + 16 * kt + col;
-          const float v = X[rr * ldx + (c < kin ? c : 0)];
-          xv[kt] = (rv && c < kin) ? v : 0.f;
+          for (int kt = 0; kt < KT; ++kt) xv[kt] = (rv && gr == k0 + 16 * kt + col) ? 1.f : 0.f;
+        } else {
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt) {
+            const int c = k0 + 16 * kt + col;
+            const float v = X[rr * ldx + (c < kin ? c : 0)];
+            xv[kt] = (rv && c < kin) ? v : 0.f;
+          }
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -532,6 +606,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
           for (int nt = 0; nt < NT; ++nt)
             acc[kt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[kt], zv[nt], acc[kt][nt], 0, 0, 0);
       } else {
+        static_assert(!ONEHOT, "group sums use FP32 operands");
         floatx4 xv[KT], zv[NT];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -583,55 +658,125 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
   }
 }
 
-// acc[k][n] += sum_b part[b][k][n] (fixed order, FP64).
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nblk, int kin_pad, int nout_pad,
-                               int kin, int nout, double *__restrict__ acc) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kin * nout) return;
-  const int k = e / nout, n = e % nout;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += (double)part[((size_t)b * kin_pad + k) * nout_pad + n];
-  acc[e] += s;
-}
-
-// part[blk][g][c]: per-column, per-group sums over the block's rows.  Thread
-// (slice, c) owns its LDS accumulators, so the sums are race-free and their
-// order fixed.
-__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ Z, int ldz, int ncol,
-                                                const int *__restrict__ rows_dev, int rows_max,
-                                                int rows_per_block,
-                                                const int32_t *__restrict__ group, int ngroups,
-                                                float *__restrict__ part) {
-  extern __shared__ float sacc[];  // [slices][ngroups][ncol]
-  const int slices = 256 / ncol;
-  const int t = threadIdx.x, c = t % ncol, sl = t / ncol;
+// Feature-major variant: Xt [kin][ldr], Zt [nout][ldr] hold one feature per
+// row and the pair rows along it; segment 2 (if seg2 > 0) starts at column
+// seg2.  Lane (c, q) of a 16-row step reads rows 4q..4q+3 of feature c as one
+// float4, which is the k-slice layout of the BF16 product; the FP32 product
+// takes the four components as four 16x16x4 steps.
+template <int KT, int NT, bool BF, bool ONEHOT>
+__global__ __launch_bounds__(256) void k_wgrad_fm(const float *__restrict__ Xt,
+                                                  const float *__restrict__ Zt, size_t ldr,
+                                                  size_t seg2, int kin, int nout,
+                                                  const int *__restrict__ rows_dev, int rows_max,
+                                                  int rows_per_block,
+                                                  const int32_t *__restrict__ group,
+                                                  float *__restrict__ part, int kin_pad,
+                                                  int nout_pad) {
+  __shared__ float red[4][KT * NT * 256];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rows = rows_dev ? min(rows_dev[0], rows_max) : rows_max;
   const int r0 = blockIdx.x * rows_per_block;
   const int r1 = min(rows, r0 + rows_per_block);
-  for (int e = t; e < slices * ngroups * ncol; e += 256) sacc[e] = 0.f;
-  __syncthreads();
-  if (sl < slices) {
-    float *my = sacc + (size_t)sl * ngroups * ncol + c;
-    for (int r = r0 + sl; r < r1; r += slices) {
-      const int g = group ? group[r] : 0;
-      my[g * ncol] += Z[(size_t)r * ldz + c];
+  const int k0 = blockIdx.y * 16 * KT, n0 = blockIdx.z * 16 * NT;
+  floatx4 acc[KT][NT];
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[kt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int col = lane & 15, quad = lane >> 4;
+  const int nseg = (ONEHOT || seg2 == 0) ? 1 : 2;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const size_t base = seg ? seg2 : 0;
+    for (int rg = r0 + w * 16; rg < r1; rg += 64) {
+      const int rq = rg + 4 * quad;
+      bool rv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rv[j] = rq + j < r1;
+      floatx4 xv[KT], zv[NT];
+      if constexpr (ONEHOT) {
+        const int4 gq = group ? *(const int4 *)(group + rq) : make_int4(0, 0, 0, 0);
+        const int gg[4] = {gq.x, gq.y, gq.z, gq.w};
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xv[kt][j] = (rv[j] && gg[j] == k0 + 16 * kt + col) ? 1.f : 0.f;
+      } else {
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int c = k0 + 16 * kt + col;
+          const floatx4 v = *(const floatx4 *)(Xt + (size_t)(c < kin ? c : 0) * ldr + base + rq);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xv[kt][j] = (rv[j] && c < kin) ? v[j] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int c = n0 + 16 * nt + col;
+        const floatx4 v = *(const floatx4 *)(Zt + (size_t)(c < nout ? c : 0) * ldr + base + rq);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zv[nt][j] = (rv[j] && c < nout) ? v[j] : 0.f;
+      }
+      if constexpr (BF) {
+        bf16x4 xb[KT], zb[NT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) xb[kt] = __builtin_convertvector(xv[kt], bf16x4);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) zb[nt] = __builtin_convertvector(zv[nt], bf16x4);
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[kt][nt] =
+                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xb[kt], zb[nt], acc[kt][nt], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              acc[kt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[kt][j], zv[nt][j],
+                                                                  acc[kt][nt], 0, 0, 0);
+      }
     }
   }
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w][((kt * NT + nt) * 4 + v) * 64 + lane] = acc[kt][nt][v];
   __syncthreads();
-  for (int e = t; e < ngroups * ncol; e += 256) {
-    float s = 0.f;
-    for (int k = 0; k < slices; ++k) s += sacc[(size_t)k * ngroups * ncol + e];
-    part[(size_t)blockIdx.x * ngroups * ncol + e] = s;
+  for (int e = threadIdx.x; e < KT * NT * 256; e += 256) {
+    const float sum = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    const int l = e & 63, v = (e >> 6) & 3, tile = e >> 8;
+    const int kt = tile / NT, nt = tile % NT;
+    const int ki = k0 + 16 * kt + 4 * (l >> 4) + v, nj = n0 + 16 * nt + (l & 15);
+    if (ki < kin_pad && nj < nout_pad)
+      part[((size_t)blockIdx.x * kin_pad + ki) * nout_pad + nj] = sum;
   }
 }
 
-__global__ void k_sum_parts(const float *__restrict__ part, int nblk, int n,
-                            double *__restrict__ acc) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// acc[k][n] += sum_b part[b][k][n] in a fixed order: thread (slice, e) sums
+// the blocks b = slice (mod 16) of output e in FP64, then the 16 slices are
+// added in slice order.
+__global__ __launch_bounds__(256) void k_reduce_parts(const float *__restrict__ part, int nblk,
+                                                      int kin_pad, int nout_pad, int kin,
+                                                      int nout, double *__restrict__ acc) {
+  __shared__ double red[16][16];
+  const int el = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int e = blockIdx.x * 16 + el;
+  const bool ok = e < kin * nout;
+  const int k = ok ? e / nout : 0, n = ok ? e % nout : 0;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * n + e];
-  acc[e] += s;
+  for (int b = sl; b < nblk; b += 16) s += (double)part[((size_t)b * kin_pad + k) * nout_pad + n];
+  red[sl][el] = s;
+  __syncthreads();
+  if (sl == 0 && ok) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q][el];
+    acc[e] += t;
+  }
 }
 
 // --------------------------------------------------------------------- Adam
@@ -686,24 +831,50 @@ __global__ __launch_bounds__(256) void k_force_error(const double *__restrict__ 
 
 inline unsigned nblk(size_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int KT, int NT>
+template <int KT, int NT, bool ONEHOT>
 void wgrad_t(const float *X1, const float *X2, int ldx, const float *Z1, const float *Z2, int ldz,
-             int kin, int nout, const int *rows_dev, int rows_max, int bf16, float *part,
-             size_t part_cap, double *acc, hipStream_t s) {
+             int kin, int nout, const int *rows_dev, int rows_max, int bf16,
+             const int32_t *group, float *part, size_t part_cap, double *acc, hipStream_t s) {
   const int kin_pad = (kin + 15) / 16 * 16, nout_pad = (nout + 15) / 16 * 16;
   const int gy = (kin + 16 * KT - 1) / (16 * KT), gz = (nout + 16 * NT - 1) / (16 * NT);
   const size_t per = (size_t)kin_pad * nout_pad;
-  int rpb = 1024;
+  // about two row blocks per compute unit, each a multiple of 64 rows
+  int rpb = std::max(1024, (rows_max + 511) / 512);
+  rpb = (rpb + 63) / 64 * 64;
   while ((size_t)((rows_max + rpb - 1) / rpb) * per > part_cap) rpb *= 2;
   const int gx = std::max(1, (rows_max + rpb - 1) / rpb);
   const dim3 grid(gx, gy, gz);
-  if (bf16)
-    hipLaunchKernelGGL((k_wgrad<KT, NT, true>), grid, dim3(256), 0, s, X1, X2, ldx, Z1, Z2, ldz,
-                       kin, nout, rows_dev, rows_max, rpb, part, kin_pad, nout_pad);
+  if (bf16 && !ONEHOT)
+    hipLaunchKernelGGL((k_wgrad<KT, NT, true, false>), grid, dim3(256), 0, s, X1, X2, ldx, Z1, Z2,
+                       ldz, kin, nout, rows_dev, rows_max, rpb, group, part, kin_pad, nout_pad);
   else
-    hipLaunchKernelGGL((k_wgrad<KT, NT, false>), grid, dim3(256), 0, s, X1, X2, ldx, Z1, Z2, ldz,
-                       kin, nout, rows_dev, rows_max, rpb, part, kin_pad, nout_pad);
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk((size_t)kin * nout, 256)), dim3(256), 0, s, part,
+    hipLaunchKernelGGL((k_wgrad<KT, NT, false, ONEHOT>), grid, dim3(256), 0, s, X1, X2, ldx, Z1,
+                       Z2, ldz, kin, nout, rows_dev, rows_max, rpb, group, part, kin_pad,
+                       nout_pad);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nblk((size_t)kin * nout, 16)), dim3(256), 0, s, part,
+                     gx, kin_pad, nout_pad, kin, nout, acc);
+}
+
+template <int KT, int NT, bool ONEHOT>
+void wgrad_fm_t(const float *Xt, const float *Zt, size_t ldr, size_t seg2, int kin, int nout,
+                const int *rows_dev, int rows_max, int bf16, const int32_t *group, float *part,
+                size_t part_cap, double *acc, hipStream_t s) {
+  const int kin_pad = (kin + 15) / 16 * 16, nout_pad = (nout + 15) / 16 * 16;
+  const int gy = (kin + 16 * KT - 1) / (16 * KT), gz = (nout + 16 * NT - 1) / (16 * NT);
+  const size_t per = (size_t)kin_pad * nout_pad;
+  // row blocks of a multiple of 64 rows, about four per compute unit
+  int rpb = std::max(512, (rows_max + 1023) / 1024);
+  rpb = (rpb + 63) / 64 * 64;
+  while ((size_t)((rows_max + rpb - 1) / rpb) * per > part_cap) rpb *= 2;
+  const int gx = std::max(1, (rows_max + rpb - 1) / rpb);
+  const dim3 grid(gx, gy, gz);
+  if (bf16 && !ONEHOT)
+    hipLaunchKernelGGL((k_wgrad_fm<KT, NT, true, false>), grid, dim3(256), 0, s, Xt, Zt, ldr,
+                       seg2, kin, nout, rows_dev, rows_max, rpb, group, part, kin_pad, nout_pad);
+  else
+    hipLaunchKernelGGL((k_wgrad_fm<KT, NT, false, ONEHOT>), grid, dim3(256), 0, s, Xt, Zt, ldr,
+                       seg2, kin, nout, rows_dev, rows_max, rpb, group, part, kin_pad, nout_pad);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nblk((size_t)kin * nout, 16)), dim3(256), 0, s, part,
                      gx, kin_pad, nout_pad, kin, nout, acc);
 }
 
@@ -747,11 +918,18 @@ void launch_tr_fit_l0(const float *t1, const float *zd1, const float *yb1, const
 }
 
 void launch_tr_pair_rev(const TrainPairArgs &a, const float4 *delta, const float *Td,
-                        const float *Db, int ldD, size_t Pcap, float *X3, float *Z3, float *X2,
-                        float *Z2, float *Z1, float *WS1, int *grp, hipStream_t s) {
+                        const float *Db, int ldD, size_t Pcap, size_t ldr, float *X3, float *Z3,
+                        float *X2, float *Z2, float *Z1, float *WS1, float *HB2, int *grp,
+                        hipStream_t s) {
   if (a.nloc <= 0) return;
   hipLaunchKernelGGL(k_tr_pair_rev, dim3(nblk(a.nloc, kWaves)), dim3(256), 0, s, a, delta, Td, Db,
-                     ldD, Pcap, X3, Z3, X2, Z2, Z1, WS1, grp);
+                     ldD, Pcap, ldr, X3, Z3, HB2, grp);
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned blocks = std::min<unsigned>(nblk((size_t)a.nloc * a.sel, 256), 8u * cus);
+  hipLaunchKernelGGL(k_tr_pair_rev2, dim3(blocks), dim3(256), 0, s, a, a.pair_off + a.nloc, Pcap,
+                     ldr, HB2, grp, X2, Z2, Z1, WS1);
 }
 
 void tr_wgrad(const float *X1, const float *X2, int ldx, const float *Z1, const float *Z2, int ldz,
@@ -759,29 +937,50 @@ void tr_wgrad(const float *X1, const float *X2, int ldx, const float *Z1, const 
               size_t part_cap, double *acc, hipStream_t s) {
   if (rows_max <= 0) return;
   if (kin <= 16 && nout <= 32)
-    wgrad_t<1, 2>(X1, X2, ldx, Z1, Z2, ldz, kin, nout, rows_dev, rows_max, bf16, part, part_cap,
-                  acc, s);
+    wgrad_t<1, 2, false>(X1, X2, ldx, Z1, Z2, ldz, kin, nout, rows_dev, rows_max, bf16, nullptr,
+                         part, part_cap, acc, s);
   else if (kin <= 32 && nout <= 64)
-    wgrad_t<2, 4>(X1, X2, ldx, Z1, Z2, ldz, kin, nout, rows_dev, rows_max, bf16, part, part_cap,
-                  acc, s);
+    wgrad_t<2, 4, false>(X1, X2, ldx, Z1, Z2, ldz, kin, nout, rows_dev, rows_max, bf16, nullptr,
+                         part, part_cap, acc, s);
   else
-    wgrad_t<4, 4>(X1, X2, ldx, Z1, Z2, ldz, kin, nout, rows_dev, rows_max, bf16, part, part_cap,
-                  acc, s);
+    wgrad_t<4, 4, false>(X1, X2, ldx, Z1, Z2, ldz, kin, nout, rows_dev, rows_max, bf16, nullptr,
+                         part, part_cap, acc, s);
+}
+
+void tr_wgrad_fm(const float *Xt, const float *Zt, size_t ldr, size_t seg2, int kin, int nout,
+                 const int *rows_dev, int rows_max, int bf16, float *part, size_t part_cap,
+                 double *acc, hipStream_t s) {
+  if (rows_max <= 0) return;
+  if (kin <= 16 && nout <= 32)
+    wgrad_fm_t<1, 2, false>(Xt, Zt, ldr, seg2, kin, nout, rows_dev, rows_max, bf16, nullptr,
+                            part, part_cap, acc, s);
+  else
+    wgrad_fm_t<2, 4, false>(Xt, Zt, ldr, seg2, kin, nout, rows_dev, rows_max, bf16, nullptr,
+                            part, part_cap, acc, s);
+}
+
+void tr_colsum_fm(const float *Zt, size_t ldr, int ncol, const int *rows_dev, int rows_max,
+                  const int32_t *group, int ngroups, float *part, size_t part_cap, double *acc,
+                  hipStream_t s) {
+  if (rows_max <= 0) return;
+  if (ngroups <= 16)
+    wgrad_fm_t<1, 4, true>(nullptr, Zt, ldr, 0, ngroups, ncol, rows_dev, rows_max, 0, group, part,
+                           part_cap, acc, s);
+  else
+    wgrad_fm_t<4, 4, true>(nullptr, Zt, ldr, 0, ngroups, ncol, rows_dev, rows_max, 0, group, part,
+                           part_cap, acc, s);
 }
 
 void tr_colsum(const float *Z, int ldz, int ncol, const int *rows_dev, int rows_max,
                const int32_t *group, int ngroups, float *part, size_t part_cap, double *acc,
                hipStream_t s) {
   if (rows_max <= 0) return;
-  const int slices = 256 / ncol;
-  int rpb = 2048;
-  const size_t per = (size_t)ngroups * ncol;
-  while ((size_t)((rows_max + rpb - 1) / rpb) * per > part_cap) rpb *= 2;
-  const int gx = (rows_max + rpb - 1) / rpb;
-  const size_t lds = (size_t)slices * ngroups * ncol * sizeof(float);
-  hipLaunchKernelGGL(k_colsum, dim3(gx), dim3(256), lds, s, Z, ldz, ncol, rows_dev, rows_max, rpb,
-                     group, ngroups, part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(per, 256)), dim3(256), 0, s, part, gx, (int)per, acc);
+  if (ngroups <= 16)
+    wgrad_t<1, 4, true>(nullptr, nullptr, 0, Z, nullptr, ldz, ngroups, ncol, rows_dev, rows_max,
+                        0, group, part, part_cap, acc, s);
+  else
+    wgrad_t<4, 4, true>(nullptr, nullptr, 0, Z, nullptr, ldz, ngroups, ncol, rows_dev, rows_max,
+                        0, group, part, part_cap, acc, s);
 }
 
 void launch_adam(float *theta, float *m, float *v, const double *g, int n, float lr, float b1,

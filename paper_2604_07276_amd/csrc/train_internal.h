@@ -27,8 +27,8 @@ struct TrainPairArgs {
   float inv_sel;
   const float *table;                // [ntypes][ntypes][16] first layer folded with the type embedding
   const float *ws;                   // [16] first-layer weight of s
-  const float *W2, *b2;              // [16][32], [32]  (row-major W[k][o])
-  const float *W3, *b3;              // [32][64], [64]
+  const float *W2t, *b2;             // [32][16] (W2 transposed: row o holds W2[:, o]), [32]
+  const float *W3t, *b3;             // [64][32], [64]
   int ntypes;
   const float *T;                    // [nloc][4][64] descriptor factor T
   int axis;
@@ -54,20 +54,34 @@ void launch_tr_fit_top(const float *t2, const float *y2, const float *yd1, const
 void launch_tr_fit_l0(const float *t1, const float *zd1, const float *yb1, const float *w_out,
                       const float *a, int nloc, int H, int ld, float *zb1, hipStream_t s);
 // Reverse sweep of the descriptor and the embedding net per pair; writes the
-// weight-gradient rows (primal rows [0, P), tangent rows [Pcap, Pcap + P)):
-//   X3 [.][32] = h2 | h2', Z3 [.][64] = z3-bar | z3'-bar,
-//   X2 [.][16] = h1 | h1', Z2 [.][32] = z2-bar | z2'-bar,
-//   Z1 [P][16] = z1-bar, WS1 [P][16] = ws-bar per pair, grp [P] = t_j * ntypes + t_i.
+// weight-gradient operands feature-major (feature f of pair row r at
+// f * ldr + r; primal rows [0, P), tangent rows [Pcap, Pcap + P)):
+//   X3 [32][ldr] = h2 | h2', Z3 [64][ldr] = z3-bar | z3'-bar,
+//   X2 [16][ldr] = h1 | h1', Z2 [32][ldr] = z2-bar | z2'-bar,
+//   Z1 [16][ldr] = z1-bar, WS1 [16][ldr] = ws-bar per pair (primal rows only),
+//   grp [P] = t_j * ntypes + t_i.
+// Pcap and ldr are multiples of 16.
+// HB2 [64][ldr] is scratch between the two passes (h2-bar | h2'-bar).
 void launch_tr_pair_rev(const TrainPairArgs &a, const float4 *delta, const float *Td,
-                        const float *Db, int ldD, size_t Pcap, float *X3, float *Z3, float *X2,
-                        float *Z2, float *Z1, float *WS1, int *grp, hipStream_t s);
+                        const float *Db, int ldD, size_t Pcap, size_t ldr, float *X3, float *Z3,
+                        float *X2, float *Z2, float *Z1, float *WS1, float *HB2, int *grp,
+                        hipStream_t s);
+// As tr_wgrad and tr_colsum for feature-major operands (Xt [kin][ldr], Zt
+// [nout][ldr], group [rows]); the second segment starts at row seg2 (0: none).
+void tr_wgrad_fm(const float *Xt, const float *Zt, size_t ldr, size_t seg2, int kin, int nout,
+                 const int *rows_dev, int rows_max, int bf16, float *part, size_t part_cap,
+                 double *acc, hipStream_t s);
+void tr_colsum_fm(const float *Zt, size_t ldr, int ncol, const int *rows_dev, int rows_max,
+                  const int32_t *group, int ngroups, float *part, size_t part_cap, double *acc,
+                  hipStream_t s);
 // acc[kin][nout] += sum_r X1[r]^T Z1[r] + X2[r]^T Z2[r] over r < rows (rows
 // from *rows_dev when set, else rows_max); FP32 (or BF16-operand) matrix-core
 // partials per row block, summed in fixed order in FP64.
 void tr_wgrad(const float *X1, const float *X2, int ldx, const float *Z1, const float *Z2, int ldz,
               int kin, int nout, const int *rows_dev, int rows_max, int bf16, float *part,
               size_t part_cap, double *acc, hipStream_t s);
-// acc[g][c] += sum over rows r with group[r] == g of Z[r][c] (group == nullptr: g = 0).
+// acc[g][c] += sum over rows r with group[r] == g of Z[r][c] (group == nullptr: g = 0),
+// as a matrix-core product with a generated one-hot operand; ngroups <= 64.
 void tr_colsum(const float *Z, int ldz, int ncol, const int *rows_dev, int rows_max,
                const int32_t *group, int ngroups, float *part, size_t part_cap, double *acc,
                hipStream_t s);
