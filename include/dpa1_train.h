@@ -76,6 +76,15 @@ int dp_train_params(const dp_trainer *t, double *params, int32_t *nparams);
 /* Write the current weights as a weights file usable by dp_create. */
 int dp_train_save(const dp_trainer *t, const char *path);
 
+/* Checkpoint and resume: the FP32 master weights, the Adam moments m and v
+ * and the step count, in a file of this library's own format (magic
+ * "DPA1TRN", int32 count and step, then three FP32 arrays).  Resuming into a
+ * trainer created from a model of the same shape continues the run exactly
+ * (the same later steps give bit-identical weights); DP_ERR_WEIGHTS when the
+ * file does not match the trainer. */
+int dp_train_checkpoint(const dp_trainer *t, const char *path);
+int dp_train_resume(dp_trainer *t, const char *path);
+
 void dp_train_destroy(dp_trainer *t);
 
 /* Audit helper: over n atoms, rmse_max [2] (host) = (sqrt(sum |a - b|^2 / (3n)),

@@ -27,7 +27,8 @@ EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
             "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error",
             # student trainer (include/dpa1_train.h)
             "dp_train_create", "dp_train_gradient", "dp_train_step", "dp_train_params",
-            "dp_train_save", "dp_train_destroy", "dp_force_error")
+            "dp_train_save", "dp_train_checkpoint", "dp_train_resume", "dp_train_destroy",
+            "dp_force_error")
 PREC_FP32 = 0
 PREC_BF16 = 1
 
@@ -79,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_train_step.argtypes = [P, P, P, P, I, I, P, P, D, P, P]
     lib.dp_train_params.argtypes = [P, P, P]
     lib.dp_train_save.argtypes = [P, ctypes.c_char_p]
+    lib.dp_train_checkpoint.argtypes = [P, ctypes.c_char_p]
+    lib.dp_train_resume.argtypes = [P, ctypes.c_char_p]
     lib.dp_train_destroy.argtypes = [P]
     lib.dp_train_destroy.restype = None
     lib.dp_force_error.argtypes = [P, P, I, P, P]
@@ -86,7 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist",
                  "dp_set_timing", "dp_kernel_times", "dp_model_info", "dp_train_create",
                  "dp_train_gradient", "dp_train_step", "dp_train_params", "dp_train_save",
-                 "dp_force_error"):
+                 "dp_train_checkpoint", "dp_train_resume", "dp_force_error"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -284,7 +287,15 @@ class Trainer:
         return out
 
     def save(self, path: str):
+        """Current weights as a weights file (usable by Model)."""
         _check(_lib.dp_train_save(self._h, path.encode()))
+
+    def checkpoint(self, path: str):
+        """FP32 masters, Adam moments and step count (resume continues exactly)."""
+        _check(_lib.dp_train_checkpoint(self._h, path.encode()))
+
+    def resume(self, path: str):
+        _check(_lib.dp_train_resume(self._h, path.encode()))
 
 
 def force_error(a, b, stream=None):

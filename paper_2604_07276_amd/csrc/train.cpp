@@ -515,6 +515,49 @@ int dp_train_save(const dp_trainer *t, const char *path) {
   return DP_OK;
 }
 
+int dp_train_checkpoint(const dp_trainer *t, const char *path) {
+  if (!t || !path) return fail(DP_ERR_ARG, "NULL argument");
+  HIP_TRY(hipSetDevice(t->m->device));
+  const size_t np = (size_t)t->nparams;
+  std::vector<float> mv(2 * np);
+  HIP_TRY(hipMemcpy(mv.data(), t->am, sizeof(float) * np, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(mv.data() + np, t->av, sizeof(float) * np, hipMemcpyDeviceToHost));
+  FILE *f = fopen(path, "wb");
+  if (!f) return fail(DP_ERR_WEIGHTS, "cannot write '%s'", path);
+  const int32_t head[2] = {t->nparams, t->adam_t};
+  bool ok = fwrite("DPA1TRN\0", 1, 8, f) == 8 && fwrite(head, sizeof(head), 1, f) == 1 &&
+            fwrite(t->theta_h.data(), sizeof(float), np, f) == np &&
+            fwrite(mv.data(), sizeof(float), 2 * np, f) == 2 * np;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? DP_OK : fail(DP_ERR_WEIGHTS, "short write to '%s'", path);
+}
+
+int dp_train_resume(dp_trainer *t, const char *path) {
+  if (!t || !path) return fail(DP_ERR_ARG, "NULL argument");
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(DP_ERR_WEIGHTS, "cannot open '%s'", path);
+  char magic[8] = {0};
+  int32_t head[2] = {0, 0};
+  const size_t np = (size_t)t->nparams;
+  std::vector<float> th(np), mv(2 * np);
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "DPA1TRN\0", 8) == 0 &&
+            fread(head, sizeof(head), 1, f) == 1 && head[0] == t->nparams && head[1] >= 0 &&
+            fread(th.data(), sizeof(float), np, f) == np &&
+            fread(mv.data(), sizeof(float), 2 * np, f) == 2 * np;
+  char extra;
+  ok = ok && fread(&extra, 1, 1, f) == 0;
+  fclose(f);
+  if (!ok) return fail(DP_ERR_WEIGHTS, "'%s' is not a checkpoint of this trainer", path);
+  HIP_TRY(hipSetDevice(t->m->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(t->theta, th.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t->am, mv.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t->av, mv.data() + np, sizeof(float) * np, hipMemcpyHostToDevice));
+  t->theta_h = th;
+  t->adam_t = head[1];
+  return load_weights_image(t->m, make_image(t), true);
+}
+
 void dp_train_destroy(dp_trainer *t) {
   if (!t) return;
   (void)hipSetDevice(t->m->device);

@@ -119,7 +119,11 @@ def time_steps(model, frames, types, box, reps: int, torch):
 
 
 def run(n_train=2000, n_eval=200, steps=2000, lr0=1e-3, lr1=1e-5, pref_e=1.0, pref_f=100.0,
-        precision="bf16", threshold=3e-2, audit_every=10, seed=0, out_weights=None, log=None):
+        precision="bf16", threshold=3e-2, audit_every=10, seed=0, out_weights=None, log=None,
+        target="dpa1"):
+    """The pipeline above.  ``target`` "dpa1" labels with the DPA-1 teacher;
+    "student" labels with the student architecture under other weights (a
+    target the student can represent exactly: a check of the training)."""
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("the student pipeline needs a GPU")
@@ -128,7 +132,12 @@ def run(n_train=2000, n_eval=200, steps=2000, lr0=1e-3, lr1=1e-5, pref_e=1.0, pr
     tmp = tempfile.mkdtemp()
     t_path = os.path.join(tmp, "teacher_seed0.bin")
     s_path = os.path.join(tmp, "student_seed1.bin")
-    synth.make_weights(t_path, seed=0)
+    if target == "dpa1":
+        synth.make_weights(t_path, seed=0)
+    elif target == "student":
+        synth.make_weights(t_path, seed=7, shape=synth.STUDENT_SHAPE)
+    else:
+        raise ValueError(f"unknown target {target!r}")
     synth.make_weights(s_path, seed=1, shape=synth.STUDENT_SHAPE)
     base = synth.protein_system(seed)
     n = len(base.coords)
@@ -241,9 +250,14 @@ def main(argv=None):
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="bf16")
     ap.add_argument("--threshold", type=float, default=3e-2)
     ap.add_argument("--save", default=None, help="write the trained student weights here")
+    ap.add_argument("--target", choices=("dpa1", "student"), default="dpa1",
+                    help="label with the DPA-1 teacher, or with the student architecture "
+                         "under other weights (a representable target)")
     args = ap.parse_args(argv)
     out = run(args.train_frames, args.eval_frames, args.steps, args.lr0, args.lr1, args.pref_e,
-              args.pref_f, args.precision, args.threshold, out_weights=args.save, log=sys.stderr)
+              args.pref_f, args.precision, args.threshold, out_weights=args.save, log=sys.stderr,
+              target=args.target)
+    out["target"] = args.target
     print(json.dumps(out), flush=True)
     return 0
 

@@ -167,3 +167,49 @@ def test_force_error_helper():
     rmse, mx = binding.force_error(torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda"))
     assert rmse == pytest.approx(np.sqrt(np.mean((a - b) ** 2)), rel=1e-12)
     assert mx == np.max(np.abs(a - b))
+
+
+def test_checkpoint_resume_continues_exactly(student_path, batch, tmp_path):
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base, frames, e_lab, f_lab = batch
+    x, t, el, fl = _device_batch(torch, base, frames, e_lab, f_lab)
+    a = binding.Trainer(student_path, RC, SEL, pref_e=PE, pref_f=PF)
+    for _ in range(3):
+        a.step(x, t, base.box, el, fl, 1e-3)
+    ck = str(tmp_path / "trainer.ckpt")
+    a.checkpoint(ck)
+    for _ in range(2):
+        a.step(x, t, base.box, el, fl, 1e-3)
+    b = binding.Trainer(student_path, RC, SEL, pref_e=PE, pref_f=PF)
+    b.resume(ck)
+    for _ in range(2):
+        b.step(x, t, base.box, el, fl, 1e-3)
+    assert np.array_equal(a.params(), b.params())
+    c = binding.Trainer(student_path, RC, SEL)
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"DPA1TRN\0" + b"\0" * 8)
+    with pytest.raises(binding.DPError):
+        c.resume(str(bad))
+    for tr in (a, b, c):
+        tr.close()
+
+
+def test_force_only_training_learns_realisable_forces(student_path, batch, tmp_path):
+    """The force term alone trains: forces of the same architecture with other
+    weights are learned (loss down by an order of magnitude in 40 steps)."""
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base, frames, _, _ = batch
+    tgt = str(tmp_path / "target.bin")
+    synth.make_weights(tgt, seed=7, shape=synth.STUDENT_SHAPE)
+    m = binding.Model(tgt, RC, SEL)
+    f_lab = np.stack([m.compute(fr, base.types, base.box, len(fr), 0)[1] for fr in frames])
+    m.close()
+    x, t, el, fl = _device_batch(torch, base, frames, np.zeros(len(frames)), f_lab)
+    tr = binding.Trainer(student_path, RC, SEL, pref_e=0.0, pref_f=PF,
+                         precision=binding.PREC_BF16)
+    losses = [tr.step(x, t, base.box, el, fl, 1e-3)[2] for _ in range(40)]
+    tr.close()
+    print("force loss", losses[0], "->", losses[-1], flush=True)
+    assert losses[-1] < 0.1 * losses[0]
