@@ -84,6 +84,41 @@ def flop_model(nnei: np.ndarray, shape) -> dict:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_protein15668_fp32_step.md")
 
 
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
+
+
+def byte_model(nnei: np.ndarray, shape) -> dict:
+    """Algorithmic HBM bytes per step of the attention and projection kernels.
+
+    The FP32 inputs each kernel must read and the outputs it must write, at
+    the real widths (M = embedding width, d = attention width), once each;
+    the stored logits lam (n per query row) and softmax statistics are part
+    of the forward's output and the backward's input.  Returns
+    {kernel: (bytes per step, launches per step)}.
+    """
+    P = float(nnei.sum())
+    M, d, L = shape["M"], shape["dattn"], shape["n_attn"]
+    f4 = 4.0
+    out = {
+        "qkv_fwd": (L * P * f4 * (M + 3 * d), L),
+        "qkv_bwd": (L * P * f4 * (3 * d + M + 2 * M + 1 + 2 * M), L),
+        "oproj_ln_fwd": (L * P * f4 * (d + M + 2 * M + 1), L),
+        "oproj_bwd": (L * P * f4 * (M + d), L),
+    }
+    nn = nnei.astype(np.float64)
+    for c, npad in enumerate((32, 64, 96, 128)):
+        sel_c = (nnei > npad - 32) & (nnei <= npad)
+        Pc = float(nn[sel_c].sum())
+        n2c = float((nn[sel_c] ** 2).sum())
+        # fwd: Q, K, V, gate (rhat, sw) in; o, lam, (m, 1/Z) out
+        out[f"attn_fwd_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + d + 2) + f4 * n2c), L)
+        # bwd_q: K, V, dO, o, gate, (m, 1/Z), lam in; dQ, (m, 1/Z, D_q), query sums out
+        out[f"attn_bwd_q_n{npad}"] = (L * (Pc * f4 * (5 * d + 4 + 2 + d + 4 + 4) + f4 * n2c), L)
+        # bwd_k: Q, V, dO, gate, stats, query sums, lam in; dK, dV, dE/dsw, dE/drhat out
+        out[f"attn_bwd_k_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + 4 + 4 + 2 * d + 4) + f4 * n2c), L)
+    return out
+
+
 def source_hash() -> str:
     """Hash of the library sources; HBM counters are only valid for the build they came from."""
     h = hashlib.sha256()
@@ -276,10 +311,22 @@ def main():
         avg_s = ms / cnt * 1e-3
         per_launch = flops[dom][0] / flops[dom][1]
         achieved = per_launch / avg_s / 1e12
+        frac_mfma = achieved / FP32_MFMA_PEAK_TFLOPS
+        bytes_model = byte_model(nnei, shape)
+        bytes_launch = (bytes_model[dom][0] / bytes_model[dom][1]) if dom in bytes_model else None
+        gbps = None if bytes_launch is None else bytes_launch / avg_s / 1e9
+        frac_hbm = None if gbps is None else gbps / HBM_PEAK_GBPS
+        # the kernel's bound is the roof it is closer to
+        use_hbm = frac_hbm is not None and frac_hbm > frac_mfma
         tr = measured_traffic(dom)
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
-                    "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+        roofline = {"bound": "hbm" if use_hbm else "mfma", "kernel": dom,
+                    "achieved": round(gbps if use_hbm else achieved, 2),
+                    "peak": HBM_PEAK_GBPS if use_hbm else FP32_MFMA_PEAK_TFLOPS,
+                    "unit": "GB/s" if use_hbm else "TFLOP/s",
+                    "frac": round(frac_hbm if use_hbm else frac_mfma, 4),
+                    "frac_mfma": round(frac_mfma, 4),
+                    "frac_hbm": None if frac_hbm is None else round(frac_hbm, 4),
+                    "algorithmic_bytes_per_launch": bytes_launch,
                     "traffic": None if tr is None else tr[0] + tr[1],
                     "traffic_fetch_bytes": None if tr is None else tr[0],
                     "traffic_write_bytes": None if tr is None else tr[1],
