@@ -309,19 +309,14 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   }
 }
 
-template <class F>
-bool dispatch(int c0, int c1, int c2, F f) {
-  if (c0 == 2 && c1 == 4 && c2 == 7) {
-    f.template operator()<2, 4, 7>();
-    return true;
-  }
-  return false;
-}
+// Instantiated widths (padded to 16): the benchmark model's 32/64/112
+// (25/50/100) and the distilled student's 16/32/64.
+bool is_student_widths(int ld0, int ld1, int ld2) { return ld0 == 16 && ld1 == 32 && ld2 == 64; }
 
 }  // namespace
 
 bool emb_fused_supported(int ld0, int ld1, int ld2) {
-  return ld0 == 32 && ld1 == 64 && ld2 == 112;
+  return (ld0 == 32 && ld1 == 64 && ld2 == 112) || is_student_widths(ld0, ld1, ld2);
 }
 
 void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
@@ -329,7 +324,12 @@ void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
             e.Pptr};
   const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
   if (blocks == 0) return;
-  if (e.bf16)
+  const bool st = is_student_widths(pad16(e.n0), pad16(e.n1), pad16(e.n2));
+  if (st && e.bf16)
+    hipLaunchKernelGGL((k_emb_fwd<1, 2, 4, true>), dim3(blocks), dim3(256), 0, s, a, G0);
+  else if (st)
+    hipLaunchKernelGGL((k_emb_fwd<1, 2, 4, false>), dim3(blocks), dim3(256), 0, s, a, G0);
+  else if (e.bf16)
     hipLaunchKernelGGL((k_emb_fwd<2, 4, 7, true>), dim3(blocks), dim3(256), 0, s, a, G0);
   else
     hipLaunchKernelGGL((k_emb_fwd<2, 4, 7, false>), dim3(blocks), dim3(256), 0, s, a, G0);
@@ -340,7 +340,12 @@ void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t
             e.Pptr};
   const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
   if (blocks == 0) return;
-  if (e.bf16)
+  const bool st = is_student_widths(pad16(e.n0), pad16(e.n1), pad16(e.n2));
+  if (st && e.bf16)
+    hipLaunchKernelGGL((k_emb_bwd<1, 2, 4, true>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+  else if (st)
+    hipLaunchKernelGGL((k_emb_bwd<1, 2, 4, false>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+  else if (e.bf16)
     hipLaunchKernelGGL((k_emb_bwd<2, 4, 7, true>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
   else
     hipLaunchKernelGGL((k_emb_bwd<2, 4, 7, false>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);

@@ -272,7 +272,9 @@ def test_replication_2x2x1(model):
 @pytest.mark.parametrize("tag,shape", [
     # embedding widths that take the unfused paths: per-layer embedding GEMMs
     # and the stand-alone output-projection + layer-norm GEMM (padded width 64)
-    ("emb16-32-64_attn1", dict(emb=(16, 32, 64), n_attn=1, fit=(120, 120))),
+    ("emb24-48-64_attn1", dict(emb=(24, 48, 64), n_attn=1, fit=(120, 120))),
+    # the distilled student's shape: fused 16/32/64 embedding, no attention
+    ("student_dpse", dict(emb=(16, 32, 64), axis=8, n_attn=0, fit=(128, 128))),
     # widths 25 -> 50 -> 50: identity residual in the last embedding layer
     ("emb25-50-50_attn2", dict(emb=(25, 50, 50), n_attn=2, fit=(64, 64, 64))),
     # no attention layer: the descriptor takes the embedding output directly
