@@ -284,12 +284,16 @@ constexpr int stage_floats() {
 // own query rows and the outputs.  The scaled dot products lam = q.k/sqrt(d)
 // (row stride kLamLd, all NPAD key columns of every query row) and the
 // softmax statistics (m, 1/Z) of every query are stored for the adjoint,
-// which then does not recompute Q K^T.
+// which then does not recompute Q K^T.  The forward and the key-tile adjoint
+// issue the next centre's staging loads during their last phase, into
+// registers the current centre no longer needs, so that the HBM latency of a
+// centre's operands overlaps the previous centre's products (two workgroups
+// per compute unit leave the registers for it).
 
 constexpr int kLamLd = kAttnLamLd;
 
 template <int NPAD, bool BF>
-__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) void k_attn_fwd(
+__global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) : 2) void k_attn_fwd(
     const float *__restrict__ qkv, const float *__restrict__ geom,
     const int *__restrict__ pair_off, const int *__restrict__ nnei,
     const int *__restrict__ clist, const int *__restrict__ ccount, int sel, float shift,
@@ -301,22 +305,40 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;  // 1/sqrt(128)
   const int cnt = *ccount;
+  // FP32: the staging loads of a centre are issued during the A V phase of the
+  // previous one (BF16 holds more registers per tile and loads per centre)
+  constexpr bool PREF = !BF;
+  float4 sv[8];
+  floatx4 qv[8];
+  float4 gv;
+  int n_nx = 0, base_nx = 0;
+  if (PREF && (int)blockIdx.x < cnt) {
+    const int tid = fresh_tid();
+    const int i0 = clist[blockIdx.x];
+    n_nx = nnei[i0];
+    base_nx = pair_off[i0];
+    stage_rows_load<NPAD>(qkv + 128, ld, base_nx, n_nx, tid, sv);  // K
+    gv = gate_load(geom, base_nx, n_nx, tid);
+    load_rows(qkv, ld, base_nx, n_nx, (tid >> 6) * 16 + (tid & 15), (tid & 63) >> 4, qv);
+  }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const int tid = fresh_tid();
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int r = lane & 15, g = lane >> 4;
-    const int i = clist[it];
-    const int n = nnei[i];
-    const int base = pair_off[i];
+    if constexpr (!PREF) {
+      const int i = clist[it];
+      n_nx = nnei[i];
+      base_nx = pair_off[i];
+      stage_rows_load<NPAD>(qkv + 128, ld, base_nx, n_nx, tid, sv);  // K
+      gv = gate_load(geom, base_nx, n_nx, tid);
+      load_rows(qkv, ld, base_nx, n_nx, wave * 16 + r, g, qv);
+    }
+    const int n = n_nx;
+    const int base = base_nx;
     const int ntile = (n + 15) >> 4;
     const int q = wave * 16 + r;
     const bool qok = q < n;
-    float4 sv[8];
-    stage_rows_load<NPAD>(qkv + 128, ld, base, n, tid, sv);  // K
-    const float4 gv = gate_load(geom, base, n, tid);
-    floatx4 qv[8];
-    load_rows(qkv, ld, base, n, q, g, qv);
     stage_rows_store<NPAD>(buf, tid, n, sv);
     gate_store<NPAD>(kg, tid, n, gv);
     __syncthreads();
@@ -365,6 +387,17 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 
     __syncthreads();
     stage_t_store<NPAD>(buf, tid, n, vpre);  // V^T
     __syncthreads();
+    if constexpr (PREF) {
+      const int itn = it + (int)gridDim.x;
+      if (itn < cnt) {
+        const int inx = clist[itn];
+        n_nx = nnei[inx];
+        base_nx = pair_off[inx];
+        stage_rows_load<NPAD>(qkv + 128, ld, base_nx, n_nx, tid, sv);
+        gv = gate_load(geom, base_nx, n_nx, tid);
+        load_rows(qkv, ld, base_nx, n_nx, q, g, qv);
+      }
+    }
 
     if (wave < ntile) {
       const float4 gq = kg[q];
@@ -517,7 +550,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
 }
 
 template <int NPAD, bool BF>
-__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_k(
+__global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void k_attn_bwd_k(
     const float *__restrict__ qkv, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
     const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
@@ -532,27 +565,50 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
+  // FP32: the staging loads of a centre are issued during phase 2 of the
+  // previous one, and the Q rows of phase 2 during phase 1 (BF16 loads per
+  // centre and per phase)
+  constexpr bool PREF = !BF;
+  float4 sv[8];
+  floatx4 vreg[8];
+  float4 gv, av;
+  int n_nx = 0, base_nx = 0;
+  if (PREF && (int)blockIdx.x < cnt) {
+    const int tid = fresh_tid();
+    const int kk = (tid >> 6) * 16 + (tid & 15);
+    const int i0 = clist[blockIdx.x];
+    n_nx = nnei[i0];
+    base_nx = pair_off[i0];
+    stage_rows_load<NPAD>(dO, 128, base_nx, n_nx, tid, sv);  // dO
+    gv = gate_load(geom, base_nx, n_nx, tid);
+    av = astat[base_nx + (tid < n_nx ? tid : 0)];
+    load_rows(qkv + 256, ld, base_nx, n_nx, kk, (tid & 63) >> 4, vreg);
+  }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const int tid = fresh_tid();
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int r = lane & 15, g = lane >> 4;
-    const int i = clist[it];
-    const int n = nnei[i];
-    const int base = pair_off[i];
+    if constexpr (!PREF) {
+      const int i = clist[it];
+      n_nx = nnei[i];
+      base_nx = pair_off[i];
+      stage_rows_load<NPAD>(dO, 128, base_nx, n_nx, tid, sv);  // dO
+      gv = gate_load(geom, base_nx, n_nx, tid);
+      av = astat[base_nx + (tid < n_nx ? tid : 0)];
+      load_rows(qkv + 256, ld, base_nx, n_nx, wave * 16 + r, g, vreg);
+    }
+    const int n = n_nx;
+    const int base = base_nx;
     const int ntile = (n + 15) >> 4;
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
-    float4 sv[8];
-    stage_rows_load<NPAD>(dO, 128, base, n, tid, sv);  // dO
-    const float4 gv = gate_load(geom, base, n, tid);
-    const float4 av = astat[base + (tid < n ? tid : 0)];
-    floatx4 vreg[8];
-    load_rows(qkv + 256, ld, base, n, kk, g, vreg);
     stage_rows_store<NPAD>(buf, tid, n, sv);
     gate_store<NPAD>(kg, tid, n, gv);
     if (tid < NPAD) stats[tid] = tid < n ? av : make_float4(0.f, 1.f, 0.f, 0.f);
     __syncthreads();
+    float4 qpre[8];
+    if constexpr (PREF) stage_t_load<NPAD>(qkv, ld, base, n, tid, qpre);  // Q rows of phase 2
 
     // ---------------- phase 1: dA key-major, dV, dS and the key-side sums
     floatx4 ds[NT];
@@ -623,8 +679,21 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       drkz = sum_groups(drkz);
     }
     __syncthreads();
-    stage_t<NPAD>(qkv, ld, base, n, buf, tid);  // Q^T
+    if constexpr (!PREF) stage_t_load<NPAD>(qkv, ld, base, n, tid, qpre);
+    stage_t_store<NPAD>(buf, tid, n, qpre);  // Q^T
     __syncthreads();
+    if constexpr (PREF) {
+      const int itn = it + (int)gridDim.x;
+      if (itn < cnt) {
+        const int inx = clist[itn];
+        n_nx = nnei[inx];
+        base_nx = pair_off[inx];
+        stage_rows_load<NPAD>(dO, 128, base_nx, n_nx, tid, sv);
+        gv = gate_load(geom, base_nx, n_nx, tid);
+        av = astat[base_nx + (tid < n_nx ? tid : 0)];
+        load_rows(qkv + 256, ld, base_nx, n_nx, kk, g, vreg);
+      }
+    }
 
     // ---------------- phase 2: dK = dS^T Q
     if (wave < ntile) {
