@@ -809,14 +809,17 @@ __global__ __launch_bounds__(128) void k_desc_fwd(const float *__restrict__ geom
 // backward of the last embedding layer (ln_mode 1), or dG only (ln_mode 2).
 // Sixteen lanes share a pair (lane li holds features li + 16k), so the row
 // reductions take four cross-lane steps and four pairs run per wavefront.
+// KF features per lane (16 lanes x KF >= ldg); LN_MODE as ln_mode below, fixed
+// at compile time so that operands a mode does not use are never loaded.
+template <int KF, int LN_MODE>
 __global__ __launch_bounds__(256) void k_desc_bwd(
     const float *__restrict__ geom, const float *__restrict__ G, int ldg,
     const float *__restrict__ T, const float *__restrict__ dD, int ldd,
     const int *__restrict__ pair_off, const int *__restrict__ nnei, int sel, int M, int axis,
-    int ln_mode, const float *__restrict__ gamma, const float *__restrict__ xhat,
+    const float *__restrict__ gamma, const float *__restrict__ xhat,
     const float *__restrict__ rstd, const float *__restrict__ temb, float *__restrict__ dG,
     float *__restrict__ dnext, float *__restrict__ dRt) {
-  constexpr int KF = 8;  // features per lane: 16 lanes x 8 = 128 >= ldg
+  constexpr int ln_mode = LN_MODE;
   __shared__ float Ts[4][128];
   __shared__ float dTs[4][128];
   __shared__ float part[16][16][4];
@@ -880,9 +883,7 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
   const float invm = 1.0f / (float)M;
   // Every global load of a pair is issued before any of its values is used
   // and is unconditional: feature indices are clamped to the row (columns
-  // past M hold zeros), operands a mode does not use are read from G.
-  const float *xsrc = ln_mode == 0 ? xhat : G;
-  const float *tsrc = ln_mode == 1 ? temb : G;
+  // past M hold zeros).
   for (int j = grp; j < n; j += 16) {
     const size_t p = (size_t)(base + j);
     const float4 gq = *(const float4 *)(geom + p * kGeom);  // s, rx, ry, rz
@@ -892,10 +893,10 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
       const int m = li + 16 * k;
       const int mc = m < ldg ? m : 0;
       gm[k] = G[p * ldg + mc];
-      xv[k] = xsrc[p * ldg + mc];
-      tv[k] = tsrc[p * ldg + mc];
+      xv[k] = ln_mode == 0 ? xhat[p * ldg + mc] : 0.f;
+      tv[k] = ln_mode == 1 ? temb[p * ldg + mc] : 0.f;
     }
-    const float rs = (ln_mode == 0 ? rstd : geom)[p];
+    const float rs = ln_mode == 0 ? rstd[p] : 0.f;
     const float R0 = gq.x, R1 = gq.x * gq.y, R2 = gq.x * gq.z, R3 = gq.x * gq.w;
     float dg[KF];
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, s1 = 0.f, s2 = 0.f;
@@ -1091,8 +1092,10 @@ void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair
                      hipStream_t s) {
   if (nloc <= 0) return;
   const int ldd = pad16(M * axis);
-  hipLaunchKernelGGL(k_desc_fwd, dim3(nloc), dim3(128), 0, s, geom, G, ldg, pair_off, nnei, sel,
-                     M, axis, T, dmat, ldd);
+  // one lane per feature: a single wavefront when M <= 64
+  const int threads = M <= 64 ? 64 : 128;
+  hipLaunchKernelGGL(k_desc_fwd, dim3(nloc), dim3(threads), 0, s, geom, G, ldg, pair_off, nnei,
+                     sel, M, axis, T, dmat, ldd);
 }
 
 void launch_desc_bwd(const float *geom, const float *G, int ldg, const float *T,
@@ -1102,9 +1105,26 @@ void launch_desc_bwd(const float *geom, const float *G, int ldg, const float *T,
                      float *dRt, hipStream_t s) {
   if (nloc <= 0) return;
   const int ldd = pad16(M * axis);
-  hipLaunchKernelGGL(k_desc_bwd, dim3(nloc), dim3(256), 0, s, geom, G, ldg, T, dD, ldd,
-                     pair_off, nnei, sel, M, axis, ln_mode, gamma, xhat, rstd, t_emb, dG, dnext,
-                     dRt);
+#define DESC_BWD(KF, MODE)                                                                  \
+  hipLaunchKernelGGL((k_desc_bwd<KF, MODE>), dim3(nloc), dim3(256), 0, s, geom, G, ldg, T, dD, \
+                     ldd, pair_off, nnei, sel, M, axis, gamma, xhat, rstd, t_emb, dG, dnext,   \
+                     dRt)
+  if (ldg <= 64) {
+    if (ln_mode == 0)
+      DESC_BWD(4, 0);
+    else if (ln_mode == 1)
+      DESC_BWD(4, 1);
+    else
+      DESC_BWD(4, 2);
+  } else {
+    if (ln_mode == 0)
+      DESC_BWD(8, 0);
+    else if (ln_mode == 1)
+      DESC_BWD(8, 1);
+    else
+      DESC_BWD(8, 2);
+  }
+#undef DESC_BWD
 }
 
 }  // namespace dpa1
