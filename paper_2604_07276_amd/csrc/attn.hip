@@ -284,11 +284,11 @@ constexpr int stage_floats() {
 // own query rows and the outputs.  The scaled dot products lam = q.k/sqrt(d)
 // (row stride kLamLd, all NPAD key columns of every query row) and the
 // softmax statistics (m, 1/Z) of every query are stored for the adjoint,
-// which then does not recompute Q K^T.  The forward and the key-tile adjoint
-// issue the next centre's staging loads during their last phase, into
-// registers the current centre no longer needs, so that the HBM latency of a
-// centre's operands overlaps the previous centre's products (two workgroups
-// per compute unit leave the registers for it).
+// which then does not recompute Q K^T.  The FP32 forward issues the next
+// centre's staging loads during its last phase, into registers the current
+// centre no longer needs, so that the HBM latency of a centre's operands
+// overlaps the previous centre's products (two workgroups per compute unit
+// leave the registers for it).
 
 constexpr int kLamLd = kAttnLamLd;
 
@@ -565,41 +565,23 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
-  // FP32: the staging loads of a centre are issued during phase 2 of the
-  // previous one, and the Q rows of phase 2 during phase 1 (BF16 loads per
-  // centre and per phase)
+  // FP32: the Q rows of phase 2 are loaded during phase 1 (BF16 loads them
+  // after phase 1, holding fewer registers)
   constexpr bool PREF = !BF;
-  float4 sv[8];
-  floatx4 vreg[8];
-  float4 gv, av;
-  int n_nx = 0, base_nx = 0;
-  if (PREF && (int)blockIdx.x < cnt) {
-    const int tid = fresh_tid();
-    const int kk = (tid >> 6) * 16 + (tid & 15);
-    const int i0 = clist[blockIdx.x];
-    n_nx = nnei[i0];
-    base_nx = pair_off[i0];
-    stage_rows_load<NPAD>(dO, 128, base_nx, n_nx, tid, sv);  // dO
-    gv = gate_load(geom, base_nx, n_nx, tid);
-    av = astat[base_nx + (tid < n_nx ? tid : 0)];
-    load_rows(qkv + 256, ld, base_nx, n_nx, kk, (tid & 63) >> 4, vreg);
-  }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const int tid = fresh_tid();
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int r = lane & 15, g = lane >> 4;
-    if constexpr (!PREF) {
-      const int i = clist[it];
-      n_nx = nnei[i];
-      base_nx = pair_off[i];
-      stage_rows_load<NPAD>(dO, 128, base_nx, n_nx, tid, sv);  // dO
-      gv = gate_load(geom, base_nx, n_nx, tid);
-      av = astat[base_nx + (tid < n_nx ? tid : 0)];
-      load_rows(qkv + 256, ld, base_nx, n_nx, wave * 16 + r, g, vreg);
-    }
-    const int n = n_nx;
-    const int base = base_nx;
+    const int i = clist[it];
+    const int n = nnei[i];
+    const int base = pair_off[i];
+    float4 sv[8];
+    stage_rows_load<NPAD>(dO, 128, base, n, tid, sv);  // dO
+    const float4 gv = gate_load(geom, base, n, tid);
+    const float4 av = astat[base + (tid < n ? tid : 0)];
+    floatx4 vreg[8];
+    load_rows(qkv + 256, ld, base, n, wave * 16 + r, g, vreg);
     const int ntile = (n + 15) >> 4;
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
@@ -682,18 +664,6 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     if constexpr (!PREF) stage_t_load<NPAD>(qkv, ld, base, n, tid, qpre);
     stage_t_store<NPAD>(buf, tid, n, qpre);  // Q^T
     __syncthreads();
-    if constexpr (PREF) {
-      const int itn = it + (int)gridDim.x;
-      if (itn < cnt) {
-        const int inx = clist[itn];
-        n_nx = nnei[inx];
-        base_nx = pair_off[inx];
-        stage_rows_load<NPAD>(dO, 128, base_nx, n_nx, tid, sv);
-        gv = gate_load(geom, base_nx, n_nx, tid);
-        av = astat[base_nx + (tid < n_nx ? tid : 0)];
-        load_rows(qkv + 256, ld, base_nx, n_nx, kk, g, vreg);
-      }
-    }
 
     // ---------------- phase 2: dK = dS^T Q
     if (wave < ntile) {

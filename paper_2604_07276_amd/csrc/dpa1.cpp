@@ -157,7 +157,7 @@ int dpa1::load_weights_image(dp_model *m, const std::vector<char> &buf, bool ref
     return fail(DP_ERR_WEIGHTS, "axis width must be in [1, min(16, M)]");
   if (m->n_attn < 0 || m->n_attn > 16) return fail(DP_ERR_WEIGHTS, "bad attention layer count");
   if (m->n_attn > 0 && m->dattn != 128)
-    return fail(DP_ERR_WEIGHTS, "attention width %d unsupported (this build: 128)", m->dattn);
+    return fail(DP_ERR_WEIGHTS, "attention width %d unsupported (the attention kernels take 128)", m->dattn);
   const int x0 = 1 + 2 * m->tebd;
   if (residual_rule(x0, m->emb[0]) != RES_NONE)
     return fail(DP_ERR_WEIGHTS, "a residual on the first embedding layer is unsupported");
