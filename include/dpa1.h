@@ -141,6 +141,22 @@ int dp_backward_device(dp_model *m, const double *d_atom_weight, double *d_grad_
 enum dp_precision { DP_PREC_FP32 = 0, DP_PREC_BF16 = 1 };
 int dp_set_precision(dp_model *m, int precision);
 
+/* Memory budget of the workspace in bytes (0: unlimited, the default).  When
+ * storing the activations of every attention layer for the adjoint would make
+ * the workspace exceed it, the attention layers share one set of QKV,
+ * attention-output, logit and softmax-statistics buffers and the adjoint
+ * recomputes each earlier layer's forward from its stored input just before
+ * that layer's backward: the results are bit-identical, at the cost of about
+ * one attention forward per extra layer.  A step whose workspace exceeds the
+ * budget even so returns DP_ERR_OOM.  Takes effect at the next step (the
+ * workspace is released and laid out again); waits for the handle's last
+ * step.  Returns DP_ERR_ARG for a negative or non-finite budget. */
+int dp_set_memory_budget(dp_model *m, double bytes);
+
+/* Workspace bytes currently allocated and whether the attention activations
+ * are recomputed in the adjoint (1) or stored per layer (0). */
+int dp_memory_info(const dp_model *m, int64_t *workspace_bytes, int32_t *recompute);
+
 /* Wait for the handle's last step and return its device-side status. */
 int dp_sync(dp_model *m);
 

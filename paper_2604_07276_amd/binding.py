@@ -23,8 +23,9 @@ STATUS_NAMES = {
     -5: "DP_ERR_WEIGHTS", -6: "DP_ERR_DEVICE", -7: "DP_ERR_OOM",
 }
 EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
-            "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist", "dp_set_timing",
-            "dp_kernel_times", "dp_model_info", "dp_destroy", "dp_last_error",
+            "dp_backward_device", "dp_set_precision", "dp_set_memory_budget", "dp_memory_info",
+            "dp_sync", "dp_debug_nlist", "dp_set_timing", "dp_kernel_times", "dp_model_info",
+            "dp_destroy", "dp_last_error",
             # student trainer (include/dpa1_train.h)
             "dp_train_create", "dp_train_gradient", "dp_train_step", "dp_train_params",
             "dp_train_save", "dp_train_checkpoint", "dp_train_resume", "dp_train_destroy",
@@ -65,6 +66,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_forward_device.argtypes = [P, P, P, P, I, I, P, P, P]
     lib.dp_backward_device.argtypes = [P, P, P, P, P]
     lib.dp_set_precision.argtypes = [P, I]
+    lib.dp_set_memory_budget.argtypes = [P, D]
+    lib.dp_memory_info.argtypes = [P, P, P]
     lib.dp_sync.argtypes = [P]
     lib.dp_debug_nlist.argtypes = [P, P, P]
     lib.dp_set_timing.argtypes = [P, I]
@@ -86,7 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_train_destroy.restype = None
     lib.dp_force_error.argtypes = [P, P, I, P, P]
     for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
-                 "dp_backward_device", "dp_set_precision", "dp_sync", "dp_debug_nlist",
+                 "dp_backward_device", "dp_set_precision", "dp_set_memory_budget",
+                 "dp_memory_info", "dp_sync", "dp_debug_nlist",
                  "dp_set_timing", "dp_kernel_times", "dp_model_info", "dp_train_create",
                  "dp_train_gradient", "dp_train_step", "dp_train_params", "dp_train_save",
                  "dp_train_checkpoint", "dp_train_resume", "dp_force_error"):
@@ -194,6 +198,18 @@ class Model:
         """Operand precision of the matrix-core products (dp_set_precision):
         PREC_FP32 (default) or PREC_BF16 (BF16 operands, FP32 accumulation)."""
         _check(_lib.dp_set_precision(self._h, int(precision)))
+
+    def set_memory_budget(self, nbytes: float):
+        """Workspace budget in bytes (0: unlimited); above it the attention
+        activations are recomputed in the adjoint (dp_set_memory_budget)."""
+        _check(_lib.dp_set_memory_budget(self._h, float(nbytes)))
+
+    def memory_info(self):
+        """(workspace bytes, recompute flag) of the current workspace."""
+        b = ctypes.c_int64()
+        r = ctypes.c_int32()
+        _check(_lib.dp_memory_info(self._h, ctypes.byref(b), ctypes.byref(r)))
+        return int(b.value), bool(r.value)
 
     def sync(self):
         """Wait for the last step; raises on a device-side error (overflow, bad type)."""

@@ -327,7 +327,9 @@ struct Carver {
 
 // Lays out every buffer for the given capacity; with base == nullptr it only
 // measures.  Per-pair buffers hold nloc*sel rows plus one tile of slack.
-size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
+// With shared set, every attention layer uses one set of QKV, attention-
+// output, logit and softmax-statistics buffers (the adjoint recomputes them).
+size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell, bool shared) {
   Carver c{base};
   auto &w = m->w;
   const size_t P = (size_t)nloc * m->sel + 64;
@@ -368,10 +370,17 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
   w.G.assign(na + 1, nullptr);
   w.G[0] = w.h[ne - 1];
   for (int a = 0; a < na; ++a) {
-    w.qkv[a] = c.take<float>(P * 3 * m->dattn);
-    w.o[a] = c.take<float>(P * m->dattn);
-    w.lam[a] = c.take<float>(P * kAttnLamLd);
-    w.fstat[a] = c.take<float>(P * 2);
+    if (shared && a > 0) {
+      w.qkv[a] = w.qkv[0];
+      w.o[a] = w.o[0];
+      w.lam[a] = w.lam[0];
+      w.fstat[a] = w.fstat[0];
+    } else {
+      w.qkv[a] = c.take<float>(P * 3 * m->dattn);
+      w.o[a] = c.take<float>(P * m->dattn);
+      w.lam[a] = c.take<float>(P * kAttnLamLd);
+      w.fstat[a] = c.take<float>(P * 2);
+    }
     w.xhat[a] = c.take<float>(P * m->ldM);
     w.rstd[a] = c.take<float>(P);
     w.G[a + 1] = c.take<float>(P * m->ldM);
@@ -413,10 +422,22 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell) {
 }
 
 int ensure_workspace(dp_model *m, int nloc, int nall, int ncell) {
-  if (nloc <= m->cap_nloc && nall <= m->cap_nall && ncell <= m->cap_ncell) return DP_OK;
+  // the layout is fixed for the capacity until it grows or the budget changes
+  if (m->arena && nloc <= m->cap_nloc && nall <= m->cap_nall && ncell <= m->cap_ncell)
+    return DP_OK;
   const int cl = std::max(nloc, m->cap_nloc), ca = std::max(nall, m->cap_nall),
             cc = std::max(ncell, m->cap_ncell);
-  const size_t bytes = carve(m, nullptr, cl, ca, cc);
+  // layout: every layer's attention activations stored, unless that exceeds
+  // the memory budget (then shared buffers and recomputation in the adjoint);
+  // the measuring passes write null pointers, so the table is restored after
+  const dp_model::WS saved = m->w;
+  const size_t full = carve(m, nullptr, cl, ca, cc, false);
+  const bool shared = m->n_attn > 1 && m->mem_budget > 0 && (double)full > m->mem_budget;
+  const size_t bytes = shared ? carve(m, nullptr, cl, ca, cc, true) : full;
+  m->w = saved;
+  if (m->mem_budget > 0 && (double)bytes > m->mem_budget)
+    return fail(DP_ERR_OOM, "workspace of %zu bytes exceeds the memory budget of %.0f bytes%s",
+                bytes, m->mem_budget, m->n_attn > 1 ? " even with recomputation" : "");
   if (m->arena) {
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipFree(m->arena));
@@ -425,7 +446,9 @@ int ensure_workspace(dp_model *m, int nloc, int nall, int ncell) {
   HIP_TRY(hipMalloc(&m->arena, bytes));
   HIP_TRY(hipMemset(m->arena, 0, bytes));
   m->arena_bytes = bytes;
-  carve(m, (char *)m->arena, cl, ca, cc);
+  carve(m, (char *)m->arena, cl, ca, cc, shared);
+  m->recompute = shared;
+  m->fwd.valid = false;
   m->cap_nloc = cl;
   m->cap_nall = ca;
   m->cap_ncell = cc;
@@ -621,6 +644,7 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   m->have_step = true;
   m->last_nloc = nloc;
   m->fwd = dp_model::FwdState{d_coords, grid, nloc, nall, true};
+  m->shared_layer = na - 1;
   return DP_OK;
 }
 
@@ -691,6 +715,19 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   }
   for (int a = na - 1; a >= 0; --a) {
     const auto &A = m->attn[a];
+    if (m->recompute && m->shared_layer != a) {
+      // the shared buffers hold another layer: recompute this layer's forward
+      // from its stored input G[a] (the same kernels, so the same values)
+      GemmArgs r1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16};
+      RUN("qkv_fwd_recompute", gemm_linear(r1, A.b_qkv, w.qkv[a], 3 * D, s));
+      for (int cls = 0; cls < attn_class_count(sel); ++cls)
+        RUN("attn_fwd_recompute",
+            launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
+      GemmArgs r2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16};
+      RUN("oproj_ln_recompute", gemm_ln_res(r2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a],
+                                            ldM, w.G[a + 1], w.xhat[a], w.rstd[a], s));
+      m->shared_layer = a;
+    }
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
@@ -1005,6 +1042,31 @@ int dp_set_precision(dp_model *m, int precision) {
   if (m->last) (void)hipStreamSynchronize(m->last);
   m->bf16 = precision == DP_PREC_BF16;
   m->fwd.valid = false;  // a pending adjoint must come from a forward in the new mode
+  return DP_OK;
+}
+
+int dp_set_memory_budget(dp_model *m, double bytes) {
+  if (!m) return fail(DP_ERR_ARG, "model handle is NULL");
+  if (!(bytes >= 0) || !std::isfinite(bytes)) return fail(DP_ERR_ARG, "bad memory budget");
+  if (m->last) (void)hipStreamSynchronize(m->last);
+  m->mem_budget = bytes;
+  // the layout is chosen again at the next step
+  if (m->arena) {
+    int rc = set_device(m);
+    if (rc) return rc;
+    HIP_TRY(hipFree(m->arena));
+    m->arena = nullptr;
+    m->arena_bytes = 0;
+    m->cap_nloc = m->cap_nall = m->cap_ncell = -1;
+    m->fwd.valid = false;
+  }
+  return DP_OK;
+}
+
+int dp_memory_info(const dp_model *m, int64_t *workspace_bytes, int32_t *recompute) {
+  if (!m || !workspace_bytes || !recompute) return fail(DP_ERR_ARG, "NULL argument");
+  *workspace_bytes = (int64_t)m->arena_bytes;
+  *recompute = m->recompute ? 1 : 0;
   return DP_OK;
 }
 

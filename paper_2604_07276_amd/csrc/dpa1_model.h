@@ -113,6 +113,9 @@ struct dp_model {
   void *arena = nullptr;
   size_t arena_bytes = 0;
   int cap_nloc = -1, cap_nall = -1, cap_ncell = -1;
+  double mem_budget = 0;   // workspace budget in bytes (0: unlimited)
+  bool recompute = false;  // attention activations shared across layers, recomputed
+  int shared_layer = -1;   // layer whose activations the shared buffers hold
   struct WS {
     double *coords, *out_e, *out_f, *out_v, *out_ae, *vir_part;
     int32_t *types, *types_safe;

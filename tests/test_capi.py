@@ -97,3 +97,11 @@ def test_trainer_calls_reject_bad_arguments(weights_path):
     out = (ctypes.c_double * 2)()
     assert lib.dp_force_error(None, None, -1, out, None) == -1
     assert lib.dp_force_error(None, None, 0, out, None) == 0 and out[0] == 0.0
+
+
+def test_memory_budget_calls_reject_bad_arguments():
+    lib = binding.load_library()
+    assert lib.dp_set_memory_budget(None, 1.0) == -1
+    b = ctypes.c_int64()
+    r = ctypes.c_int32()
+    assert lib.dp_memory_info(None, ctypes.byref(b), ctypes.byref(r)) == -1
