@@ -119,13 +119,22 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
     return out
 
 
-def source_hash() -> str:
-    """Hash of the library sources; HBM counters are only valid for the build they came from."""
+def kernel_sources(kernel: str) -> list:
+    """Library sources that define a kernel's code and launch (the attention
+    kernels: attn.hip and the shared internal header; others: every source)."""
+    csrc = os.path.join(ROOT, "paper_2604_07276_amd", "csrc")
+    if kernel.startswith("attn_"):
+        return [os.path.join(csrc, "attn.hip"), os.path.join(csrc, "dpa1_internal.h")]
+    return sorted(f for f in glob.glob(os.path.join(csrc, "*"))
+                  if f.endswith((".hip", ".cpp", ".h")))
+
+
+def source_hash(kernel: str = "") -> str:
+    """Hash of a kernel's sources; HBM counters are only valid for the code they came from."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_07276_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".cpp", ".h")):
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for f in kernel_sources(kernel):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -139,7 +148,7 @@ def measured_traffic(kernel: str):
         return None
     m = re.search(r"bench-traffic: kernel=(\S+) source=(\S+) fetch_bytes=(\d+) write_bytes=(\d+)",
                   text)
-    if not m or m.group(1) != kernel or m.group(2) != source_hash():
+    if not m or m.group(1) != kernel or m.group(2) != source_hash(kernel):
         return None
     return int(m.group(3)), int(m.group(4))
 
