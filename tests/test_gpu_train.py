@@ -213,3 +213,28 @@ def test_force_only_training_learns_realisable_forces(student_path, batch, tmp_p
     tr.close()
     print("force loss", losses[0], "->", losses[-1], flush=True)
     assert losses[-1] < 0.1 * losses[0]
+
+
+def test_gradient_matches_oracle_open_boundaries(student_path):
+    """An open cluster (no box): the trainer takes the library's open-boundary
+    neighbour search; the gradient must still match the oracle."""
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    base = synth.open_cluster(80, 6.5, 5, seed=4)
+    frames = np.stack([synth.noisy_frame(base, k, 0.05) for k in range(2)])
+    rng = np.random.default_rng(8)
+    e_lab = rng.normal(0.0, 1.0, size=2)
+    f_lab = rng.normal(0.0, 0.05, size=frames.shape)
+    print("trainer gradient parity: open 80-atom cluster x 2 frames", flush=True)
+    model = orc.load_model(student_path)
+    (L, _, _), grads = tro.loss_and_grad(model, frames, base.types, None, e_lab, f_lab, RC, SEL,
+                                         PE, PF)
+    g_ref = tro.flatten(model, grads)
+    tr = binding.Trainer(student_path, RC, SEL, pref_e=PE, pref_f=PF)
+    x, t, el, fl = _device_batch(torch, base, frames, e_lab, f_lab)
+    loss, g = tr.gradient(x, t, None, el, fl)
+    tr.close()
+    assert loss[0] == pytest.approx(L, rel=1e-5)
+    rel = _per_tensor(model, g, g_ref)
+    bad = {k: v for k, v in rel.items() if not v <= 1e-4}
+    assert not bad, bad
