@@ -33,7 +33,7 @@ struct dp_trainer {
   // weights-file image: header bytes, then the tensors (FP64) in file order
   std::vector<char> header;
   std::vector<std::string> names;
-  std::vector<size_t> offs, sizes;
+  std::vector<size_t> offs;
   int nparams = 0;
   std::vector<float> theta_h;  // host copy of the masters
   float *theta = nullptr, *am = nullptr, *av = nullptr;
@@ -83,7 +83,6 @@ void tensor_list(const dp_model *m, dp_trainer *t) {
   auto add = [&](const std::string &n, size_t cnt) {
     t->names.push_back(n);
     t->offs.push_back(t->nparams);
-    t->sizes.push_back(cnt);
     t->nparams += (int)cnt;
   };
   const int T = m->ntypes, E = m->tebd;

@@ -798,10 +798,6 @@ __global__ void k_fill_f64(double *p, size_t n) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0.0;
 }
-__global__ void k_fill_f32(float *p, size_t n) {
-  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = 0.f;
-}
 
 __global__ __launch_bounds__(256) void k_force_error(const double *__restrict__ a,
                                                      const double *__restrict__ b, int n,
@@ -997,9 +993,6 @@ void launch_force_error(const double *a, const double *b, int n, double *part, h
 
 void launch_fill_f64(double *p, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill_f64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
-}
-void launch_fill_f32(float *p, size_t n, hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
 }
 
 }  // namespace dpa1

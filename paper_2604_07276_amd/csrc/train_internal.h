@@ -89,7 +89,6 @@ void tr_colsum(const float *Z, int ldz, int ncol, const int *rows_dev, int rows_
 void launch_adam(float *theta, float *m, float *v, const double *g, int n, float lr, float b1,
                  float b2, float eps, float bc1, float bc2, hipStream_t s);
 void launch_fill_f64(double *p, size_t n, hipStream_t s);
-void launch_fill_f32(float *p, size_t n, hipStream_t s);
 
 }  // namespace dpa1
 
