@@ -67,15 +67,46 @@ __device__ __forceinline__ float sum_rows(float v) {  // over the 16 lanes of a 
   return v;
 }
 
-// Load one 16x128 row tile as the MFMA B operand: lane holds row r,
-// features 16c + 4g + {0..3}.  Rows past n read row 0 of the centre (finite
-// values; every use of such a row is masked), so no load waits on a select.
-__device__ __forceinline__ void load_rows(const float *__restrict__ rows, int ld, int base,
-                                          int n, int row, int g, floatx4 (&v)[8]) {
-  const float *rb = rows + (size_t)base * ld;
+// Pair tensors (QKV, the attention output o, dO, dQKV) are stored FP32, or
+// BF16 in BF16 mode (SB), where they are only ever BF16 matrix-core operands
+// (the one elementwise use, D_q = dO . o, then sees the rounded values).
+// Offsets are in elements of the storage type.
+template <bool SB>
+__device__ __forceinline__ const float *pt_at(const float *base, size_t e) {
+  if constexpr (SB) return (const float *)((const __bf16 *)base + e);
+  else return base + e;
+}
+template <bool SB>
+__device__ __forceinline__ float *pt_at(float *base, size_t e) {
+  if constexpr (SB) return (float *)((__bf16 *)base + e);
+  else return base + e;
+}
+template <bool SB>
+__device__ __forceinline__ floatx4 ldp4(const float *p, int e) {
+  if constexpr (SB)
+    return __builtin_convertvector(*(const bf16x4 *)((const __bf16 *)p + e), floatx4);
+  else
+    return *(const floatx4 *)(p + e);
+}
+template <bool SB>
+__device__ __forceinline__ void stp4(float *p, int e, const floatx4 &v) {
+  if constexpr (SB)
+    *(bf16x4 *)((__bf16 *)p + e) = __builtin_convertvector(v, bf16x4);
+  else
+    *(floatx4 *)(p + e) = v;
+}
+
+// Load one 16x128 row tile (columns col..col+127) as the MFMA B operand:
+// lane holds row r, features 16c + 4g + {0..3}.  Rows past n read row 0 of
+// the centre (finite values; every use of such a row is masked), so no load
+// waits on a select.
+template <bool SB>
+__device__ __forceinline__ void load_rows(const float *__restrict__ rows, int col, int ld,
+                                          int base, int n, int row, int g, floatx4 (&v)[8]) {
+  const float *rb = pt_at<SB>(rows, (size_t)base * ld + col);
   const int off = (row < n ? row : 0) * ld + 4 * g;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) v[c] = *(const floatx4 *)(rb + off + 16 * c);
+  for (int c = 0; c < 8; ++c) v[c] = ldp4<SB>(rb, off + 16 * c);
 }
 
 // Row stride of the row-major LDS tiles: 128 features + 4 (with it, eight
@@ -91,9 +122,9 @@ constexpr int kLDR = 132;
 // every global load of a phase before it waits for any (a load whose value is
 // consumed at once, or a branch that overwrites it, serialises the latencies).
 // Rows past n read row 0 and are written as zeros (a select at the write).
-template <int NPAD>
-__device__ __forceinline__ void stage_rows_load(const float *__restrict__ src, int ld, int base,
-                                                int n, int tid, float4 (&v)[8]) {
+template <int NPAD, bool SB>
+__device__ __forceinline__ void stage_rows_load(const float *__restrict__ src, int col, int ld,
+                                                int base, int n, int tid, float4 (&v)[8]) {
   constexpr int THREADS = NPAD / 16 * 64;
   static_assert(NPAD * 32 / THREADS == 8, "eight float4 per thread");
 #pragma unroll
@@ -101,7 +132,8 @@ __device__ __forceinline__ void stage_rows_load(const float *__restrict__ src, i
     const int idx = tid + it * THREADS;
     const int row = idx >> 5, c4 = idx & 31;
     const int rr = row < n ? row : 0;
-    v[it] = *(const float4 *)(src + (size_t)(base + rr) * ld + 4 * c4);
+    const floatx4 x = ldp4<SB>(pt_at<SB>(src, (size_t)(base + rr) * ld + col + 4 * c4), 0);
+    v[it] = make_float4(x[0], x[1], x[2], x[3]);
   }
 }
 template <int NPAD>
@@ -126,15 +158,18 @@ __device__ __forceinline__ void stage_rows_store(float *X, int tid, int n, const
 // The load half and the LDS half are separate so that a kernel can issue the
 // loads one phase early (while the previous phase computes) and write LDS
 // after the barrier that frees the buffer.
-template <int NPAD>
-__device__ __forceinline__ void stage_t_load(const float *__restrict__ src, int ld, int base,
-                                             int n, int tid, float4 (&v)[8]) {
+template <int NPAD, bool SB>
+__device__ __forceinline__ void stage_t_load(const float *__restrict__ src, int col, int ld,
+                                             int base, int n, int tid, float4 (&v)[8]) {
   const int row = (tid >> 6) * 16 + (tid & 15);
   const int cq = (tid >> 4) & 3;
   const int rr = row < n ? row : 0;
-  const float *sp = src + (size_t)(base + rr) * ld + 4 * cq;
+  const float *sp = pt_at<SB>(src, (size_t)(base + rr) * ld + col + 4 * cq);
 #pragma unroll
-  for (int it = 0; it < 8; ++it) v[it] = *(const float4 *)(sp + 16 * it);
+  for (int it = 0; it < 8; ++it) {
+    const floatx4 x = ldp4<SB>(sp, 16 * it);
+    v[it] = make_float4(x[0], x[1], x[2], x[3]);
+  }
 }
 // rows past n (loaded from row 0) are written as zeros
 template <int NPAD>
@@ -151,13 +186,6 @@ __device__ __forceinline__ void stage_t_store(float *XT, int tid, int n, const f
     d[2 * LDT] = ok ? v[it].z : 0.f;
     d[3 * LDT] = ok ? v[it].w : 0.f;
   }
-}
-template <int NPAD>
-__device__ __forceinline__ void stage_t(const float *__restrict__ src, int ld, int base, int n,
-                                        float *XT, int tid) {
-  float4 v[8];
-  stage_t_load<NPAD>(src, ld, base, n, tid, v);
-  stage_t_store<NPAD>(XT, tid, n, v);
 }
 
 // Gate record of neighbour t = tid (rhat, sw; zeros past n), for kg[NPAD]:
@@ -317,9 +345,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
     const int i0 = clist[blockIdx.x];
     n_nx = nnei[i0];
     base_nx = pair_off[i0];
-    stage_rows_load<NPAD>(qkv + 128, ld, base_nx, n_nx, tid, sv);  // K
+    stage_rows_load<NPAD, BF>(qkv, 128, ld, base_nx, n_nx, tid, sv);  // K
     gv = gate_load(geom, base_nx, n_nx, tid);
-    load_rows(qkv, ld, base_nx, n_nx, (tid >> 6) * 16 + (tid & 15), (tid & 63) >> 4, qv);
+    load_rows<BF>(qkv, 0, ld, base_nx, n_nx, (tid >> 6) * 16 + (tid & 15), (tid & 63) >> 4, qv);
   }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const int tid = fresh_tid();
@@ -330,9 +358,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
       const int i = clist[it];
       n_nx = nnei[i];
       base_nx = pair_off[i];
-      stage_rows_load<NPAD>(qkv + 128, ld, base_nx, n_nx, tid, sv);  // K
+      stage_rows_load<NPAD, BF>(qkv, 128, ld, base_nx, n_nx, tid, sv);  // K
       gv = gate_load(geom, base_nx, n_nx, tid);
-      load_rows(qkv, ld, base_nx, n_nx, wave * 16 + r, g, qv);
+      load_rows<BF>(qkv, 0, ld, base_nx, n_nx, wave * 16 + r, g, qv);
     }
     const int n = n_nx;
     const int base = base_nx;
@@ -343,7 +371,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
     gate_store<NPAD>(kg, tid, n, gv);
     __syncthreads();
     float4 vpre[8];  // V, read while Q K^T and the softmax run
-    stage_t_load<NPAD>(qkv + 256, ld, base, n, tid, vpre);
+    stage_t_load<NPAD, BF>(qkv, 256, ld, base, n, tid, vpre);
 
     floatx4 st[NT];
     float invz = 0.f;
@@ -393,9 +421,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
         const int inx = clist[itn];
         n_nx = nnei[inx];
         base_nx = pair_off[inx];
-        stage_rows_load<NPAD>(qkv + 128, ld, base_nx, n_nx, tid, sv);
+        stage_rows_load<NPAD, BF>(qkv, 128, ld, base_nx, n_nx, tid, sv);
         gv = gate_load(geom, base_nx, n_nx, tid);
-        load_rows(qkv, ld, base_nx, n_nx, q, g, qv);
+        load_rows<BF>(qkv, 0, ld, base_nx, n_nx, q, g, qv);
       }
     }
 
@@ -417,9 +445,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
         accum_lds<NPAD, BF>(buf, kt, r, g, at, oacc);
       }
       if (qok) {
-        float *op = out + (size_t)(base + q) * 128 + 4 * g;
+        float *op = pt_at<BF>(out, (size_t)(base + q) * 128 + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(op + 16 * ft) = oacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(op, 16 * ft, oacc[ft]);
       }
     }
     __syncthreads();  // LDS is restaged for the next centre
@@ -467,11 +495,11 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const int q = wave * 16 + r;
     const bool qok = q < n;
     float4 sv[8];
-    stage_rows_load<NPAD>(qkv + 256, ld, base, n, tid, sv);  // V
+    stage_rows_load<NPAD, BF>(qkv, 256, ld, base, n, tid, sv);  // V
     const float4 gv = gate_load(geom, base, n, tid);
     floatx4 dov[8], ov[8];
-    load_rows(dO, 128, base, n, q, g, dov);
-    load_rows(o, 128, base, n, q, g, ov);
+    load_rows<BF>(dO, 0, 128, base, n, q, g, dov);
+    load_rows<BF>(o, 0, 128, base, n, q, g, ov);
     stage_rows_store<NPAD>(buf, tid, n, sv);
     gate_store<NPAD>(kg, tid, n, gv);
     __syncthreads();
@@ -484,7 +512,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       dq = sum_groups(dq);
     }
     float4 kpre[8];  // K, read while dA^T is formed
-    stage_t_load<NPAD>(qkv + 128, ld, base, n, tid, kpre);
+    stage_t_load<NPAD, BF>(qkv, 128, ld, base, n, tid, kpre);
 
     floatx4 da[NT];
     if (wave < ntile) qk_lds<NT, BF>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
@@ -540,9 +568,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       drqz = sum_groups(drqz);
       if (g == 0 && qok) qside[base + q] = make_float4(dwq, drqx, drqy, drqz);
       if (qok) {
-        float *dp = dqkv + (size_t)(base + q) * ld + 4 * g;
+        float *dp = pt_at<BF>(dqkv, (size_t)(base + q) * ld + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dqacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(dp, 16 * ft, dqacc[ft]);
       }
     }
     __syncthreads();  // LDS is restaged for the next centre
@@ -577,11 +605,11 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     const int n = nnei[i];
     const int base = pair_off[i];
     float4 sv[8];
-    stage_rows_load<NPAD>(dO, 128, base, n, tid, sv);  // dO
+    stage_rows_load<NPAD, BF>(dO, 0, 128, base, n, tid, sv);  // dO
     const float4 gv = gate_load(geom, base, n, tid);
     const float4 av = astat[base + (tid < n ? tid : 0)];
     floatx4 vreg[8];
-    load_rows(qkv + 256, ld, base, n, wave * 16 + r, g, vreg);
+    load_rows<BF>(qkv, 256, ld, base, n, wave * 16 + r, g, vreg);
     const int ntile = (n + 15) >> 4;
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
@@ -590,7 +618,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     if (tid < NPAD) stats[tid] = tid < n ? av : make_float4(0.f, 1.f, 0.f, 0.f);
     __syncthreads();
     float4 qpre[8];
-    if constexpr (PREF) stage_t_load<NPAD>(qkv, ld, base, n, tid, qpre);  // Q rows of phase 2
+    if constexpr (PREF) stage_t_load<NPAD, BF>(qkv, 0, ld, base, n, tid, qpre);  // Q rows of phase 2
 
     // ---------------- phase 1: dA key-major, dV, dS and the key-side sums
     floatx4 ds[NT];
@@ -651,9 +679,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
         __builtin_amdgcn_sched_barrier(0);
       }
       if (kok) {
-        float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
+        float *dp = pt_at<BF>(dqkv, (size_t)(base + kk) * ld + 256 + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(dp, 16 * ft, dvacc[ft]);
       }
       dwk = sum_groups(dwk);
       drkx = sum_groups(drkx);
@@ -661,7 +689,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
       drkz = sum_groups(drkz);
     }
     __syncthreads();
-    if constexpr (!PREF) stage_t_load<NPAD>(qkv, ld, base, n, tid, qpre);
+    if constexpr (!PREF) stage_t_load<NPAD, BF>(qkv, 0, ld, base, n, tid, qpre);
     stage_t_store<NPAD>(buf, tid, n, qpre);  // Q^T
     __syncthreads();
 
@@ -674,9 +702,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
       for (int qt = 0; qt < NT; ++qt)
         if (qt < ntile) accum_lds<NPAD, BF>(buf, qt, r, g, ds[qt], dkacc);
       if (kok) {
-        float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+        float *dp = pt_at<BF>(dqkv, (size_t)(base + kk) * ld + 128 + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(dp, 16 * ft, dkacc[ft]);
         if (g == 0) {
           const float4 qs = qsbuf[base + kk];
           const size_t p = (size_t)(base + kk);

@@ -610,12 +610,13 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift, m->bf16};
   for (int a = 0; a < na; ++a) {
     const auto &A = m->attn[a];
+    // in BF16 mode QKV, o, dO and dQKV are stored in BF16 (matrix-core operands only)
     GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16};
-    RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s));
+    RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnFwdName[cls],
           launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
-    GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16};
+    GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
     RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
                                     w.G[a + 1], w.xhat[a], w.rstd[a], s));
   }
@@ -719,17 +720,17 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       // the shared buffers hold another layer: recompute this layer's forward
       // from its stored input G[a] (the same kernels, so the same values)
       GemmArgs r1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16};
-      RUN("qkv_fwd_recompute", gemm_linear(r1, A.b_qkv, w.qkv[a], 3 * D, s));
+      RUN("qkv_fwd_recompute", gemm_linear(r1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
       for (int cls = 0; cls < attn_class_count(sel); ++cls)
         RUN("attn_fwd_recompute",
             launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
-      GemmArgs r2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16};
+      GemmArgs r2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
       RUN("oproj_ln_recompute", gemm_ln_res(r2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a],
                                             ldM, w.G[a + 1], w.xhat[a], w.rstd[a], s));
       m->shared_layer = a;
     }
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16};
-    RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s));
+    RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnBwdQName[cls],
           launch_attn_bwd_q_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a], w.dqkv,
@@ -738,7 +739,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       RUN(kAttnBwdKName[cls],
           launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dqkv, w.astat, w.qside,
                                   w.gw, w.gr, a != na - 1, s));
-    GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax, m->bf16};
+    GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
     const int mode = a > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = a > 0 ? m->attn[a - 1].gamma : nullptr;
     const float *xh = a > 0 ? w.xhat[a - 1] : nullptr;

@@ -72,6 +72,7 @@ struct GemmArgs {
   const int *Mptr;
   int Mmax;       // grid sizing bound
   int bf16;       // 1: BF16 matrix-core operands (FP32 accumulate), 0: FP32
+  int xbf16;      // with bf16: X is stored in BF16 (row stride ldx in elements)
 };
 
 enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_FOLD = 4 };
@@ -81,8 +82,9 @@ enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_F
 void gemm_tanh_res(const GemmArgs &a, const float *bias, const int32_t *row_type, int bias_ld,
                    const float *res, int ldr, int res_mode, int res_fin, float *y, int ldy,
                    float *tout, int ldt, hipStream_t s);
-// y = acc + b (b may be null)
-void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s);
+// y = acc + b (b may be null); ybf16: y stored in BF16
+void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s,
+                 int ybf16 = 0);
 // Attention output projection with layer norm and residual:
 //   yv = acc + b; xhat = (yv - mean) * rstd; gout = gin + gamma*xhat + beta.
 void gemm_ln_res(const GemmArgs &a, const float *bias, const float *gamma, const float *beta,

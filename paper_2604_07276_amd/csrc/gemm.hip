@@ -40,6 +40,22 @@ __device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, f
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// X operand storage: BF selects the matrix-core operand precision (0 FP32,
+// 1 BF16 operands from an FP32 X, 2 BF16 operands from an X stored in BF16).
+// p points at element 0 of the lane's run of four in the X storage type.
+template <int BF>
+__device__ __forceinline__ const float *x_at(const float *X, size_t elem) {
+  if constexpr (BF == 2) return (const float *)((const __bf16 *)X + elem);
+  else return X + elem;
+}
+template <int BF>
+__device__ __forceinline__ floatx4 ldx4(const float *p, int k) {
+  if constexpr (BF == 2)
+    return __builtin_convertvector(*(const bf16x4 *)((const __bf16 *)p + k), floatx4);
+  else
+    return *(const floatx4 *)(p + k);
+}
+
 __device__ __forceinline__ float row_sum16(float v) {
   // sum over the four lane groups that share (lane % 16)
   v += __shfl_xor(v, 16);
@@ -50,7 +66,7 @@ __device__ __forceinline__ float row_sum16(float v) {
 template <class Epi, int NT>
 __device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs);
 
-template <int MT, int NT, class Epi, bool BF>
+template <int MT, int NT, class Epi, int BF>
 __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi epi) {
   __shared__ float cs[Epi::kCols * NT * 16];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
@@ -82,7 +98,7 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   for (int mt = 0; mt < MT; ++mt) {
     const int row = row0 + mt * 16 + r;
     xok[mt] = row < M;  // rows past M read row 0 and are never stored
-    xrow[mt] = a.X + (size_t)(xok[mt] ? row : 0) * a.ldx + 4 * g;
+    xrow[mt] = x_at<BF>(a.X, (size_t)(xok[mt] ? row : 0) * a.ldx + 4 * g);
   }
   const float *wrow[NT];
 #pragma unroll
@@ -96,7 +112,7 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   // accumulators back to back.
   floatx4 xv[MT], wv[NT], xn[MT], wn[NT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) xv[mt] = *(const floatx4 *)(xrow[mt]);
+  for (int mt = 0; mt < MT; ++mt) xv[mt] = ldx4<BF>(xrow[mt], 0);
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
     wv[nt] = *(const floatx4 *)(wrow[nt]);
@@ -104,7 +120,7 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   for (int k0 = 0; k0 < a.K; k0 += 16) {
     const int kn = k0 + 16 < a.K ? k0 + 16 : k0;  // last chunk reloads itself (unused)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) xn[mt] = *(const floatx4 *)(xrow[mt] + kn);
+    for (int mt = 0; mt < MT; ++mt) xn[mt] = ldx4<BF>(xrow[mt], kn);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
       wn[nt] = *(const floatx4 *)(wrow[nt] + kn);
@@ -148,19 +164,19 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
 // launch rather than once per tile.  gridDim.x is a multiple of 8 so that
 // the column blocks of one row tile are dispatched to the same XCD (shared
 // L2 for the activations).
-template <int MT, int KCH>
+template <int MT, int KCH, int BF>
 __device__ __forceinline__ void load_x_tile(const GemmArgs &a, int row0, int M, int r, int g,
                                             floatx4 (&x)[MT][KCH]) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int row = row0 + mt * 16 + r;
-    const float *xp = a.X + (size_t)(row < M ? row : 0) * a.ldx + 4 * g;
+    const float *xp = x_at<BF>(a.X, (size_t)(row < M ? row : 0) * a.ldx + 4 * g);
 #pragma unroll
-    for (int c = 0; c < KCH; ++c) x[mt][c] = *(const floatx4 *)(xp + 16 * c);
+    for (int c = 0; c < KCH; ++c) x[mt][c] = ldx4<BF>(xp, 16 * c);
   }
 }
 
-template <int MT, int NT, int KCH, class Epi, bool BF>
+template <int MT, int NT, int KCH, class Epi, int BF>
 __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   constexpr int K = KCH * 16;
   constexpr int LDW = K + 4;
@@ -186,12 +202,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   const int stride = gridDim.x * 64 * MT;  // rows between a wave's consecutive tiles
   int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
   floatx4 xr[MT][KCH], xn[MT][KCH];
-  if (row0 < M) load_x_tile<MT, KCH>(a, row0, M, r, g, xr);
+  if (row0 < M) load_x_tile<MT, KCH, BF>(a, row0, M, r, g, xr);
   for (; row0 < M; row0 += stride) {
     // the layer-norm epilogue holds more registers: its prefetch waits until
     // the current tile's activations are dead
     if constexpr (Epi::kLds == 1)
-      if (row0 + stride < M) load_x_tile<MT, KCH>(a, row0 + stride, M, r, g, xn);
+      if (row0 + stride < M) load_x_tile<MT, KCH, BF>(a, row0 + stride, M, r, g, xn);
     floatx4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -224,7 +240,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
       }
     }
     if constexpr (Epi::kLds == 2)
-      if (row0 + stride < M) load_x_tile<MT, KCH>(a, row0 + stride, M, r, g, xn);
+      if (row0 + stride < M) load_x_tile<MT, KCH, BF>(a, row0 + stride, M, r, g, xn);
     epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -255,6 +271,7 @@ struct EpiLinear {
   float *y;
   int ldy;
   int Nreal;
+  int ybf16;  // 1: y is stored in BF16 (rounded to nearest even)
   __device__ __forceinline__ const float *col(int) const { return bias; }
   template <int MT, int NT>
   __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
@@ -272,7 +289,10 @@ struct EpiLinear {
         floatx4 o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) o[v] = n0 + v < Nreal ? acc[mt][nt][v] + b[v] : 0.f;
-        *(floatx4 *)(y + (size_t)row * ldy + n0) = o;
+        if (ybf16)
+          *(bf16x4 *)((__bf16 *)y + (size_t)row * ldy + n0) = to_bf16(o);
+        else
+          *(floatx4 *)(y + (size_t)row * ldy + n0) = o;
       }
     }
   }
@@ -664,7 +684,7 @@ int cu_count() {
 
 // Grid of the streaming kernel: one block per 4*16*MT rows, capped at the
 // number of blocks the device holds at once (the kernel loops over tiles).
-template <int MT, int NT, class Epi, bool BF>
+template <int MT, int NT, class Epi, int BF>
 void launch_stream_p(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) {
   static int per_cu = 0;
   if (per_cu == 0) {
@@ -684,8 +704,9 @@ void launch_stream_p(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s
 }
 template <int MT, int NT, class Epi>
 void launch_stream(const GemmArgs &a, const Epi &e, unsigned gy, hipStream_t s) {
-  if (a.bf16) launch_stream_p<MT, NT, Epi, true>(a, e, gy, s);
-  else launch_stream_p<MT, NT, Epi, false>(a, e, gy, s);
+  if (a.bf16 && a.xbf16) launch_stream_p<MT, NT, Epi, 2>(a, e, gy, s);
+  else if (a.bf16) launch_stream_p<MT, NT, Epi, 1>(a, e, gy, s);
+  else launch_stream_p<MT, NT, Epi, 0>(a, e, gy, s);
 }
 
 template <class Epi, int MT>
@@ -718,10 +739,12 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
   if (gx <= 0) return;
   const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4 + Epi::kCols);
-  if (a.bf16)
-    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, true>), dim3(gx, gy), dim3(256), lds, s, a, e);
+  if (a.bf16 && a.xbf16)
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 2>), dim3(gx, gy), dim3(256), lds, s, a, e);
+  else if (a.bf16)
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 1>), dim3(gx, gy), dim3(256), lds, s, a, e);
   else
-    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, false>), dim3(gx, gy), dim3(256), lds, s, a, e);
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 0>), dim3(gx, gy), dim3(256), lds, s, a, e);
 }
 
 // Rows per wave: two 16-row tiles for the large pair-batched products,
@@ -748,8 +771,9 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
 
 }  // namespace
 
-void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s) {
-  EpiLinear e{bias, y, ldy, a.Nreal};
+void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s,
+                 int ybf16) {
+  EpiLinear e{bias, y, ldy, a.Nreal, ybf16};
   run(a, e, false, s);
 }
 
