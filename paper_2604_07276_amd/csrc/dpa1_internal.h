@@ -14,6 +14,17 @@ namespace dpa1 {
 constexpr int kPad = 16;
 inline int pad16(int x) { return (x + kPad - 1) / kPad * kPad; }
 
+// tanh x = 1 - 2 / (exp(2x) + 1) with the hardware base-2 exponential and
+// reciprocal (v_exp_f32, v_rcp_f32): five VALU operations and no branch.  It
+// saturates to +-1 without NaN (exp(2x) = inf gives 1 - 0, exp(2x) = 0 gives
+// 1 - 2).  Its error is a few FP32 ulps of 1 in absolute terms (no relative
+// accuracy as x -> 0); every activation it feeds is added to O(1) terms or
+// enters as 1 - t^2, where that is the rounding level of FP32 storage.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.88539008177792681f);  // 2 / ln 2
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 // Geometry record of one neighbour pair (8 floats):
 //   s = sw/r, rhat (3), sw, r, dsw/dr, unused.
 enum GeomField { G_S = 0, G_RX = 1, G_RY = 2, G_RZ = 3, G_SW = 4, G_R = 5, G_DSW = 6 };

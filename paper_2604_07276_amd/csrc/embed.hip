@@ -68,10 +68,12 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
 }
 
 // value of the residual term for output column n: x[n] (identity), x[n mod fin]
-// (doubling) or 0, read from the wave's LDS copy of its rows.  The reads are
-// unconditional (in-row indices) and the mode picks with selects.
+// (doubling, where every stored column has n < 2 fin, so n mod fin is one
+// conditional subtraction; padding columns read some in-row value and are
+// masked by the caller) or 0, read from the wave's LDS copy of its rows.  The
+// reads are unconditional (in-row indices) and the mode picks with selects.
 __device__ __forceinline__ float res_fwd(const float *rowp, int mode, int fin, int n) {
-  const float v = rowp[mode == RES_DOUBLE ? n % fin : n];
+  const float v = rowp[mode == RES_DOUBLE && n >= fin ? n - fin : n];
   return mode == RES_NONE ? 0.f : v;
 }
 // gradient flowing back through the residual into input column k
@@ -100,74 +102,94 @@ struct EmbArgs {
   const int *Pptr;
 };
 
-template <int C0, int C1, int C2, bool BF>
-__global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
-  constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
-  __shared__ float xs[4][MT * 16][LD1 + 1];  // per wave: rows of h1 then h2
-  __shared__ float b2s[LD1], b3s[LD2];
-  const int P = *a.Pptr;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
-  stage_vec<LD1>(a.b2, b2s);
-  stage_vec<LD2>(a.b3, b3s);
-  __syncthreads();
-  if (row0 >= P) return;
-  const int r = lane & 15, g = lane >> 4;
-  float(*xw)[LD1 + 1] = xs[wave];
-
-  floatx4 x0[MT][C0];
+// Rows [row0, row0 + 16 MT) of h1 as the B operand of layer 2 (rows past P
+// read row 0 and are never stored).
+template <int C0>
+__device__ __forceinline__ void load_h1(const float *h1, int row0, int P, int r, int g,
+                                        floatx4 (&x0)[MT][C0]) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int row = row0 + mt * 16 + r;
     const int rr = row < P ? row : 0;
 #pragma unroll
     for (int c = 0; c < C0; ++c)
-      x0[mt][c] = *(const floatx4 *)(a.h1 + (size_t)rr * LD0 + 16 * c + 4 * g);
+      x0[mt][c] = *(const floatx4 *)(h1 + (size_t)rr * (C0 * 16) + 16 * c + 4 * g);
   }
+}
+
+// Persistent over row tiles (the grid holds what the device keeps resident,
+// three workgroups per CU).  Loading the next tile's h1 rows ahead costs the
+// registers of the third workgroup and measured slower.
+template <int C0, int C1, int C2, bool BF>
+__global__ __launch_bounds__(256, 3) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
+  constexpr int LD1 = C1 * 16, LD2 = C2 * 16;
+  __shared__ float xs[4][MT * 16][LD1 + 1];  // per wave: rows of h1 then h2
+  __shared__ float b2s[LD1], b3s[LD2];
+  const int P = *a.Pptr;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int stride = gridDim.x * 4 * 16 * MT;
+  int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  stage_vec<LD1>(a.b2, b2s);
+  stage_vec<LD2>(a.b3, b3s);
+  __syncthreads();
+  for (; row0 < P; row0 += stride) {
+    // per-lane indices are taken afresh in every iteration from a value the
+    // optimiser cannot see through, so that the addresses derived from them
+    // are recomputed here instead of being held in registers across the loop
+    int lane_it = lane;
+    asm volatile("" : "+v"(lane_it));
+    const int r = lane_it & 15, g = lane_it >> 4;
+    float(*xw)[LD1 + 1] = xs[wave];
+    floatx4 x0[MT][C0];
+    load_h1<C0>(a.h1, row0, P, r, g, x0);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int c = 0; c < C0; ++c)
+      for (int c = 0; c < C0; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
-  floatx4 acc1[MT][C1];
-  layer<C0, C1, BF>(a.W2t, r, g, x0, acc1);
-  __builtin_amdgcn_wave_barrier();
-  floatx4 x1[MT][C1];
+        for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
+    floatx4 acc1[MT][C1];
+    layer<C0, C1, BF>(a.W2t, r, g, x0, acc1);
+    __builtin_amdgcn_wave_barrier();
+    floatx4 x1[MT][C1];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < C1; ++nt)
+      for (int nt = 0; nt < C1; ++nt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int n = nt * 16 + 4 * g + v;
-        const float h = tanhf(acc1[mt][nt][v] + b2s[n]) + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
-        x1[mt][nt][v] = n < a.n1 ? h : 0.f;
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          const float h =
+              tanh_fast(acc1[mt][nt][v] + b2s[n]) + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
+          x1[mt][nt][v] = n < a.n1 ? h : 0.f;
+        }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
+    floatx4 acc2[MT][C2];
+    layer<C1, C2, BF>(a.W3t, r, g, x1, acc2);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      if (row >= P) continue;
+#pragma unroll
+      for (int nt = 0; nt < C2; ++nt) {
+        floatx4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          const float h =
+              tanh_fast(acc2[mt][nt][v] + b3s[n]) + res_fwd(xw[mt * 16 + r], a.res3, a.n1, n);
+          o[v] = n < a.n2 ? h : 0.f;
+        }
+        *(floatx4 *)(G0 + (size_t)row * LD2 + nt * 16 + 4 * g) = o;
       }
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < C1; ++nt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
-  floatx4 acc2[MT][C2];
-  layer<C1, C2, BF>(a.W3t, r, g, x1, acc2);
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int row = row0 + mt * 16 + r;
-    if (row >= P) continue;
-#pragma unroll
-    for (int nt = 0; nt < C2; ++nt) {
-      floatx4 o;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int n = nt * 16 + 4 * g + v;
-        const float h = tanhf(acc2[mt][nt][v] + b3s[n]) + res_fwd(xw[mt * 16 + r], a.res3, a.n1, n);
-        o[v] = n < a.n2 ? h : 0.f;
-      }
-      *(floatx4 *)(G0 + (size_t)row * LD2 + nt * 16 + 4 * g) = o;
     }
   }
 }
@@ -180,25 +202,22 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   __shared__ float b2s[LD1], b3s[LD2], wss[LD0];
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  const int stride = gridDim.x * 4 * 16 * MT;
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
   stage_vec<LD0>(a.ws, wss);
   __syncthreads();
-  if (row0 >= P) return;
-  const int r = lane & 15, g = lane >> 4;
+  // persistent over row tiles, as the forward (no prefetch: the registers
+  // are taken by the adjoint; per-lane indices taken afresh as there)
+  for (int row0 = (blockIdx.x * 4 + wave) * 16 * MT; row0 < P; row0 += stride) {
+  int lane_it = lane;
+  asm volatile("" : "+v"(lane_it));
+  const int r = lane_it & 15, g = lane_it >> 4;
   float(*xw)[LD2 + 1] = xs[wave];
-
+  __builtin_amdgcn_wave_barrier();
   // ---- recompute the forward
   floatx4 x0[MT][C0];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int row = row0 + mt * 16 + r;
-    const int rr = row < P ? row : 0;
-#pragma unroll
-    for (int c = 0; c < C0; ++c)
-      x0[mt][c] = *(const floatx4 *)(a.h1 + (size_t)rr * LD0 + 16 * c + 4 * g);
-  }
+  load_h1<C0>(a.h1, row0, P, r, g, x0);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -217,7 +236,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          const float t = tanhf(acc1[mt][nt][v] + b2s[n]);
+          const float t = tanh_fast(acc1[mt][nt][v] + b2s[n]);
           const float h = t + res_fwd(xw[mt * 16 + r], a.res2, a.n0, n);
           t1[mt][nt][v] = n < a.n1 ? t : 0.f;
           x1[mt][nt][v] = n < a.n1 ? h : 0.f;
@@ -234,7 +253,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int n = nt * 16 + 4 * g + v;
-          const float t = tanhf(acc2[mt][nt][v] + b3s[n]);
+          const float t = tanh_fast(acc2[mt][nt][v] + b3s[n]);
           d2[mt][nt][v] = n < a.n2 ? t : 0.f;
         }
   }
@@ -307,6 +326,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
     const int row = row0 + mt * 16 + r;
     if (g == 0 && row < P) gs[row] = s;
   }
+  }
 }
 
 // Instantiated widths (padded to 16): the benchmark model's 32/64/112
@@ -319,36 +339,61 @@ bool emb_fused_supported(int ld0, int ld1, int ld2) {
   return (ld0 == 32 && ld1 == 64 && ld2 == 112) || is_student_widths(ld0, ld1, ld2);
 }
 
+namespace {
+
+// Blocks of kernel k that the device holds at once (the persistent grid).
+template <class K>
+unsigned resident_blocks(K k) {
+  int nb = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb <= 0)
+    nb = 2;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return (unsigned)(nb * cus);
+}
+
+template <int C0, int C1, int C2, bool BF>
+void emb_fwd_grid(const EmbArgs &a, long tiles, float *G0, hipStream_t s) {
+  static unsigned cap = 0;
+  if (cap == 0) cap = resident_blocks(k_emb_fwd<C0, C1, C2, BF>);
+  const unsigned blocks = (unsigned)(tiles < (long)cap ? tiles : (long)cap);
+  hipLaunchKernelGGL((k_emb_fwd<C0, C1, C2, BF>), dim3(blocks), dim3(256), 0, s, a, G0);
+}
+
+template <int C0, int C1, int C2, bool BF>
+void emb_bwd_grid(const EmbArgs &a, long tiles, const float *dG0, float *gs, hipStream_t s) {
+  static unsigned cap = 0;
+  if (cap == 0) cap = resident_blocks(k_emb_bwd<C0, C1, C2, BF>);
+  const unsigned blocks = (unsigned)(tiles < (long)cap ? tiles : (long)cap);
+  hipLaunchKernelGGL((k_emb_bwd<C0, C1, C2, BF>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+}
+
+}  // namespace
+
 void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
   EmbArgs a{e.h1, e.W2t, e.b2, e.W3t, e.b3, e.W2b, e.W3b, e.ws, e.n0, e.n1, e.n2, e.res2, e.res3,
             e.Pptr};
-  const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
-  if (blocks == 0) return;
+  const long tiles = ((long)e.Pmax + 64 * MT - 1) / (64 * MT);
+  if (tiles == 0) return;
   const bool st = is_student_widths(pad16(e.n0), pad16(e.n1), pad16(e.n2));
-  if (st && e.bf16)
-    hipLaunchKernelGGL((k_emb_fwd<1, 2, 4, true>), dim3(blocks), dim3(256), 0, s, a, G0);
-  else if (st)
-    hipLaunchKernelGGL((k_emb_fwd<1, 2, 4, false>), dim3(blocks), dim3(256), 0, s, a, G0);
-  else if (e.bf16)
-    hipLaunchKernelGGL((k_emb_fwd<2, 4, 7, true>), dim3(blocks), dim3(256), 0, s, a, G0);
-  else
-    hipLaunchKernelGGL((k_emb_fwd<2, 4, 7, false>), dim3(blocks), dim3(256), 0, s, a, G0);
+  if (st && e.bf16) emb_fwd_grid<1, 2, 4, true>(a, tiles, G0, s);
+  else if (st) emb_fwd_grid<1, 2, 4, false>(a, tiles, G0, s);
+  else if (e.bf16) emb_fwd_grid<2, 4, 7, true>(a, tiles, G0, s);
+  else emb_fwd_grid<2, 4, 7, false>(a, tiles, G0, s);
 }
 
 void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t s) {
   EmbArgs a{e.h1, e.W2t, e.b2, e.W3t, e.b3, e.W2b, e.W3b, e.ws, e.n0, e.n1, e.n2, e.res2, e.res3,
             e.Pptr};
-  const unsigned blocks = (unsigned)((e.Pmax + 64 * MT - 1) / (64 * MT));
-  if (blocks == 0) return;
+  const long tiles = ((long)e.Pmax + 64 * MT - 1) / (64 * MT);
+  if (tiles == 0) return;
   const bool st = is_student_widths(pad16(e.n0), pad16(e.n1), pad16(e.n2));
-  if (st && e.bf16)
-    hipLaunchKernelGGL((k_emb_bwd<1, 2, 4, true>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
-  else if (st)
-    hipLaunchKernelGGL((k_emb_bwd<1, 2, 4, false>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
-  else if (e.bf16)
-    hipLaunchKernelGGL((k_emb_bwd<2, 4, 7, true>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
-  else
-    hipLaunchKernelGGL((k_emb_bwd<2, 4, 7, false>), dim3(blocks), dim3(256), 0, s, a, dG0, gs);
+  if (st && e.bf16) emb_bwd_grid<1, 2, 4, true>(a, tiles, dG0, gs, s);
+  else if (st) emb_bwd_grid<1, 2, 4, false>(a, tiles, dG0, gs, s);
+  else if (e.bf16) emb_bwd_grid<2, 4, 7, true>(a, tiles, dG0, gs, s);
+  else emb_bwd_grid<2, 4, 7, false>(a, tiles, dG0, gs, s);
 }
 
 }  // namespace dpa1

@@ -350,8 +350,10 @@ struct EpiTanhRes {
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
+            // doubling: Nreal = 2 res_fin, so n mod res_fin is one subtraction
             const int n = (nt0 + nt) * 16 + 4 * g + v;
-            rv[nt][v] = res[rr * ldr + (n < Nreal ? n : 0) % res_fin];
+            const int nn = n < Nreal ? n : 0;
+            rv[nt][v] = res[rr * ldr + (nn >= res_fin ? nn - res_fin : nn)];
           }
       } else {
 #pragma unroll
@@ -366,7 +368,7 @@ struct EpiTanhRes {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const bool in = n0 + v < Nreal;
-          const float t = tanhf(acc[mt][nt][v] + bl[nt][v]);
+          const float t = tanh_fast(acc[mt][nt][v] + bl[nt][v]);
           o[v] = in ? t + rv[nt][v] : 0.f;
           tv[v] = in ? t : 0.f;
         }

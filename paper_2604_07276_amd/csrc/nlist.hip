@@ -268,10 +268,10 @@ __global__ __launch_bounds__(kEnvWaves * 64) void k_env_embed1(
     float4 *hp = (float4 *)(h1 + (size_t)p * ld1);
     for (int o = 0; o < ld1; o += 4) {
       float4 v;
-      v.x = o + 0 < n1 ? tanhf(tt[o + 0] + wsv[o + 0] * s32) : 0.0f;
-      v.y = o + 1 < n1 ? tanhf(tt[o + 1] + wsv[o + 1] * s32) : 0.0f;
-      v.z = o + 2 < n1 ? tanhf(tt[o + 2] + wsv[o + 2] * s32) : 0.0f;
-      v.w = o + 3 < n1 ? tanhf(tt[o + 3] + wsv[o + 3] * s32) : 0.0f;
+      v.x = o + 0 < n1 ? tanh_fast(tt[o + 0] + wsv[o + 0] * s32) : 0.0f;
+      v.y = o + 1 < n1 ? tanh_fast(tt[o + 1] + wsv[o + 1] * s32) : 0.0f;
+      v.z = o + 2 < n1 ? tanh_fast(tt[o + 2] + wsv[o + 2] * s32) : 0.0f;
+      v.w = o + 3 < n1 ? tanh_fast(tt[o + 3] + wsv[o + 3] * s32) : 0.0f;
       hp[o >> 2] = v;
     }
   }

@@ -111,7 +111,7 @@ __device__ __forceinline__ void emb_l1(const TrainPairArgs &a, int tj, int ti, f
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int o = 4 * q + u;
-      const float t = tanhf(fmaf(wc(a.ws, o), s, zz[u]));
+      const float t = tanh_fast(fmaf(wc(a.ws, o), s, zz[u]));
       h1[o] = t;
       h1d[o] = (1.0f - t * t) * wc(a.ws, o);
     }
@@ -131,7 +131,7 @@ __device__ __forceinline__ void emb_l2(const TrainPairArgs &a, const float h1[kT
       z = fmaf(wc(a.W2t, o * kTrN1 + k), h1[k], z);
       zd = fmaf(wc(a.W2t, o * kTrN1 + k), h1d[k], zd);
     }
-    const float t = tanhf(z);
+    const float t = tanh_fast(z);
     h2[o] = t + h1[o % kTrN1];
     h2d[o] = (1.0f - t * t) * zd + h1d[o % kTrN1];
   }
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_tr_tangent(TrainPairArgs a,
           z = fmaf(wc(a.W3t, o * kTrN2 + k), h2[k], z);
           zd = fmaf(wc(a.W3t, o * kTrN2 + k), h2d[k], zd);
         }
-        const float t = tanhf(z);
+        const float t = tanh_fast(z);
         sG[w][lane * kGS + o] = t + h2[o % kTrN2];
         sGp[w][lane * kGS + o] = (1.0f - t * t) * zd + h2d[o % kTrN2];
       }
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev(
         z = fmaf(wc(a.W3t, o * kTrN2 + k), h2[k], z);
         zd = fmaf(wc(a.W3t, o * kTrN2 + k), h2d[k], zd);
       }
-      const float t = tanhf(z), g = 1.0f - t * t;
+      const float t = tanh_fast(z), g = 1.0f - t * t;
       const float zbd = g * Gdb;
       const float zb = g * (Gb - 2.0f * t * zd * Gdb);
 #pragma unroll
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) void k_tr_pair_rev2(TrainPairArgs a, const int
           z = fmaf(wc(a.W2t, o * kTrN1 + k), h1[k], z);
           zd = fmaf(wc(a.W2t, o * kTrN1 + k), h1d[k], zd);
         }
-        const float t = tanhf(z), g = 1.0f - t * t;
+        const float t = tanh_fast(z), g = 1.0f - t * t;
         const float zbd = g * hb2d[o];
         const float zb = g * (hb2[o] - 2.0f * t * zd * hb2d[o]);
 #pragma unroll
