@@ -121,10 +121,13 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
 
 def kernel_sources(kernel: str) -> list:
     """Library sources that define a kernel's code and launch (the attention
-    kernels: attn.hip and the shared internal header; others: every source)."""
+    kernels: attn.hip and the shared internal header; the attention-layer
+    projections: gemm.hip and that header; others: every source)."""
     csrc = os.path.join(ROOT, "paper_2604_07276_amd", "csrc")
     if kernel.startswith("attn_"):
         return [os.path.join(csrc, "attn.hip"), os.path.join(csrc, "dpa1_internal.h")]
+    if kernel.startswith(("qkv_", "oproj_")):
+        return [os.path.join(csrc, "gemm.hip"), os.path.join(csrc, "dpa1_internal.h")]
     return sorted(f for f in glob.glob(os.path.join(csrc, "*"))
                   if f.endswith((".hip", ".cpp", ".h")))
 
@@ -146,11 +149,11 @@ def measured_traffic(kernel: str):
             text = fh.read()
     except OSError:
         return None
-    m = re.search(r"bench-traffic: kernel=(\S+) source=(\S+) fetch_bytes=(\d+) write_bytes=(\d+)",
-                  text)
-    if not m or m.group(1) != kernel or m.group(2) != source_hash(kernel):
-        return None
-    return int(m.group(3)), int(m.group(4))
+    for m in re.finditer(
+            r"bench-traffic: kernel=(\S+) source=(\S+) fetch_bytes=(\d+) write_bytes=(\d+)", text):
+        if m.group(1) == kernel and m.group(2) == source_hash(kernel):
+            return int(m.group(3)), int(m.group(4))
+    return None
 
 
 def cpu_baseline(weights_path, sysm, budget_s: float, gpu_forces: dict) -> tuple:

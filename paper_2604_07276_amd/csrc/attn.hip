@@ -49,6 +49,15 @@ __device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, f
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// exp x = 2^(x log2 e) on the hardware v_exp_f32: two operations instead of
+// the library expf's range reduction.  Its arguments here are logits minus
+// their row maximum (<= 0); the relative error, about |x| ulps, is below the
+// FP32 rounding of what follows.  The FP32 query-tile adjoint keeps expf:
+// there the change costs two registers and with them a wavefront per SIMD.
+__device__ __forceinline__ float exp_hw(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+}
+
 __device__ __forceinline__ float sum_groups(float v) {  // over lanes sharing lane%16
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
@@ -403,12 +412,12 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
       for (int kt = 0; kt < NT; ++kt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float e = expf(st[kt][v] - m);
+          const float e = exp_hw(st[kt][v] - m);
           st[kt][v] = e;
           z += e;
         }
       }
-      z = sum_groups(z) + (float)(sel - n) * expf(-shift - m);
+      z = sum_groups(z) + (float)(sel - n) * exp_hw(-shift - m);
       invz = 1.0f / z;
       if (g == 0 && qok) fstat[base + q] = make_float2(m, invz);
     }
@@ -547,7 +556,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           const float ww = wq * gk.w;
           const float lm = ok ? lcur[v] : 0.f;
           const float l = (lm + shift) * ww - shift;
-          const float p = ok ? expf(l - m) * invz : 0.f;
+          const float p = ok ? (BF ? exp_hw(l - m) : expf(l - m)) * invz : 0.f;
           const float h = ww * c;
           const float dH = da[kt][v] * p;
           const float dL = p * (da[kt][v] * h - dq);
@@ -659,7 +668,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
           const float ww = gq.w * wk;
           const float lm = ok ? lcur[v] : 0.f;
           const float l = (lm + shift) * ww - shift;
-          const float p = ok ? expf(l - sq.x) * sq.y : 0.f;
+          const float p = ok ? exp_hw(l - sq.x) * sq.y : 0.f;
           const float h = ww * c;
           const float dav = dk[qt][v];
           const float dH = dav * p;

@@ -756,6 +756,10 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
   const int ntt = a.Npad / 16;
   int nt = ntt < 8 ? ntt : 8;
   if (full_rows && ntt > 8) nt = ntt;  // callers guarantee ntt <= 8 for row reductions
+  // per-centre products (the fitting net: few rows, long k loops) run on
+  // column blocks of at most four tiles: more wavefronts per SIMD to cover
+  // the load latency of each k step (measured best against 1, 2 and 8)
+  if (!full_rows && a.Mmax < 65536 && nt > 4) nt = 4;
   if constexpr (Epi::kLds != 0) {
     if (a.Mmax >= 65536 && (a.K == 112 || a.K == 128) && (nt == 7 || nt == 8)) {
       if (nt == 7 && a.K == 112) return launch_lds<Epi, 7, 7>(a, e, s);
