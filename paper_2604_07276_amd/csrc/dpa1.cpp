@@ -611,7 +611,7 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   for (int a = 0; a < na; ++a) {
     const auto &A = m->attn[a];
     // in BF16 mode QKV, o, dO and dQKV are stored in BF16 (matrix-core operands only)
-    GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16};
+    GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16, 0, m->M};
     RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnFwdName[cls],
@@ -719,7 +719,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
     if (m->recompute && m->shared_layer != a) {
       // the shared buffers hold another layer: recompute this layer's forward
       // from its stored input G[a] (the same kernels, so the same values)
-      GemmArgs r1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16};
+      GemmArgs r1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16, 0, m->M};
       RUN("qkv_fwd_recompute", gemm_linear(r1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
       for (int cls = 0; cls < attn_class_count(sel); ++cls)
         RUN("attn_fwd_recompute",
@@ -729,7 +729,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
                                             ldM, w.G[a + 1], w.xhat[a], w.rstd[a], s));
       m->shared_layer = a;
     }
-    GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16};
+    GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16, 0, m->M};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       RUN(kAttnBwdQName[cls],

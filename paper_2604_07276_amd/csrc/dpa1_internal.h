@@ -84,6 +84,7 @@ struct GemmArgs {
   int Mmax;       // grid sizing bound
   int bf16;       // 1: BF16 matrix-core operands (FP32 accumulate), 0: FP32
   int xbf16;      // with bf16: X is stored in BF16 (row stride ldx in elements)
+  int kreal;      // 0, or the depth up to which X and W hold data (zeros past it)
 };
 
 enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_FOLD = 4 };

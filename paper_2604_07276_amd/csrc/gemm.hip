@@ -164,7 +164,11 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
 // launch rather than once per tile.  gridDim.x is a multiple of 8 so that
 // the column blocks of one row tile are dispatched to the same XCD (shared
 // L2 for the activations).
-template <int MT, int KCH, int BF>
+// KT = 1 (FP32 only): X holds data only in the first four columns of its last
+// 16-wide chunk (zeros past them).  That chunk then takes one MFMA step in
+// which lane group g carries depth 16 (KCH - 1) + g on both operands, instead
+// of four steps over mostly zero columns; the lane loads that one value.
+template <int MT, int KCH, int BF, int KT>
 __device__ __forceinline__ void load_x_tile(const GemmArgs &a, int row0, int M, int r, int g,
                                             floatx4 (&x)[MT][KCH]) {
 #pragma unroll
@@ -172,11 +176,16 @@ __device__ __forceinline__ void load_x_tile(const GemmArgs &a, int row0, int M, 
     const int row = row0 + mt * 16 + r;
     const float *xp = x_at<BF>(a.X, (size_t)(row < M ? row : 0) * a.ldx + 4 * g);
 #pragma unroll
-    for (int c = 0; c < KCH; ++c) x[mt][c] = ldx4<BF>(xp, 16 * c);
+    for (int c = 0; c < KCH; ++c) {
+      if (KT == 1 && c == KCH - 1)
+        x[mt][c][0] = xp[16 * c - 3 * g];  // column 16 c + g of the row
+      else
+        x[mt][c] = ldx4<BF>(xp, 16 * c);
+    }
   }
 }
 
-template <int MT, int NT, int KCH, class Epi, int BF>
+template <int MT, int NT, int KCH, class Epi, int BF, int KT>
 __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   constexpr int K = KCH * 16;
   constexpr int LDW = K + 4;
@@ -202,12 +211,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   const int stride = gridDim.x * 64 * MT;  // rows between a wave's consecutive tiles
   int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
   floatx4 xr[MT][KCH], xn[MT][KCH];
-  if (row0 < M) load_x_tile<MT, KCH, BF>(a, row0, M, r, g, xr);
+  if (row0 < M) load_x_tile<MT, KCH, BF, KT>(a, row0, M, r, g, xr);
   for (; row0 < M; row0 += stride) {
     // the layer-norm epilogue holds more registers: its prefetch waits until
     // the current tile's activations are dead
     if constexpr (Epi::kLds == 1)
-      if (row0 + stride < M) load_x_tile<MT, KCH, BF>(a, row0 + stride, M, r, g, xn);
+      if (row0 + stride < M) load_x_tile<MT, KCH, BF, KT>(a, row0 + stride, M, r, g, xn);
     floatx4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -215,6 +224,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < KCH; ++c) {
+      if constexpr (KT == 1 && BF == 0) {
+        if (c == KCH - 1) {
+          // one step: depth 16 c + g on both operands (W from LDS at that depth)
+          const float *wt = wsm + r * LDW + 16 * c + g;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const float wv = wt[nt * 16 * LDW];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv, xr[mt][c][0], acc[mt][nt]);
+          }
+          continue;
+        }
+      }
       floatx4 w[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * LDW + 16 * c);
@@ -240,7 +262,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
       }
     }
     if constexpr (Epi::kLds == 2)
-      if (row0 + stride < M) load_x_tile<MT, KCH, BF>(a, row0 + stride, M, r, g, xn);
+      if (row0 + stride < M) load_x_tile<MT, KCH, BF, KT>(a, row0 + stride, M, r, g, xn);
     epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -741,12 +763,16 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   if (gx > row_tiles) gx = (row_tiles + 7) / 8 * 8;
   if (gx <= 0) return;
   const size_t lds = sizeof(float) * NT * 16 * (KCH * 16 + 4 + Epi::kCols);
+  // FP32 with data only in the first four columns of the last chunk
+  const bool short_tail = a.kreal > 16 * (KCH - 1) && a.kreal <= 16 * (KCH - 1) + 4;
   if (a.bf16 && a.xbf16)
-    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 2>), dim3(gx, gy), dim3(256), lds, s, a, e);
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 2, 4>), dim3(gx, gy), dim3(256), lds, s, a, e);
   else if (a.bf16)
-    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 1>), dim3(gx, gy), dim3(256), lds, s, a, e);
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 1, 4>), dim3(gx, gy), dim3(256), lds, s, a, e);
+  else if (short_tail)
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 0, 1>), dim3(gx, gy), dim3(256), lds, s, a, e);
   else
-    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 0>), dim3(gx, gy), dim3(256), lds, s, a, e);
+    hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 0, 4>), dim3(gx, gy), dim3(256), lds, s, a, e);
 }
 
 // Rows per wave: two 16-row tiles for the large pair-batched products,
