@@ -69,16 +69,41 @@ __device__ void stage_cols(const Epi &e, int nt0, int npad, float *cs);
 template <int MT, int NT, class Epi, int BF>
 __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi epi) {
   __shared__ float cs[Epi::kCols * NT * 16];
+  // The block's W^T rows of one 16-deep k chunk, double-buffered: the four
+  // wavefronts share each chunk instead of each reading it from L2.
+  // Used by the BF16 instances and the 16-row (per-centre) tiles; the FP32
+  // 64-row tiles keep per-wavefront W streams (see the k loop).
+  constexpr bool kShareW = BF != 0 || MT < 4;
+  constexpr int kWS = 20;  // row stride (16 + 4)
+  __shared__ float wsh[kShareW ? 2 : 1][kShareW ? NT * 16 : 1][kWS];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
   const int nt0 = blockIdx.y * NT;
   stage_cols<Epi, NT>(epi, nt0, a.Npad, cs);
   __syncthreads();
   const int ntt = a.Npad / 16;
+  // W staging: thread tid moves float4 q = tid + 256 j of the chunk, row
+  // q / 4 of the block's W^T rows, k quad q % 4 (column tiles past the last
+  // one stage a duplicate of tile 0; their outputs are never stored)
+  constexpr int NQ = NT * 16 * 4;
+  constexpr int JW = (NQ + 255) / 256;
+  const float *wsrc[JW];
+#pragma unroll
+  for (int j = 0; j < JW; ++j) {
+    const int q = tid + 256 * j < NQ ? tid + 256 * j : 0;
+    const int n = q >> 2;
+    const int tile = nt0 + n / 16 < ntt ? nt0 + n / 16 : 0;
+    wsrc[j] = a.Wt + (size_t)(tile * 16 + n % 16) * a.K + 4 * (q & 3);
+  }
   // persistent over row tiles: the grid is sized to the resident capacity
-  // (launch gaps and the tail of short-lived waves otherwise cost ~40%)
-  for (int row0 = (blockIdx.x * 4 + wave) * 16 * MT; row0 < M; row0 += gridDim.x * 64 * MT) {
+  // (launch gaps and the tail of short-lived waves otherwise cost ~40%).
+  // Every wavefront of a block runs the same iterations (the block-level
+  // barriers of the k loop need all four): a wavefront whose rows are all
+  // past M computes on row 0 and stores nothing.
+  for (int blk0 = blockIdx.x * 64 * MT; blk0 < M; blk0 += gridDim.x * 64 * MT) {
+  const int row0 = blk0 + wave * 16 * MT;
   // per-lane offsets are recomputed in every iteration from an index the
   // optimiser cannot see through, instead of being held across the loop
   int lane_it = lane;
@@ -100,55 +125,100 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
     xok[mt] = row < M;  // rows past M read row 0 and are never stored
     xrow[mt] = x_at<BF>(a.X, (size_t)(xok[mt] ? row : 0) * a.ldx + 4 * g);
   }
-  const float *wrow[NT];
+  if constexpr (kShareW) {
+    float4 wst[JW];
+    auto wload = [&](int k) {
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
-    wrow[nt] = a.Wt + (size_t)(tile * 16 + r) * a.K + 4 * g;
-  }
-
-  // Double-buffered k loop: the operands of chunk k0 + 16 are loaded while
-  // chunk k0 is multiplied; the MFMAs of one k step go to independent
-  // accumulators back to back.
-  floatx4 xv[MT], wv[NT], xn[MT], wn[NT];
+      for (int j = 0; j < JW; ++j) wst[j] = *(const float4 *)(wsrc[j] + k);
+    };
+    auto wstore = [&](int b) {
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) xv[mt] = ldx4<BF>(xrow[mt], 0);
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt)
-    wv[nt] = *(const floatx4 *)(wrow[nt]);
-#pragma unroll 1
-  for (int k0 = 0; k0 < a.K; k0 += 16) {
-    const int kn = k0 + 16 < a.K ? k0 + 16 : k0;  // last chunk reloads itself (unused)
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) xn[mt] = ldx4<BF>(xrow[mt], kn);
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-      wn[nt] = *(const floatx4 *)(wrow[nt] + kn);
-    __builtin_amdgcn_sched_barrier(0);
-    // Tiles past the last column tile (nt0 + nt >= ntt) multiply a duplicate of
-    // tile 0 and are never stored: no branch inside the MFMA sequence.
-    if constexpr (BF) {
-      bf16x4 xb[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(xv[mt]);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const bf16x4 wb = to_bf16(wv[nt]);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(wb, xb[mt], acc[mt][nt]);
+      for (int j = 0; j < JW; ++j) {
+        const int q = tid + 256 * j;
+        if (NQ % 256 == 0 || q < NQ) *(float4 *)&wsh[b][q >> 2][4 * (q & 3)] = wst[j];
       }
-    } else {
+    };
+
+    // Double-buffered k loop: the operands of chunk k0 + 16 (the block's W
+    // rows, the wavefront's X rows) are loaded while chunk k0 is multiplied;
+    // the MFMAs of one k step go to independent accumulators back to back.
+    floatx4 xv[MT], xn[MT];
+    wload(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) xv[mt] = ldx4<BF>(xrow[mt], 0);
+    wstore(0);
+    __syncthreads();
+    int b = 0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < a.K; k0 += 16) {
+      const bool more = k0 + 16 < a.K;  // uniform
+      if (more) {
+        wload(k0 + 16);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) xn[mt] = ldx4<BF>(xrow[mt], k0 + 16);
+      }
+      floatx4 wv[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) wv[nt] = *(const floatx4 *)&wsh[b][nt * 16 + r][4 * g];
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (BF) {
+        bf16x4 xb[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(xv[mt]);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf16x4 wb = to_bf16(wv[nt]);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(wb, xb[mt], acc[mt][nt]);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
+      }
+      if (more) wstore(b ^ 1);
+      __syncthreads();  // chunk k0 + 16 staged; buffer b free again
+      b ^= 1;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
+    }
+  } else {
+    // FP32 64-row tiles: each wavefront streams its own W rows from L2 (the
+    // per-chunk block barrier of the shared staging costs these long-K
+    // products more than the L2 reads it saves)
+    const float *wrow[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+      wrow[nt] = a.Wt + (size_t)(tile * 16 + r) * a.K + 4 * g;
+    }
+    floatx4 xv[MT], wv[NT], xn[MT], wn[NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) xv[mt] = ldx4<BF>(xrow[mt], 0);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) wv[nt] = *(const floatx4 *)(wrow[nt]);
+#pragma unroll 1
+    for (int k0 = 0; k0 < a.K; k0 += 16) {
+      const int kn = k0 + 16 < a.K ? k0 + 16 : k0;  // last chunk reloads itself (unused)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) xn[mt] = ldx4<BF>(xrow[mt], kn);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) wn[nt] = *(const floatx4 *)(wrow[nt] + kn);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) wv[nt] = wn[nt];
     }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) wv[nt] = wn[nt];
   }
   epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
   }
