@@ -10,6 +10,11 @@ recomputes its activations from the first layer instead of storing them.
 
 A handle keeps the activations of its latest forward only: a backward whose
 forward has been superseded by another forward on the same handle raises.
+The backward first waits for the forward and raises on the conditions the
+device found there (a neighbour overflow, an out-of-range type), so a
+truncated neighbour list never yields a gradient.  The coordinates are saved
+with save_for_backward: an in-place change between forward and backward
+(the adjoint reads them) raises torch's version-counter error.
 """
 
 from __future__ import annotations
@@ -32,7 +37,9 @@ class DPA1AtomicEnergy(torch.autograd.Function):
         model._fwd_serial = getattr(model, "_fwd_serial", 0) + 1
         ctx.model = model
         ctx.serial = model._fwd_serial
-        ctx.keep = (x, t)  # the adjoint reads these buffers
+        # the adjoint reads these buffers; x shares coords' version counter
+        # when no copy was needed, so in-place edits of coords are caught
+        ctx.save_for_backward(x, t)
         ctx.nall = x.shape[0]
         ctx.nloc = nloc
         return e[:nloc]
@@ -43,7 +50,9 @@ class DPA1AtomicEnergy(torch.autograd.Function):
         if getattr(model, "_fwd_serial", None) != ctx.serial:
             raise RuntimeError("the model handle ran another forward since this one; "
                                "its activations are gone")
-        x, _ = ctx.keep
+        x, _ = ctx.saved_tensors
+        # device-side status of the forward (neighbour overflow, bad type)
+        model.sync()
         grad = torch.empty((ctx.nall, 3), dtype=torch.float64, device=x.device)
         w = grad_e.detach().to(torch.float64).contiguous()
         if ctx.nloc == 0:

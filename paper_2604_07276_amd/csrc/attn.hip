@@ -199,18 +199,38 @@ __device__ __forceinline__ void stage_t_store(float *XT, int tid, int n, const f
 
 // Gate record of neighbour t = tid (rhat, sw; zeros past n), for kg[NPAD]:
 // one unconditional load per thread (threads past NPAD read slot 0), written
-// by gate_store.
+// by gate_store.  lo is the FP32 remainder of the switch value (sw - hi in
+// FP64), so that hi + lo carries sw to the logits with FP64 accuracy.
 __device__ __forceinline__ float4 gate_load(const float *__restrict__ geom, int base, int n,
-                                            int tid) {
+                                            int tid, float &lo) {
   const int t = tid < n ? tid : 0;
   const float4 *gp = (const float4 *)(geom + (size_t)(base + t) * kGeom);
-  const float4 a = gp[0], b = gp[1];  // s, rx, ry, rz | sw, r, dsw, -
+  const float4 a = gp[0], b = gp[1];  // s, rx, ry, rz | sw, r, dsw, sw remainder
+  lo = b.w;
   return make_float4(a.y, a.z, a.w, b.x);
 }
+// kw[NPAD]: the switch value of each neighbour in FP64 (zero past n).
 template <int NPAD>
-__device__ __forceinline__ void gate_store(float4 *kg, int tid, int n, const float4 &v) {
+__device__ __forceinline__ void gate_store(float4 *kg, double *kw, int tid, int n,
+                                           const float4 &v, float lo) {
   const bool ok = tid < n;
-  if (tid < NPAD) kg[tid] = make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
+  if (tid < NPAD) {
+    kg[tid] = make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
+    kw[tid] = ok ? (double)v.w + (double)lo : 0.0;
+  }
+}
+
+// Scaled logit L = (lam + S) w_q w_k - S of the FP32 path, with the switch
+// values and the shift in FP64 and one rounding at the end.  The logit's
+// sensitivity to each switch value is lam + S (about S = 20), so with FP32
+// switch values and FP32 arithmetic here the logit carries an absolute error
+// of a few 1e-6; at the rare centres where a pair of opposite neighbours
+// attend strongly to each other the forces amplify that by ~1e4 (measured on
+// the oracle's formula evaluated in FP32).  The products and every other
+// elementwise step stay FP32; the BF16 mode keeps FP32 logits.
+__device__ __forceinline__ float logit64(float lam, double wq, double wk, float shift) {
+  const double s = (double)shift;
+  return (float)fma((double)lam + s, wq * wk, -s);
 }
 
 // acc[ft] += XT^T-tile x bt : contraction over the 16 rows of tile 'tile',
@@ -338,7 +358,8 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;
-  float *buf = (float *)(smem + NPAD);  // K rows, then V^T
+  double *kw = (double *)(smem + NPAD);  // [NPAD] switch values in FP64
+  float *buf = (float *)(kw + NPAD);     // K rows, then V^T
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;  // 1/sqrt(128)
   const int cnt = *ccount;
@@ -348,6 +369,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
   float4 sv[8];
   floatx4 qv[8];
   float4 gv;
+  float gl = 0.f;
   int n_nx = 0, base_nx = 0;
   if (PREF && (int)blockIdx.x < cnt) {
     const int tid = fresh_tid();
@@ -355,7 +377,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
     n_nx = nnei[i0];
     base_nx = pair_off[i0];
     stage_rows_load<NPAD, BF>(qkv, 128, ld, base_nx, n_nx, tid, sv);  // K
-    gv = gate_load(geom, base_nx, n_nx, tid);
+    gv = gate_load(geom, base_nx, n_nx, tid, gl);
     load_rows<BF>(qkv, 0, ld, base_nx, n_nx, (tid >> 6) * 16 + (tid & 15), (tid & 63) >> 4, qv);
   }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
@@ -368,7 +390,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
       n_nx = nnei[i];
       base_nx = pair_off[i];
       stage_rows_load<NPAD, BF>(qkv, 128, ld, base_nx, n_nx, tid, sv);  // K
-      gv = gate_load(geom, base_nx, n_nx, tid);
+      gv = gate_load(geom, base_nx, n_nx, tid, gl);
       load_rows<BF>(qkv, 0, ld, base_nx, n_nx, wave * 16 + r, g, qv);
     }
     const int n = n_nx;
@@ -377,7 +399,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
     const int q = wave * 16 + r;
     const bool qok = q < n;
     stage_rows_store<NPAD>(buf, tid, n, sv);
-    gate_store<NPAD>(kg, tid, n, gv);
+    gate_store<NPAD>(kg, kw, tid, n, gv, gl);
     __syncthreads();
     float4 vpre[8];  // V, read while Q K^T and the softmax run
     stage_t_load<NPAD, BF>(qkv, 256, ld, base, n, tid, vpre);
@@ -394,13 +416,15 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
         for (int kt = 0; kt < NT; ++kt) *(floatx4 *)(lp + 16 * kt) = st[kt];
       }
       const float wq = qok ? kg[q].w : 0.f;
+      const double wqd = qok ? kw[q] : 0.0;
       float mx = -FLT_MAX;
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = kt * 16 + 4 * g + v;
-          float l = (st[kt][v] + shift) * wq * kg[k].w - shift;
+          float l = BF ? (st[kt][v] + shift) * wq * kg[k].w - shift
+                       : logit64(st[kt][v], wqd, kw[k], shift);
           l = k < n ? l : -INFINITY;
           st[kt][v] = l;
           mx = fmaxf(mx, l);
@@ -431,7 +455,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
         n_nx = nnei[inx];
         base_nx = pair_off[inx];
         stage_rows_load<NPAD, BF>(qkv, 128, ld, base_nx, n_nx, tid, sv);
-        gv = gate_load(geom, base_nx, n_nx, tid);
+        gv = gate_load(geom, base_nx, n_nx, tid, gl);
         load_rows<BF>(qkv, 0, ld, base_nx, n_nx, q, g, qv);
       }
     }
@@ -487,8 +511,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     float *__restrict__ dqkv, float4 *__restrict__ astat, float4 *__restrict__ qside) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
-  float4 *kg = smem;                  // [NPAD] rhat, sw
-  float *buf = (float *)(kg + NPAD);  // V rows, then K^T
+  float4 *kg = smem;                     // [NPAD] rhat, sw
+  double *kw = (double *)(kg + NPAD);    // [NPAD] switch values in FP64
+  float *buf = (float *)(kw + NPAD);     // V rows, then K^T
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
@@ -505,12 +530,13 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const bool qok = q < n;
     float4 sv[8];
     stage_rows_load<NPAD, BF>(qkv, 256, ld, base, n, tid, sv);  // V
-    const float4 gv = gate_load(geom, base, n, tid);
+    float gl;
+    const float4 gv = gate_load(geom, base, n, tid, gl);
     floatx4 dov[8], ov[8];
     load_rows<BF>(dO, 0, 128, base, n, q, g, dov);
     load_rows<BF>(o, 0, 128, base, n, q, g, ov);
     stage_rows_store<NPAD>(buf, tid, n, sv);
-    gate_store<NPAD>(kg, tid, n, gv);
+    gate_store<NPAD>(kg, kw, tid, n, gv, gl);
     __syncthreads();
     float dq = 0.f;
     if (wave < ntile) {
@@ -533,6 +559,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       const int qr = qok ? q : 0;
       const float4 gq = kg[q];
       const float wq = qok ? gq.w : 0.f;
+      const double wqd = qok ? kw[q] : 0.0;
       const float2 fs = fstat[base + qr];
       const float m = fs.x, invz = fs.y;
       if (g == 0 && qok) astat[base + q] = make_float4(m, invz, dq, 0.f);
@@ -555,7 +582,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
           const float ww = wq * gk.w;
           const float lm = ok ? lcur[v] : 0.f;
-          const float l = (lm + shift) * ww - shift;
+          const float l = BF ? (lm + shift) * ww - shift : logit64(lm, wqd, kw[k], shift);
           const float p = ok ? (BF ? exp_hw(l - m) : expf(l - m)) * invz : 0.f;
           const float h = ww * c;
           const float dH = da[kt][v] * p;
@@ -598,7 +625,8 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
   extern __shared__ float4 smem[];
   float4 *kg = smem;                     // [NPAD] rhat, sw
   float4 *stats = kg + NPAD;             // [NPAD] m, 1/Z, D_q of each query
-  float *buf = (float *)(stats + NPAD);  // dO rows, then Q^T
+  double *kw = (double *)(stats + NPAD); // [NPAD] switch values in FP64
+  float *buf = (float *)(kw + NPAD);     // dO rows, then Q^T
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
@@ -615,7 +643,8 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     const int base = pair_off[i];
     float4 sv[8];
     stage_rows_load<NPAD, BF>(dO, 0, 128, base, n, tid, sv);  // dO
-    const float4 gv = gate_load(geom, base, n, tid);
+    float gl;
+    const float4 gv = gate_load(geom, base, n, tid, gl);
     const float4 av = astat[base + (tid < n ? tid : 0)];
     floatx4 vreg[8];
     load_rows<BF>(qkv, 256, ld, base, n, wave * 16 + r, g, vreg);
@@ -623,7 +652,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
     stage_rows_store<NPAD>(buf, tid, n, sv);
-    gate_store<NPAD>(kg, tid, n, gv);
+    gate_store<NPAD>(kg, kw, tid, n, gv, gl);
     if (tid < NPAD) stats[tid] = tid < n ? av : make_float4(0.f, 1.f, 0.f, 0.f);
     __syncthreads();
     float4 qpre[8];
@@ -635,6 +664,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     if (wave < ntile) {
       const float4 gk = kg[kk];
       const float wk = kok ? gk.w : 0.f;
+      const double wkd = kok ? kw[kk] : 0.0;
       // lam of this key against the queries of one tile (lane: key r,
       // queries 4g + v), read one query tile ahead
       const float *lc = lam + (size_t)base * kLamLd + kk;
@@ -667,7 +697,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
           const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
           const float ww = gq.w * wk;
           const float lm = ok ? lcur[v] : 0.f;
-          const float l = (lm + shift) * ww - shift;
+          const float l = BF ? (lm + shift) * ww - shift : logit64(lm, kw[qq], wkd, shift);
           const float p = ok ? exp_hw(l - sq.x) * sq.y : 0.f;
           const float h = ww * c;
           const float dav = dk[qt][v];
@@ -954,15 +984,15 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
 // costs one wave of exiting blocks.
 template <int NPAD>
 size_t fwd_lds() {
-  return sizeof(float4) * NPAD + sizeof(float) * stage_floats<NPAD>();
+  return (sizeof(float4) + sizeof(double)) * NPAD + sizeof(float) * stage_floats<NPAD>();
 }
 template <int NPAD>
 size_t bwdq_lds() {
-  return sizeof(float4) * NPAD + sizeof(float) * stage_floats<NPAD>();
+  return (sizeof(float4) + sizeof(double)) * NPAD + sizeof(float) * stage_floats<NPAD>();
 }
 template <int NPAD>
 size_t bwdk_lds() {
-  return sizeof(float4) * 2 * NPAD + sizeof(float) * stage_floats<NPAD>();
+  return (sizeof(float4) * 2 + sizeof(double)) * NPAD + sizeof(float) * stage_floats<NPAD>();
 }
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.

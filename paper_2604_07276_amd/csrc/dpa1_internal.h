@@ -26,8 +26,8 @@ __device__ __forceinline__ float tanh_fast(float x) {
 }
 
 // Geometry record of one neighbour pair (8 floats):
-//   s = sw/r, rhat (3), sw, r, dsw/dr, unused.
-enum GeomField { G_S = 0, G_RX = 1, G_RY = 2, G_RZ = 3, G_SW = 4, G_R = 5, G_DSW = 6 };
+//   s = sw/r, rhat (3), sw, r, dsw/dr, and the FP32 remainder sw - (float)sw.
+enum GeomField { G_S = 0, G_RX = 1, G_RY = 2, G_RZ = 3, G_SW = 4, G_R = 5, G_DSW = 6, G_SWLO = 7 };
 constexpr int kGeom = 8;
 
 // Cell grid used for the O(N) neighbour search.

@@ -262,7 +262,8 @@ __global__ __launch_bounds__(kEnvWaves * 64) void k_env_embed1(
     const double sv = sw / r;
     float4 *gp = (float4 *)(geom + (size_t)p * kGeom);
     gp[0] = make_float4((float)sv, (float)(d[0] / r), (float)(d[1] / r), (float)(d[2] / r));
-    gp[1] = make_float4((float)sw, (float)r, (float)dsw, 0.0f);
+    // slot 7: FP32 remainder of sw (the FP32 attention logits take hi + lo in FP64)
+    gp[1] = make_float4((float)sw, (float)r, (float)dsw, (float)(sw - (double)(float)sw));
     const float s32 = (float)sv;
     const float *tt = tab + ((size_t)tj * ntypes + ti) * ld1;
     float4 *hp = (float4 *)(h1 + (size_t)p * ld1);

@@ -100,3 +100,27 @@ def test_stale_forward_raises(model):
         torch.autograd.grad(e1.sum(), x)
     (g,) = torch.autograd.grad(e2.sum(), x)
     assert torch.isfinite(g).all()
+
+
+def test_backward_raises_on_device_error_and_inplace_edit(model, weights_path):
+    import torch
+    from paper_2604_07276_amd import binding
+    from paper_2604_07276_amd.autograd import atomic_energies
+    s = synth.parity_system(8)
+    print("case: backward after a neighbour overflow; backward after an in-place edit", flush=True)
+    small = binding.Model(weights_path, RC, 40)
+    try:
+        x = _dev(s.coords).requires_grad_(True)
+        e = atomic_energies(small, x, _dev(s.types), s.box, 192, 0)
+        with pytest.raises(binding.DPError) as ei:
+            torch.autograd.grad(e.sum(), x)
+        assert ei.value.code == -4
+    finally:
+        small.close()
+    leaf = _dev(s.coords).requires_grad_(True)
+    x = leaf * 1.0  # a non-leaf that can be edited in place
+    e = atomic_energies(model, x, _dev(s.types), s.box, 192, 0)
+    with torch.no_grad():
+        x.add_(0.01)
+    with pytest.raises(RuntimeError):
+        torch.autograd.grad(e.sum(), leaf)
