@@ -87,10 +87,31 @@ int dp_train_resume(dp_trainer *t, const char *path);
 
 void dp_train_destroy(dp_trainer *t);
 
+/* Largest n accepted by the force-error calls (3n + 2^16 fits an int). */
+#define DP_FORCE_ERROR_MAX_ATOMS 700000000
+
 /* Audit helper: over n atoms, rmse_max [2] (host) = (sqrt(sum |a - b|^2 / (3n)),
- * max_k,c |a_kc - b_kc|) of two device force arrays [n][3]; synchronous. */
+ * max_k,c |a_kc - b_kc|) of two device force arrays [n][3]; synchronous.
+ * Allocates and frees a small device buffer for its partial sums per call.
+ * DP_ERR_ARG for n < 0, n > DP_FORCE_ERROR_MAX_ATOMS or a NULL pointer. */
 int dp_force_error(const double *d_a, const double *d_b, int n, double *rmse_max,
                    void *hip_stream);
+
+/* The same audit reduction for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops): no hipMalloc, hipFree
+ * or other allocation.  The per-block partial sums live in a fixed 4 KiB
+ * device array inside the library (one copy per GPU, held until the process
+ * ends); the 256-block cap of the reduction makes every accepted n fit.
+ *   d_a, d_b     device force arrays [n][3] (FP64), caller-owned.
+ *   d_rmse_max   device output [2]: (RMSE, max abs difference), the values
+ *                dp_force_error returns (the partial sums are added in the
+ *                same order); zeros for n = 0.
+ *   hip_stream   stream to enqueue on (NULL: default stream); asynchronous.
+ * DP_ERR_ARG for n < 0, n > DP_FORCE_ERROR_MAX_ATOMS or a NULL pointer,
+ * before any device work.  Calls that overlap on one GPU share the array and
+ * race: serialise them (one stream, or events). */
+int dp_force_error_noalloc(const double *d_a, const double *d_b, int n, double *d_rmse_max,
+                           void *hip_stream);
 
 #ifdef __cplusplus
 }

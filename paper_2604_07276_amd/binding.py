@@ -29,7 +29,7 @@ EXPORTED = ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
             # student trainer (include/dpa1_train.h)
             "dp_train_create", "dp_train_gradient", "dp_train_step", "dp_train_params",
             "dp_train_save", "dp_train_checkpoint", "dp_train_resume", "dp_train_destroy",
-            "dp_force_error")
+            "dp_force_error", "dp_force_error_noalloc")
 PREC_FP32 = 0
 PREC_BF16 = 1
 
@@ -88,12 +88,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dp_train_destroy.argtypes = [P]
     lib.dp_train_destroy.restype = None
     lib.dp_force_error.argtypes = [P, P, I, P, P]
+    lib.dp_force_error_noalloc.argtypes = [P, P, I, P, P]
     for name in ("dp_create", "dp_compute", "dp_compute_device", "dp_forward_device",
                  "dp_backward_device", "dp_set_precision", "dp_set_memory_budget",
                  "dp_memory_info", "dp_sync", "dp_debug_nlist",
                  "dp_set_timing", "dp_kernel_times", "dp_model_info", "dp_train_create",
                  "dp_train_gradient", "dp_train_step", "dp_train_params", "dp_train_save",
-                 "dp_train_checkpoint", "dp_train_resume", "dp_force_error"):
+                 "dp_train_checkpoint", "dp_train_resume", "dp_force_error",
+                 "dp_force_error_noalloc"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -321,3 +323,12 @@ def force_error(a, b, stream=None):
     _check(_lib.dp_force_error(_ptr(a), _ptr(b), int(a.shape[0]), out.ctypes.data,
                                _stream_ptr(stream)))
     return float(out[0]), float(out[1])
+
+
+def force_error_noalloc(a, b, out, stream=None):
+    """dp_force_error_noalloc: (RMSE, max abs error) of two [N, 3] float64
+    device force arrays into the float64 device tensor ``out`` [2],
+    asynchronously, without any device allocation."""
+    load_library()
+    _check(_lib.dp_force_error_noalloc(_ptr(a), _ptr(b), int(a.shape[0]), _ptr(out),
+                                       _stream_ptr(stream)))

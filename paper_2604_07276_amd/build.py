@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpa1.so")
 SOURCES = ["dpa1.cpp", "train.cpp", "nlist.hip", "gemm.hip", "attn.hip", "embed.hip", "misc.hip",
-           "train.hip"]
+           "train.hip", "noalloc.hip"]
 
 
 def hipcc():

@@ -568,6 +568,9 @@ int dp_force_error(const double *d_a, const double *d_b, int n, double *rmse_max
                    void *hip_stream) {
   if (!rmse_max || n < 0 || (n > 0 && (!d_a || !d_b)))
     return fail(DP_ERR_ARG, "bad arguments");
+  if (n > DP_FORCE_ERROR_MAX_ATOMS)
+    return fail(DP_ERR_ARG, "n = %d exceeds DP_FORCE_ERROR_MAX_ATOMS (%d)", n,
+                DP_FORCE_ERROR_MAX_ATOMS);
   rmse_max[0] = rmse_max[1] = 0.0;
   if (n == 0) return DP_OK;
   hipStream_t s = (hipStream_t)hip_stream;
