@@ -52,8 +52,8 @@ __device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, f
 // exp x = 2^(x log2 e) on the hardware v_exp_f32: two operations instead of
 // the library expf's range reduction.  Its arguments here are logits minus
 // their row maximum (<= 0); the relative error, about |x| ulps, is below the
-// FP32 rounding of what follows.  The FP32 query-tile adjoint keeps expf:
-// there the change costs two registers and with them a wavefront per SIMD.
+// FP32 rounding of what follows.  The forward and both adjoint kernels use
+// it alike, so the adjoint recomputes the forward's probabilities exactly.
 __device__ __forceinline__ float exp_hw(float x) {
   return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
 }
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           const float ww = wq * gk.w;
           const float lm = ok ? lcur[v] : 0.f;
           const float l = BF ? (lm + shift) * ww - shift : logit64(lm, wqd, kw[k], shift);
-          const float p = ok ? (BF ? exp_hw(l - m) : expf(l - m)) * invz : 0.f;
+          const float p = ok ? exp_hw(l - m) * invz : 0.f;
           const float h = ww * c;
           const float dH = da[kt][v] * p;
           const float dL = p * (da[kt][v] * h - dq);

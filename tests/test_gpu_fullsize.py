@@ -19,8 +19,8 @@
 
 Bars: FP32 as in the small parity tests (|dE|/N <= 1e-6 eV, max |dF| <=
 1e-4 eV/A, |dXi|/N <= 1e-6 eV, e_i <= 1e-5 eV, lists bit-exact); BF16 force
-RMSE <= 5e-3 eV/A, |dE|/N <= 5e-4 eV, and a loose bound on the largest force
-error that catches indexing mistakes.
+RMSE <= 5e-3 eV/A over every atom, |dE|/N <= 5e-4 eV, and a loose bound on
+the largest force error that catches indexing mistakes.
 """
 
 import sys
@@ -273,7 +273,13 @@ def test_replica_62672(model, protein, oracle_frame0, replica_oracle, precision)
         assert dE <= E_TOL and np.abs(dF_all).max() <= F_TOL
         assert np.abs(V - 4 * Vo).max() / nb <= V_TOL
     else:
-        assert de_s.mean() <= BF_E_TOL and rmse_s <= BF_F_RMSE
-        assert np.linalg.norm(dF_s, axis=1).max() <= BF_F_MAX
+        # The BF16 force error is heavy-tailed: a handful of centres where two
+        # opposite neighbours attend strongly to each other amplify operand
+        # rounding ~1e4-fold (the 10 worst atoms of the frame carry ~3/4 of
+        # its squared error), so the RMSE of a 1,000-atom sample depends on
+        # whether it holds one of them.  The 5e-3 target is asserted on every
+        # atom; the sample's RMSE is reported and bounded at twice the target.
         assert dE <= BF_E_TOL and rmse_all <= BF_F_RMSE
         assert np.linalg.norm(dF_all, axis=1).max() <= BF_F_MAX
+        assert de_s.mean() <= BF_E_TOL and rmse_s <= 2 * BF_F_RMSE
+        assert np.linalg.norm(dF_s, axis=1).max() <= BF_F_MAX
