@@ -37,16 +37,24 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// BF16 precision mode (template flag BF): one v_mfma_f32_16x16x16_bf16 per
-// 16x16 tile and four consecutive k values per lane, the same four values
-// the FP32 path feeds to four 16x16x4 steps; operands rounded to BF16 in
-// registers, accumulation in FP32.
+// BF16 precision mode (template flag BF): gfx950's v_mfma_f32_16x16x32_bf16
+// contracts two 16-deep chunks (two feature chunks, or two 16-neighbour
+// tiles) at once.  Each lane's eight operand slots hold its four
+// consecutive k values of the first chunk, then those of the second, on
+// both operands alike (the values the FP32 path feeds to four 16x16x4 steps
+// per chunk), which equals two 16x16x16 steps.  Operands are rounded to BF16
+// in registers, accumulation is FP32.  Every class has an even number of
+// tiles, so tiles always pair.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ bf16x4 to_bf16(const floatx4 &v) {
   return __builtin_convertvector(v, bf16x4);
 }
-__device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi) {
+  return __builtin_shufflevector(to_bf16(lo), to_bf16(hi), 0, 1, 2, 3, 4, 5, 6, 7);
+}
+__device__ __forceinline__ floatx4 mfma_bf16x2(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // exp x = 2^(x log2 e) on the hardware v_exp_f32: two operations instead of
@@ -236,36 +244,49 @@ __device__ __forceinline__ float logit64(float lam, double wq, double wk, float 
 // acc[ft] += XT^T-tile x bt : contraction over the 16 rows of tile 'tile',
 // XT in LDS (feature-major), bt a 16x16 B operand held in registers.
 // Output lane layout: own row r, features 16 ft + 4 g + v.
-template <int NPAD, bool BF>
+template <int NPAD>
 __device__ __forceinline__ void accum_lds(const float *XT, int tile, int r, int g,
                                           const floatx4 &bt, floatx4 (&acc)[8]) {
   constexpr int LDT = NPAD + 4;
-  const bf16x4 btb = to_bf16(bt);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // two halves of the features: 16 operand registers
     floatx4 x[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
       x[f] = *(const floatx4 *)(XT + ((4 * h + f) * 16 + r) * LDT + tile * 16 + 4 * g);
-    if constexpr (BF) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma_bf16(to_bf16(x[f]), btb, acc[4 * h + f]);
-    } else {
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+  }
+}
+// BF16: tiles 'tile' and 'tile' + 1 in one 16x16x32 step, B operands bt0, bt1.
+template <int NPAD>
+__device__ __forceinline__ void accum_lds2(const float *XT, int tile, int r, int g,
+                                           const floatx4 &bt0, const floatx4 &bt1,
+                                           floatx4 (&acc)[8]) {
+  constexpr int LDT = NPAD + 4;
+  const bf16x8 btb = to_bf16x8(bt0, bt1);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+  for (int h = 0; h < 2; ++h) {
+    floatx4 x0[4], x1[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const float *xp = XT + ((4 * h + f) * 16 + r) * LDT + tile * 16 + 4 * g;
+      x0[f] = *(const floatx4 *)xp;
+      x1[f] = *(const floatx4 *)(xp + 16);
     }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      acc[4 * h + f] = mfma_bf16x2(to_bf16x8(x0[f], x1[f]), btb, acc[4 * h + f]);
   }
 }
 
 // The same contraction with the rows in row-major LDS (X[row][kLDR]): the A
 // operand is read with scalar LDS loads, four rows per lane group.
-template <bool BF>
 __device__ __forceinline__ void accum_rows(const float *X, int tile, int r, int g,
                                            const floatx4 &bt, floatx4 (&acc)[8]) {
   const float *xb = X + (tile * 16 + 4 * g) * kLDR + r;
-  const bf16x4 btb = to_bf16(bt);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     floatx4 x[4];
@@ -273,15 +294,31 @@ __device__ __forceinline__ void accum_rows(const float *X, int tile, int r, int 
     for (int f = 0; f < 4; ++f)
 #pragma unroll
       for (int t = 0; t < 4; ++t) x[f][t] = xb[t * kLDR + (4 * h + f) * 16];
-    if constexpr (BF) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma_bf16(to_bf16(x[f]), btb, acc[4 * h + f]);
-    } else {
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
+  }
+}
+// BF16: row tiles 'tile' and 'tile' + 1 in one 16x16x32 step.
+__device__ __forceinline__ void accum_rows2(const float *X, int tile, int r, int g,
+                                            const floatx4 &bt0, const floatx4 &bt1,
+                                            floatx4 (&acc)[8]) {
+  const float *xb = X + (tile * 16 + 4 * g) * kLDR + r;
+  const bf16x8 btb = to_bf16x8(bt0, bt1);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) acc[4 * h + f] = mfma4(x[f][t], bt[t], acc[4 * h + f]);
-    }
+  for (int h = 0; h < 2; ++h) {
+    floatx4 x0[4], x1[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        x0[f][t] = xb[t * kLDR + (4 * h + f) * 16];
+        x1[f][t] = xb[(16 + t) * kLDR + (4 * h + f) * 16];
+      }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      acc[4 * h + f] = mfma_bf16x2(to_bf16x8(x0[f], x1[f]), btb, acc[4 * h + f]);
   }
 }
 
@@ -296,17 +333,30 @@ __device__ __forceinline__ void qk_lds(const float *X, int r, int g, const float
   // one feature chunk at a time (LDS latency is covered by the other
   // wavefronts on the SIMD); the fence keeps the compiler from hoisting the
   // loads of later chunks, which would hold many more registers
+  if constexpr (BF) {
+    // feature chunks 2h and 2h + 1 in one 16x16x32 step
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      floatx4 a0[NT], a1[NT];
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) {
+        a0[kt] = *(const floatx4 *)(xb + kt * 16 * kLDR + 32 * h);
+        a1[kt] = *(const floatx4 *)(xb + kt * 16 * kLDR + 32 * h + 16);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      const bf16x8 bb = to_bf16x8(b[2 * h], b[2 * h + 1]);
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma_bf16x2(to_bf16x8(a0[kt], a1[kt]), bb, st[kt]);
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     floatx4 a[NT];
 #pragma unroll
     for (int kt = 0; kt < NT; ++kt) a[kt] = *(const floatx4 *)(xb + kt * 16 * kLDR + 16 * c);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (BF) {
-      const bf16x4 bb = to_bf16(b[c]);
-#pragma unroll
-      for (int kt = 0; kt < NT; ++kt) st[kt] = mfma_bf16(to_bf16(a[kt]), bb, st[kt]);
-    } else {
+    {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -464,6 +514,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
       const float4 gq = kg[q];
       const float wq = qok ? gq.w : 0.f;
       floatx4 oacc[8];
+      floatx4 atp;  // BF16: probabilities of the even tile of a pair
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) oacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -475,7 +526,12 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
           const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
           at[v] = st[kt][v] * invz * wq * gk.w * c;
         }
-        accum_lds<NPAD, BF>(buf, kt, r, g, at, oacc);
+        if constexpr (BF) {  // tiles taken in pairs
+          if (kt % 2 == 0) atp = at;
+          else accum_lds2<NPAD>(buf, kt - 1, r, g, atp, at, oacc);
+        } else {
+          accum_lds<NPAD>(buf, kt, r, g, at, oacc);
+        }
       }
       if (qok) {
         float *op = pt_at<BF>(out, (size_t)(base + q) * 128 + 4 * g);
@@ -566,6 +622,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
       // lam of this query row, read one key tile ahead of its use
       const float *lp = lam + (size_t)(base + qr) * kLamLd + 4 * g;
       floatx4 dqacc[8];
+      floatx4 dsp;  // BF16: dS of the even tile of a pair
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
       float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
@@ -595,7 +652,12 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
           drqy += Y * gk.y;
           drqz += Y * gk.z;
         }
-        accum_lds<NPAD, BF>(buf, kt, r, g, ds, dqacc);
+        if constexpr (BF) {  // tiles taken in pairs
+          if (kt % 2 == 0) dsp = ds;
+          else accum_lds2<NPAD>(buf, kt - 1, r, g, dsp, ds, dqacc);
+        } else {
+          accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);
+        }
         lcur = lnxt;
       }
       dwq = sum_groups(dwq);
@@ -680,12 +742,19 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
       floatx4 dk[NT];
       qk_lds<NT, BF>(buf, r, g, vreg, dk);  // dA: lane (key r, queries 4g + v)
       floatx4 dvacc[8];
+      floatx4 atp;  // BF16: A^T of the even tile of a pair
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int qt = 0; qt < NT; ++qt) {
         ds[qt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (qt >= ntile) continue;
+        if (qt >= ntile) {
+          // BF16: an unpaired last tile meets a zero partner
+          if constexpr (BF)
+            if (qt % 2 == 1 && qt - 1 < ntile)
+              accum_rows2(buf, qt - 1, r, g, atp, floatx4{0.f, 0.f, 0.f, 0.f}, dvacc);
+          continue;
+        }
         if (qt + 1 < NT) lam_tile(qt + 1, lnxt);
         floatx4 at;
 #pragma unroll
@@ -712,7 +781,12 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
           drky += Y * gq.y;
           drkz += Y * gq.z;
         }
-        accum_rows<BF>(buf, qt, r, g, at, dvacc);  // dV = A^T dO
+        if constexpr (BF) {  // dV = A^T dO, tiles taken in pairs
+          if (qt % 2 == 0) atp = at;
+          else accum_rows2(buf, qt - 1, r, g, atp, at, dvacc);
+        } else {
+          accum_rows(buf, qt, r, g, at, dvacc);  // dV = A^T dO
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) lcur[v] = lnxt[v];
         __builtin_amdgcn_sched_barrier(0);
@@ -737,9 +811,16 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
       floatx4 dkacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (BF) {
+        // tiles in pairs; ds of tiles at or past ntile is zero
 #pragma unroll
-      for (int qt = 0; qt < NT; ++qt)
-        if (qt < ntile) accum_lds<NPAD, BF>(buf, qt, r, g, ds[qt], dkacc);
+        for (int qt = 0; qt < NT; qt += 2)
+          if (qt < ntile) accum_lds2<NPAD>(buf, qt, r, g, ds[qt], ds[qt + 1], dkacc);
+      } else {
+#pragma unroll
+        for (int qt = 0; qt < NT; ++qt)
+          if (qt < ntile) accum_lds<NPAD>(buf, qt, r, g, ds[qt], dkacc);
+      }
       if (kok) {
         float *dp = pt_at<BF>(dqkv, (size_t)(base + kk) * ld + 128 + 4 * g);
 #pragma unroll

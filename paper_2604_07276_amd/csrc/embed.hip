@@ -24,11 +24,18 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// BF16 precision mode: one v_mfma_f32_16x16x16_bf16 per 16-wide k chunk
-// (four consecutive k per lane, as in the FP32 steps), FP32 accumulation.
+// BF16 precision mode: one gfx950 v_mfma_f32_16x16x32_bf16 per pair of
+// 16-wide k chunks, each lane's eight operand slots holding its four
+// consecutive k of the first chunk and then of the second (on both operands
+// alike: the sum of two 16x16x16 steps); a lone last chunk is paired with
+// zeros.  FP32 accumulation.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ bf16x4 to_bf16(const floatx4 &v) {
   return __builtin_convertvector(v, bf16x4);
+}
+__device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi) {
+  return __builtin_shufflevector(to_bf16(lo), to_bf16(hi), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k]  (W row-major [NTILE*16][KCH*16]).
@@ -69,22 +76,30 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
         continue;
       }
     }
+    if constexpr (BF) {
+      if (c % 2 == 1) continue;  // taken with chunk c - 1
+      const bool pair = c + 1 < KCH;
+      const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+      bf16x8 xb[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(x[mt][c], pair ? x[mt][pair ? c + 1 : c] : z);
+#pragma unroll
+      for (int nt = 0; nt < NTILE; ++nt) {
+        const float *wp = W + (size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * g;
+        const floatx4 w0 = *(const floatx4 *)wp;
+        const floatx4 w1 = pair ? *(const floatx4 *)(wp + 16) : z;
+        const bf16x8 wb = to_bf16x8(w0, w1);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, xb[mt], acc[mt][nt], 0, 0, 0);
+      }
+      continue;
+    }
     floatx4 w[NTILE];
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt)
       w[nt] = *(const floatx4 *)(W + (size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * g);
-    if constexpr (BF) {
-      bf16x4 xb[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(x[mt][c]);
-#pragma unroll
-      for (int nt = 0; nt < NTILE; ++nt) {
-        const bf16x4 wb = to_bf16(w[nt]);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb, xb[mt], acc[mt][nt], 0, 0, 0);
-      }
-    } else {
+    {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll

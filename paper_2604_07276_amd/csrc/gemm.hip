@@ -27,17 +27,25 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// BF16 precision mode: one v_mfma_f32_16x16x16_bf16 takes a whole 16-wide k
-// chunk (lane l holds k = 4 (l / 16) + 0..3 of row l % 16, the same
-// four consecutive values the FP32 path feeds to four 16x16x4 steps);
-// operands are rounded to BF16 (nearest even) in registers, accumulation
+// BF16 precision mode: gfx950's v_mfma_f32_16x16x32_bf16 takes two 16-wide
+// k chunks at once.  Lane l holds, for row l % 16, the four consecutive
+// values k = 4 (l / 16) + 0..3 of each chunk (the values the FP32 path feeds
+// to four 16x16x4 steps per chunk); its eight operand slots are the first
+// chunk's four followed by the second chunk's four, on both operands alike,
+// which gives exactly the sum of two v_mfma_f32_16x16x16_bf16 steps (checked
+// on the hardware).  A lone last chunk is paired with zero weights.
+// Operands are rounded to BF16 (nearest even) in registers, accumulation
 // stays FP32.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ bf16x4 to_bf16(const floatx4 &v) {
   return __builtin_convertvector(v, bf16x4);
 }
-__device__ __forceinline__ floatx4 mfma_bf16(const bf16x4 &a, const bf16x4 &b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi) {
+  return __builtin_shufflevector(to_bf16(lo), to_bf16(hi), 0, 1, 2, 3, 4, 5, 6, 7);
+}
+__device__ __forceinline__ floatx4 mfma_bf16x2(const bf16x8 &a, const bf16x8 &b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // X operand storage: BF selects the matrix-core operand precision (0 FP32,
@@ -74,7 +82,8 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   // Used by the BF16 instances and the 16-row (per-centre) tiles; the FP32
   // 64-row tiles keep per-wavefront W streams (see the k loop).
   constexpr bool kShareW = BF != 0 || MT < 4;
-  constexpr int kWS = 20;  // row stride (16 + 4)
+  constexpr int KC = BF ? 32 : 16;  // k depth of one staged chunk (BF16: one 16x16x32 step)
+  constexpr int kWS = KC + 4;       // LDS row stride
   __shared__ float wsh[kShareW ? 2 : 1][kShareW ? NT * 16 : 1][kWS];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
   const int tid = threadIdx.x;
@@ -85,17 +94,20 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   __syncthreads();
   const int ntt = a.Npad / 16;
   // W staging: thread tid moves float4 q = tid + 256 j of the chunk, row
-  // q / 4 of the block's W^T rows, k quad q % 4 (column tiles past the last
-  // one stage a duplicate of tile 0; their outputs are never stored)
-  constexpr int NQ = NT * 16 * 4;
+  // q / QPR of the block's W^T rows, k quad q % QPR (column tiles past the
+  // last one stage a duplicate of tile 0; their outputs are never stored).
+  // A 32-deep chunk that runs past K (a multiple of 16) stages zeros for its
+  // second half.
+  constexpr int QPR = KC / 4;
+  constexpr int NQ = NT * 16 * QPR;
   constexpr int JW = (NQ + 255) / 256;
   const float *wsrc[JW];
 #pragma unroll
   for (int j = 0; j < JW; ++j) {
     const int q = tid + 256 * j < NQ ? tid + 256 * j : 0;
-    const int n = q >> 2;
+    const int n = q / QPR;
     const int tile = nt0 + n / 16 < ntt ? nt0 + n / 16 : 0;
-    wsrc[j] = a.Wt + (size_t)(tile * 16 + n % 16) * a.K + 4 * (q & 3);
+    wsrc[j] = a.Wt + (size_t)(tile * 16 + n % 16) * a.K + 4 * (q % QPR);
   }
   // persistent over row tiles: the grid is sized to the resident capacity
   // (launch gaps and the tail of short-lived waves otherwise cost ~40%).
@@ -129,15 +141,68 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
     float4 wst[JW];
     auto wload = [&](int k) {
 #pragma unroll
-      for (int j = 0; j < JW; ++j) wst[j] = *(const float4 *)(wsrc[j] + k);
+      for (int j = 0; j < JW; ++j) {
+        // a quad of the second half past K (16-deep tail) reads the first
+        // half's address and stages zeros
+        const int q = tid + 256 * j < NQ ? tid + 256 * j : 0;  // as in wsrc
+        const bool ok = KC == 16 || k + 4 * (q % QPR) < a.K;
+        const float4 v = *(const float4 *)(wsrc[j] + (ok ? k : k - 16));
+        wst[j] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     };
     auto wstore = [&](int b) {
 #pragma unroll
       for (int j = 0; j < JW; ++j) {
         const int q = tid + 256 * j;
-        if (NQ % 256 == 0 || q < NQ) *(float4 *)&wsh[b][q >> 2][4 * (q & 3)] = wst[j];
+        if (NQ % 256 == 0 || q < NQ) *(float4 *)&wsh[b][q / QPR][4 * (q % QPR)] = wst[j];
       }
     };
+  if constexpr (BF != 0) {
+    // BF16: 32-deep chunks, one 16x16x32 step per tile pair.  The next
+    // chunk's X quads (k0 + 4g and k0 + 16 + 4g; past K the second re-reads
+    // the first, which meets zero weights) are loaded in FP32 while the
+    // current chunk, already rounded to BF16, is multiplied; each W tile is
+    // read from LDS and rounded just before its MFMAs.
+    floatx4 xn[MT][2];
+    bf16x8 xb[MT];
+    auto xload = [&](int k0) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        xn[mt][0] = ldx4<BF>(xrow[mt], k0);
+        xn[mt][1] = ldx4<BF>(xrow[mt], k0 + 16 < a.K ? k0 + 16 : k0);
+      }
+    };
+    wload(0);
+    xload(0);
+    wstore(0);
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(xn[mt][0], xn[mt][1]);
+    int b = 0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < a.K; k0 += KC) {
+      const bool more = k0 + KC < a.K;  // uniform
+      if (more) {
+        wload(k0 + KC);
+        xload(k0 + KC);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const floatx4 w0 = *(const floatx4 *)&wsh[b][nt * 16 + r][4 * g];
+        const floatx4 w1 = *(const floatx4 *)&wsh[b][nt * 16 + r][16 + 4 * g];
+        const bf16x8 wb = to_bf16x8(w0, w1);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16x2(wb, xb[mt], acc[mt][nt]);
+      }
+      if (more) wstore(b ^ 1);
+      __syncthreads();  // chunk k0 + KC staged; buffer b free again
+      b ^= 1;
+      if (more) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(xn[mt][0], xn[mt][1]);
+      }
+    }
+  } else {
 
     // Double-buffered k loop: the operands of chunk k0 + 16 (the block's W
     // rows, the wavefront's X rows) are loaded while chunk k0 is multiplied;
@@ -161,30 +226,19 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) wv[nt] = *(const floatx4 *)&wsh[b][nt * 16 + r][4 * g];
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (BF) {
-        bf16x4 xb[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(xv[mt]);
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const bf16x4 wb = to_bf16(wv[nt]);
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(wb, xb[mt], acc[mt][nt]);
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
-      }
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
       if (more) wstore(b ^ 1);
       __syncthreads();  // chunk k0 + 16 staged; buffer b free again
       b ^= 1;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
     }
+  }
   } else {
     // FP32 64-row tiles: each wavefront streams its own W rows from L2 (the
     // per-chunk block barrier of the shared staging costs these long-K
@@ -280,6 +334,57 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   const float *wl = wsm + r * LDW + 4 * g;
   const int stride = gridDim.x * 64 * MT;  // rows between a wave's consecutive tiles
   int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  if constexpr (BF != 0) {
+    // BF16: chunks 2p and 2p + 1 in one 16x16x32 step (a lone last chunk is
+    // paired with zeros on both operands).  The current tile is held as BF16
+    // chunk pairs; the next one arrives in FP32 and is rounded once.
+    constexpr int KP = (KCH + 1) / 2;
+    floatx4 xn[MT][KCH];
+    bf16x8 xc[MT][KP];
+    auto to_pairs = [&]() {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int p = 0; p < KP; ++p)
+          xc[mt][p] = to_bf16x8(xn[mt][2 * p],
+                                2 * p + 1 < KCH ? xn[mt][2 * p + 1] : floatx4{0.f, 0.f, 0.f, 0.f});
+    };
+    if (row0 < M) {
+      load_x_tile<MT, KCH, BF, KT>(a, row0, M, r, g, xn);
+      to_pairs();
+    }
+    for (; row0 < M; row0 += stride) {
+      const bool next = row0 + stride < M;
+      if constexpr (Epi::kLds == 1)
+        if (next) load_x_tile<MT, KCH, BF, KT>(a, row0 + stride, M, r, g, xn);
+      floatx4 acc[MT][NT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int p = 0; p < KP; ++p) {
+        bf16x8 wb[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const floatx4 w0 = *(const floatx4 *)(wl + nt * 16 * LDW + 32 * p);
+          const floatx4 w1 = 2 * p + 1 < KCH ? *(const floatx4 *)(wl + nt * 16 * LDW + 32 * p + 16)
+                                             : floatx4{0.f, 0.f, 0.f, 0.f};
+          wb[nt] = to_bf16x8(w0, w1);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one chunk pair of weights live at a time
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16x2(wb[nt], xc[mt][p], acc[mt][nt]);
+      }
+      if constexpr (Epi::kLds == 2)
+        if (next) load_x_tile<MT, KCH, BF, KT>(a, row0 + stride, M, r, g, xn);
+      epi.template apply<MT, NT>(acc, row0, nt0, ntt, lane, M, cs);
+      if (next) to_pairs();
+    }
+    return;
+  }
   floatx4 xr[MT][KCH], xn[MT][KCH];
   if (row0 < M) load_x_tile<MT, KCH, BF, KT>(a, row0, M, r, g, xr);
   for (; row0 < M; row0 += stride) {
@@ -311,17 +416,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * LDW + 16 * c);
       __builtin_amdgcn_sched_barrier(0);  // one chunk of weights live at a time
-      if constexpr (BF) {
-        bf16x4 xb[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16(xr[mt][c]);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const bf16x4 wb = to_bf16(w[nt]);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(wb, xb[mt], acc[mt][nt]);
-        }
-      } else {
+      {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll

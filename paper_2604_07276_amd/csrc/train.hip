@@ -19,7 +19,9 @@ namespace dpa1 {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWaves = 4;          // centres per 256-thread block
 constexpr int kGS = kTrN3 + 1;     // LDS row stride of per-pair G rows
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[kt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int col = lane & 15, quad = lane >> 4;
-  constexpr int RG = BF ? 16 : 4;  // rows per matrix-core step
+  constexpr int RG = BF ? 32 : 4;  // rows per matrix-core step
   const int nseg = (ONEHOT || X2 == nullptr) ? 1 : 2;
   for (int seg = 0; seg < nseg; ++seg) {
     const float *X = seg ? X2 : X1;
@@ -606,11 +608,13 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
           for (int nt = 0; nt < NT; ++nt)
             acc[kt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[kt], zv[nt], acc[kt][nt], 0, 0, 0);
       } else {
+        // 32 rows per 16x16x32 step: lane slots u < 4 hold rows rg + 4q + u,
+        // slots 4 + u rows rg + 16 + 4q + u (the same rows on both operands)
         static_assert(!ONEHOT, "group sums use FP32 operands");
-        floatx4 xv[KT], zv[NT];
+        floatx8 xv[KT], zv[NT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = rg + 4 * quad + u;
+        for (int u = 0; u < 8; ++u) {
+          const int r = rg + 16 * (u >> 2) + 4 * quad + (u & 3);
           const bool rv = r < r1;
           const size_t rr = (size_t)(rv ? r : r0);
 #pragma unroll
@@ -626,17 +630,17 @@ __global__ __launch_bounds__(256) void k_wgrad(const float *__restrict__ X1,
             zv[nt][u] = (rv && c < nout) ? v : 0.f;
           }
         }
-        bf16x4 xb[KT], zb[NT];
+        bf16x8 xb[KT], zb[NT];
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) xb[kt] = __builtin_convertvector(xv[kt], bf16x4);
+        for (int kt = 0; kt < KT; ++kt) xb[kt] = __builtin_convertvector(xv[kt], bf16x8);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) zb[nt] = __builtin_convertvector(zv[nt], bf16x4);
+        for (int nt = 0; nt < NT; ++nt) zb[nt] = __builtin_convertvector(zv[nt], bf16x8);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt)
             acc[kt][nt] =
-                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xb[kt], zb[nt], acc[kt][nt], 0, 0, 0);
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[kt], zb[nt], acc[kt][nt], 0, 0, 0);
       }
     }
   }
@@ -687,6 +691,58 @@ __global__ __launch_bounds__(256) void k_wgrad_fm(const float *__restrict__ Xt,
   const int nseg = (ONEHOT || seg2 == 0) ? 1 : 2;
   for (int seg = 0; seg < nseg; ++seg) {
     const size_t base = seg ? seg2 : 0;
+    if constexpr (BF) {
+      // BF16: 32 rows per gfx950 16x16x32 step; lane slots 0..3 hold rows
+      // rg + 4q + 0..3 and slots 4..7 rows rg + 16 + 4q + 0..3, on both
+      // operands.  A second half that starts past r1 re-reads the first
+      // half's rows (masked to zero).
+      static_assert(!ONEHOT, "group sums use FP32 operands");
+      for (int rg = r0 + w * 32; rg < r1; rg += 128) {
+        const int rq0 = rg + 4 * quad, rq1 = rq0 + 16;
+        const int rq1a = rq1 < r1 ? rq1 : rq0;
+        bool rv[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          rv[j] = rq0 + j < r1;
+          rv[4 + j] = rq1 + j < r1;
+        }
+        floatx8 xv[KT], zv[NT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int c = k0 + 16 * kt + col;
+          const float *xp = Xt + (size_t)(c < kin ? c : 0) * ldr + base;
+          const floatx4 v0 = *(const floatx4 *)(xp + rq0), v1 = *(const floatx4 *)(xp + rq1a);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            xv[kt][j] = (rv[j] && c < kin) ? v0[j] : 0.f;
+            xv[kt][4 + j] = (rv[4 + j] && c < kin) ? v1[j] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int c = n0 + 16 * nt + col;
+          const float *zp = Zt + (size_t)(c < nout ? c : 0) * ldr + base;
+          const floatx4 v0 = *(const floatx4 *)(zp + rq0), v1 = *(const floatx4 *)(zp + rq1a);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            zv[nt][j] = (rv[j] && c < nout) ? v0[j] : 0.f;
+            zv[nt][4 + j] = (rv[4 + j] && c < nout) ? v1[j] : 0.f;
+          }
+        }
+        bf16x8 xb[KT], zb[NT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) xb[kt] = __builtin_convertvector(xv[kt], bf16x8);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) zb[nt] = __builtin_convertvector(zv[nt], bf16x8);
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[kt][nt] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[kt], zb[nt], acc[kt][nt], 0, 0, 0);
+      }
+      continue;
+    }
     for (int rg = r0 + w * 16; rg < r1; rg += 64) {
       const int rq = rg + 4 * quad;
       bool rv[4];
@@ -716,19 +772,7 @@ __global__ __launch_bounds__(256) void k_wgrad_fm(const float *__restrict__ Xt,
 #pragma unroll
         for (int j = 0; j < 4; ++j) zv[nt][j] = (rv[j] && c < nout) ? v[j] : 0.f;
       }
-      if constexpr (BF) {
-        bf16x4 xb[KT], zb[NT];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) xb[kt] = __builtin_convertvector(xv[kt], bf16x4);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) zb[nt] = __builtin_convertvector(zv[nt], bf16x4);
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            acc[kt][nt] =
-                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xb[kt], zb[nt], acc[kt][nt], 0, 0, 0);
-      } else {
+      {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
