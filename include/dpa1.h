@@ -49,14 +49,19 @@ enum dp_status {
   DP_ERR_SEL_OVERFLOW = -4,  /* an atom has more than sel neighbours within rcut */
   DP_ERR_WEIGHTS = -5,       /* weights file missing, malformed or unsupported */
   DP_ERR_DEVICE = -6,        /* HIP runtime error */
-  DP_ERR_OOM = -7            /* device allocation failed */
+  DP_ERR_OOM = -7,           /* device allocation failed, or the memory budget is too small */
+  DP_ERR_CAPACITY = -8       /* a device-memory step had more neighbour pairs than its
+                                workspace holds: its outputs are not valid; the workspace is
+                                laid out for the larger count at the next call */
 };
 
 /* Largest supported neighbour capacity. */
 #define DP_MAX_SEL 128
 
 /*
- * Load a weights file and upload the model to the current HIP device.
+ * Load a weights file and upload the model to the current HIP device: the
+ * DPA-1 model of Sec. II-B (type embedding, embedding net, gated attention
+ * layers, fitting net) with the cutoff rcut of the neighbour lists (Sec. II-C).
  *   weights_path  file in the DPA-1 weights format (magic "DPA1WTS"), FP64
  *                 tensors; they are rounded to FP32 once here.
  *   rcut          cutoff radius in Angstrom, > rcut_smth of the file.
@@ -68,8 +73,10 @@ enum dp_status {
 int dp_create(const char *weights_path, double rcut, int sel, dp_model **out);
 
 /*
- * Host-memory step: copies inputs to the device, runs the step on the
- * handle's own stream, copies results back and waits.
+ * Host-memory step (the per-step inference call of Sec. II-C: energy of the
+ * local atoms, forces on locals and ghosts per Eq. (7), F = -dE/dx per
+ * Eq. (2), one result copy back per output): copies inputs to the device,
+ * runs the step on the handle's own stream, copies results back and waits.
  *   coords       [(nloc+nghost)*3] FP64 positions.
  *   types        [nloc+nghost], each in [0, ntypes).
  *   box          [9] FP64, rows are the cell vectors (orthorhombic only, each
@@ -90,13 +97,18 @@ int dp_compute(dp_model *m, const double *coords, const int32_t *types, const do
                double *atom_energy);
 
 /*
- * Device-memory step, asynchronous on the caller's stream (hipStream_t, NULL
+ * Device-memory step (the same computation as dp_compute: Sec. II-C,
+ * Eq. (2), Eq. (7)), asynchronous on the caller's stream (hipStream_t, NULL
  * for the default stream).  d_coords, d_types, d_energy [1], d_forces, d_virial
  * [9] and d_atom_energy (optional) are device pointers with the layouts of
  * dp_compute; box is a host pointer as above.  The call returns after
- * enqueueing; conditions found on the device (an out-of-range type, a
- * neighbour overflow) are reported by dp_sync, and the outputs of such a step
- * are not meaningful.
+ * enqueueing, except in two cases where it first waits on the stream: with
+ * box == NULL (open boundaries) it reads the atoms' bounding box back to size
+ * the cell grid, and at the first step of a workspace (or after it grew) it
+ * reads the step's neighbour-pair count back to lay out the per-pair buffers.
+ * Conditions found on the device (an out-of-range type, a neighbour overflow,
+ * more neighbour pairs than the workspace holds: DP_ERR_CAPACITY) are
+ * reported by dp_sync, and the outputs of such a step are not meaningful.
  */
 int dp_compute_device(dp_model *m, const double *d_coords, const int32_t *d_types,
                       const double *box, int nloc, int nghost, double *d_energy,
@@ -141,7 +153,11 @@ int dp_backward_device(dp_model *m, const double *d_atom_weight, double *d_grad_
 enum dp_precision { DP_PREC_FP32 = 0, DP_PREC_BF16 = 1 };
 int dp_set_precision(dp_model *m, int precision);
 
-/* Memory budget of the workspace in bytes (0: unlimited, the default).  When
+/* Memory budget of the workspace in bytes (0: unlimited, the default); the
+ * motive is the memory growth of DP inference with system size (Sec. VI-B:
+ * ~7 GB for a small protein, an estimated >200 GB for 15k atoms).  The
+ * workspace holds its per-pair buffers for the real neighbour-pair count of
+ * the step that laid it out plus 1/8, not for nloc * sel pairs.  When
  * storing the activations of every attention layer for the adjoint would make
  * the workspace exceed it, the attention layers share one set of QKV,
  * attention-output, logit and softmax-statistics buffers and the adjoint
@@ -153,23 +169,28 @@ int dp_set_precision(dp_model *m, int precision);
  * step.  Returns DP_ERR_ARG for a negative or non-finite budget. */
 int dp_set_memory_budget(dp_model *m, double bytes);
 
-/* Workspace bytes currently allocated and whether the attention activations
- * are recomputed in the adjoint (1) or stored per layer (0). */
+/* Workspace bytes currently allocated (per-atom, per-centre and per-pair
+ * buffers) and whether the attention activations are recomputed in the
+ * adjoint (1) or stored per layer (0). */
 int dp_memory_info(const dp_model *m, int64_t *workspace_bytes, int32_t *recompute);
 
-/* Wait for the handle's last step and return its device-side status. */
+/* Wait for the handle's last step and return its device-side status
+ * (DP_ERR_TYPE, DP_ERR_SEL_OVERFLOW or DP_ERR_CAPACITY found on the device).
+ * Library plumbing: no passage of the paper defines it. */
 int dp_sync(dp_model *m);
 
 /*
- * Neighbour list of the last completed step: nlist [nloc*sel] with the
+ * Neighbour list of the last completed step (the full list within rcut of
+ * Sec. II-C, locals and ghosts as neighbours): nlist [nloc*sel] with the
  * neighbours of local atom i in ascending index order, padded with -1, and
  * nnei [nloc].  Host pointers; waits for the step.
  */
 int dp_debug_nlist(dp_model *m, int32_t *nlist, int32_t *nnei);
 
 /*
- * Per-kernel timing.  When enabled, every launch of a step is bracketed by
- * HIP events on its stream.  dp_kernel_times fills, for up to max entries,
+ * Per-kernel timing (measurement plumbing; no passage of the paper defines
+ * it).  When enabled, every launch of a step is bracketed by HIP events on
+ * its stream.  dp_kernel_times fills, for up to max entries,
  * the kernel name (NUL-terminated, 48 bytes each), the launch count and the
  * summed duration in milliseconds since the last reset; it returns the number
  * of distinct kernels.
@@ -177,13 +198,18 @@ int dp_debug_nlist(dp_model *m, int32_t *nlist, int32_t *nnei);
 int dp_set_timing(dp_model *m, int enable);
 int dp_kernel_times(dp_model *m, char *names, int64_t *counts, double *total_ms, int max);
 
-/* Model hyper-parameters: ints[8] = ntypes, tebd_dim, axis, n_attn, attn_dim,
+/* Model hyper-parameters of the loaded DPA-1 model (Sec. II-B):
+ * ints[8] = ntypes, tebd_dim, axis, n_attn, attn_dim,
  * embedding width M, fitting width, sel; dbls[3] = rcut, rcut_smth, attn_shift. */
 int dp_model_info(const dp_model *m, int32_t *ints, double *dbls);
 
+/* Release a handle: waits for its last step, frees its device weights and
+ * workspace.  NULL is ignored.  Library plumbing (no passage of the paper
+ * defines it). */
 void dp_destroy(dp_model *m);
 
-/* Message for the last nonzero return on the calling thread ("" if none). */
+/* Message for the last nonzero return on the calling thread ("" if none).
+ * Library plumbing (no passage of the paper defines it). */
 const char *dp_last_error(void);
 
 #ifdef __cplusplus

@@ -325,14 +325,24 @@ struct Carver {
   }
 };
 
-// Lays out every buffer for the given capacity; with base == nullptr it only
-// measures.  Per-pair buffers hold nloc*sel rows plus one tile of slack.
+// The workspace is two arenas.  The topology arena holds the per-atom and
+// per-centre buffers (coordinates, cell lists, neighbour lists, descriptor,
+// fitting net), laid out for nloc / nall / ncell.  The pair arena holds every
+// per-pair buffer (geometry, embedding, attention and their adjoints) for a
+// capacity of P pair rows, taken from the real neighbour-pair count of the
+// step that lays it out plus 1/8 headroom (and never more than nloc * sel),
+// instead of nloc * sel rows.  With base == nullptr the carvers only measure.
 // With shared set, every attention layer uses one set of QKV, attention-
 // output, logit and softmax-statistics buffers (the adjoint recomputes them).
-size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell, bool shared) {
+// The fused embedding kernels keep no hidden-layer activations, so their
+// per-layer buffers are not laid out.
+bool emb_is_fused(const dp_model *m) {
+  return m->emb.size() == 3 && emb_fused_supported(m->lde[0], m->lde[1], m->lde[2]);
+}
+
+size_t carve_topo(dp_model *m, char *base, int nloc, int nall, int ncell) {
   Carver c{base};
   auto &w = m->w;
-  const size_t P = (size_t)nloc * m->sel + 64;
   const size_t NL = (size_t)nloc + 16;
   w.coords = c.take<double>(3 * (size_t)nall);
   w.types = c.take<int32_t>(nall);
@@ -352,13 +362,38 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell, bool shared
   w.pair_off = c.take<int>(nloc + 1);
   w.ccount = c.take<int>(4);
   w.clist = c.take<int>(4 * (size_t)nloc);
+  w.T = c.take<float>(NL * 4 * m->M);
+  w.dmat = c.take<float>(NL * m->ldD);
+  w.e = c.take<float>(NL);
+  const int nf = (int)m->fit.size();
+  w.z.assign(nf, nullptr);
+  w.tf.assign(nf, nullptr);
+  w.fa.assign(nf, nullptr);
+  w.fdz.assign(nf, nullptr);
+  for (int l = 0; l < nf; ++l) {
+    w.z[l] = c.take<float>(NL * m->ldf[l]);
+    w.tf[l] = c.take<float>(NL * m->ldf[l]);
+    w.fa[l] = c.take<float>(NL * m->ldf[l]);
+    w.fdz[l] = c.take<float>(NL * m->ldf[l]);
+  }
+  w.dD = c.take<float>(NL * m->ldD);
+  return c.off + 256;
+}
+
+size_t carve_pairs(dp_model *m, char *base, size_t P, bool shared) {
+  Carver c{base};
+  auto &w = m->w;
+  const bool fused = emb_is_fused(m);
   w.geom = c.take<float>(P * kGeom);
   const int ne = (int)m->emb.size();
   w.h.assign(ne, nullptr);
   w.te.assign(ne, nullptr);
   for (int l = 0; l < ne; ++l) {
+    // fused: only the first layer's output (the adjoint's recomputation
+    // input) and the last one (G) are stored
+    if (fused && l > 0 && l < ne - 1) continue;
     w.h[l] = c.take<float>(P * m->lde[l]);
-    w.te[l] = l == 0 ? w.h[0] : c.take<float>(P * m->lde[l]);
+    w.te[l] = l == 0 ? w.h[0] : (fused ? nullptr : c.take<float>(P * m->lde[l]));
   }
   const int na = m->n_attn;
   w.qkv.assign(na, nullptr);
@@ -385,21 +420,6 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell, bool shared
     w.rstd[a] = c.take<float>(P);
     w.G[a + 1] = c.take<float>(P * m->ldM);
   }
-  w.T = c.take<float>(NL * 4 * m->M);
-  w.dmat = c.take<float>(NL * m->ldD);
-  w.e = c.take<float>(NL);
-  const int nf = (int)m->fit.size();
-  w.z.assign(nf, nullptr);
-  w.tf.assign(nf, nullptr);
-  w.fa.assign(nf, nullptr);
-  w.fdz.assign(nf, nullptr);
-  for (int l = 0; l < nf; ++l) {
-    w.z[l] = c.take<float>(NL * m->ldf[l]);
-    w.tf[l] = c.take<float>(NL * m->ldf[l]);
-    w.fa[l] = c.take<float>(NL * m->ldf[l]);
-    w.fdz[l] = c.take<float>(NL * m->ldf[l]);
-  }
-  w.dD = c.take<float>(NL * m->ldD);
   w.dGa = c.take<float>(P * m->ldM);
   w.dGb = c.take<float>(P * m->ldM);
   w.dY = c.take<float>(P * m->ldM);
@@ -414,44 +434,83 @@ size_t carve(dp_model *m, char *base, int nloc, int nall, int ncell, bool shared
   w.qside = c.take<float>(P * 4);
   w.du.assign(ne, nullptr);
   w.dh.assign(ne, nullptr);
-  for (int l = 0; l < ne; ++l) {
-    w.du[l] = c.take<float>(P * m->lde[l]);
-    w.dh[l] = c.take<float>(P * m->lde[l]);
-  }
+  if (!fused)
+    for (int l = 0; l < ne; ++l) {
+      w.du[l] = c.take<float>(P * m->lde[l]);
+      w.dh[l] = c.take<float>(P * m->lde[l]);
+    }
   return c.off + 256;
 }
 
+int free_arenas(dp_model *m) {
+  if (m->arena || m->parena) HIP_TRY(hipDeviceSynchronize());
+  if (m->arena) HIP_TRY(hipFree(m->arena));
+  if (m->parena) HIP_TRY(hipFree(m->parena));
+  m->arena = m->parena = nullptr;
+  m->arena_bytes = m->parena_bytes = 0;
+  m->cap_nloc = m->cap_nall = m->cap_ncell = -1;
+  m->cap_pairs = -1;
+  m->fwd.valid = false;
+  return DP_OK;
+}
+
 int ensure_workspace(dp_model *m, int nloc, int nall, int ncell) {
-  // the layout is fixed for the capacity until it grows or the budget changes
+  // the topology layout is fixed for the capacity until it grows or the
+  // budget changes; the pair arena is laid out by the forward, from the
+  // step's real pair count
   if (m->arena && nloc <= m->cap_nloc && nall <= m->cap_nall && ncell <= m->cap_ncell)
     return DP_OK;
   const int cl = std::max(nloc, m->cap_nloc), ca = std::max(nall, m->cap_nall),
             cc = std::max(ncell, m->cap_ncell);
-  // layout: every layer's attention activations stored, unless that exceeds
-  // the memory budget (then shared buffers and recomputation in the adjoint);
-  // the measuring passes write null pointers, so the table is restored after
-  const dp_model::WS saved = m->w;
-  const size_t full = carve(m, nullptr, cl, ca, cc, false);
-  const bool shared = m->n_attn > 1 && m->mem_budget > 0 && (double)full > m->mem_budget;
-  const size_t bytes = shared ? carve(m, nullptr, cl, ca, cc, true) : full;
-  m->w = saved;
+  int rc;
+  if ((rc = free_arenas(m))) return rc;
+  const size_t bytes = carve_topo(m, nullptr, cl, ca, cc);
   if (m->mem_budget > 0 && (double)bytes > m->mem_budget)
-    return fail(DP_ERR_OOM, "workspace of %zu bytes exceeds the memory budget of %.0f bytes%s",
-                bytes, m->mem_budget, m->n_attn > 1 ? " even with recomputation" : "");
-  if (m->arena) {
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(m->arena));
-    m->arena = nullptr;
-  }
+    return fail(DP_ERR_OOM, "workspace of %zu bytes exceeds the memory budget of %.0f bytes",
+                bytes, m->mem_budget);
   HIP_TRY(hipMalloc(&m->arena, bytes));
   HIP_TRY(hipMemset(m->arena, 0, bytes));
   m->arena_bytes = bytes;
-  carve(m, (char *)m->arena, cl, ca, cc, shared);
-  m->recompute = shared;
-  m->fwd.valid = false;
+  carve_topo(m, (char *)m->arena, cl, ca, cc);
   m->cap_nloc = cl;
   m->cap_nall = ca;
   m->cap_ncell = cc;
+  return DP_OK;
+}
+
+// Lays out the pair arena for at least `pairs` rows (synchronous; the caller
+// has synchronised the stream).  Every layer's attention activations are
+// stored unless that exceeds the memory budget (then shared buffers and
+// recomputation in the adjoint).
+int ensure_pairs(dp_model *m, long pairs) {
+  const long cap_max = (long)m->cap_nloc * m->sel;
+  long cap = pairs + pairs / 8;
+  cap = std::min(std::max(cap, pairs), cap_max);
+  const size_t P = (size_t)cap + 64;
+  const dp_model::WS saved = m->w;
+  const size_t full = carve_pairs(m, nullptr, P, false);
+  const bool shared = m->n_attn > 1 && m->mem_budget > 0 &&
+                      (double)(full + m->arena_bytes) > m->mem_budget;
+  const size_t bytes = shared ? carve_pairs(m, nullptr, P, true) : full;
+  m->w = saved;
+  if (m->mem_budget > 0 && (double)(bytes + m->arena_bytes) > m->mem_budget)
+    return fail(DP_ERR_OOM, "workspace of %zu bytes exceeds the memory budget of %.0f bytes%s",
+                bytes + m->arena_bytes, m->mem_budget,
+                m->n_attn > 1 ? " even with recomputation" : "");
+  if (m->parena) {
+    HIP_TRY(hipFree(m->parena));
+    m->parena = nullptr;
+    m->parena_bytes = 0;
+  }
+  HIP_TRY(hipMalloc(&m->parena, bytes));
+  HIP_TRY(hipMemset(m->parena, 0, bytes));
+  m->parena_bytes = bytes;
+  carve_pairs(m, (char *)m->parena, P, shared);
+  m->recompute = shared;
+  m->cap_pairs = cap;
+  m->cap_pairs_nloc = m->cap_nloc;
+  m->want_pairs = 0;
+  m->fwd.valid = false;
   return DP_OK;
 }
 
@@ -504,9 +563,22 @@ __global__ void k_init_flags(DevFlags *f, int *ccount) {
     f->overflow_atom = INT_MAX;
     f->overflow_count = 0;
     f->bad_type_atom = INT_MAX;
-    f->pad_ = 0;
+    f->pair_overflow = 0;
   }
   if (threadIdx.x < 4) ccount[threadIdx.x] = 0;
+}
+// Capacity check of the pair arena (one block): a step with more neighbour
+// pairs than the arena holds records its count and gets no pair work at all
+// (every neighbour count, locals and ghosts, and every pair offset set to 0),
+// so no kernel indexes past the arena; the workspace grows at the next call.
+__global__ __launch_bounds__(1024) void k_pair_guard(int *pair_off, int *nnei, int nloc, int nall,
+                                                     long cap, DevFlags *f) {
+  const int total = pair_off[nloc];
+  __syncthreads();  // every thread has read the total before any is cleared
+  if ((long)total <= cap) return;
+  if (threadIdx.x == 0) f->pair_overflow = total;
+  for (int k = threadIdx.x; k < nall; k += blockDim.x) nnei[k] = 0;
+  for (int k = threadIdx.x; k <= nloc; k += blockDim.x) pair_off[k] = 0;
 }
 __global__ void k_bbox(const double *x, int n, double *out) {
   __shared__ double red[6][256];
@@ -565,7 +637,6 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
                     double *d_atom_energy, hipStream_t s) {
   auto &w = m->w;
   const int sel = m->sel;
-  const int Pmax = nloc * sel;
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
 
@@ -584,6 +655,19 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   RUN("nlist", launch_nlist(d_coords, nloc, nall, grid, m->rcut, sel, w.atom_cell, w.cell_start,
                             w.cell_atoms, w.nlist, w.nnei, m->flags, s));
   RUN("pair_scan", launch_scan(w.nnei, nloc, w.pair_off, s));
+  if (m->cap_pairs < 0 || m->want_pairs > m->cap_pairs || m->cap_pairs_nloc != m->cap_nloc) {
+    // lay the pair arena out from this step's pair count (the only blocking
+    // point of a step, at the first step of a workspace and after growth)
+    int total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, w.pair_off + nloc, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int rc = ensure_pairs(m, std::max<long>(total, m->want_pairs));
+    if (rc) return rc;
+  } else {
+    RUN("pair_guard", hipLaunchKernelGGL(k_pair_guard, dim3(1), dim3(1024), 0, s, w.pair_off,
+                                         w.nnei, nloc, nall, m->cap_pairs, m->flags));
+  }
+  const int Pmax = (int)std::min<long>((long)nloc * sel, m->cap_pairs);
   if (na > 0) RUN("attn_classes", launch_attn_classes(w.nnei, nloc, w.ccount, w.clist, s));
   RUN("env_embed1",
       launch_env_embed1(d_coords, d_types, grid, nloc, sel, m->rcut, m->rcut_smth, w.nlist,
@@ -659,7 +743,7 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   const CellGrid &grid = fs.grid;
   const int nloc = fs.nloc, nall = fs.nall;
   const int sel = m->sel;
-  const int Pmax = nloc * sel;
+  const int Pmax = (int)std::min<long>((long)nloc * sel, m->cap_pairs);
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
   const int D = m->dattn, ldM = m->ldM;
@@ -695,7 +779,9 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   }
   // descriptor adjoint -> dG of the last layer, plus the next layer-norm / tanh seed
   float *dG_cur = w.dGa, *dG_nxt = w.dGb;
-  float *emb_du_top = w.du[ne - 1];
+  // (the fused embedding adjoint takes no seed buffer: the modes that would
+  // write one are not used then)
+  float *emb_du_top = emb_fused ? w.dY : w.du[ne - 1];
   {
     const int ln_mode = na > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = na > 0 ? m->attn[na - 1].gamma : nullptr;
@@ -783,6 +869,13 @@ int enqueue_step(dp_model *m, const double *d_coords, const int32_t *d_types, co
 
 int check_flags(dp_model *m) {
   const DevFlags &f = *m->flags_host;
+  if (f.pair_overflow > 0) {
+    m->want_pairs = f.pair_overflow;
+    return fail(DP_ERR_CAPACITY,
+                "the step had %d neighbour pairs, more than the %ld the workspace holds; its "
+                "outputs are not valid and the workspace grows at the next call",
+                f.pair_overflow, m->cap_pairs);
+  }
   if (f.bad_type_atom != INT_MAX)
     return fail(DP_ERR_TYPE, "atom %d has a type outside [0, %d)", f.bad_type_atom, m->ntypes);
   if (f.overflow_atom != INT_MAX)
@@ -919,6 +1012,14 @@ int dp_compute(dp_model *m, const double *coords, const int32_t *types, const do
   if ((rc = enqueue_step(m, w.coords, w.types, grid, nloc, nall, w.out_e, w.out_f, w.out_v,
                          w.out_ae, s)))
     return rc;
+  // a step that outgrew the pair arena is run again on the grown arena
+  HIP_TRY(hipStreamSynchronize(s));
+  if (m->flags_host->pair_overflow > 0) {
+    m->want_pairs = m->flags_host->pair_overflow;
+    if ((rc = enqueue_step(m, w.coords, w.types, grid, nloc, nall, w.out_e, w.out_f, w.out_v,
+                           w.out_ae, s)))
+      return rc;
+  }
   std::vector<double> F(3 * (size_t)nall), AE(nloc);
   double E = 0, V[9];
   HIP_TRY(hipMemcpyAsync(&E, w.out_e, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1052,21 +1153,17 @@ int dp_set_memory_budget(dp_model *m, double bytes) {
   if (m->last) (void)hipStreamSynchronize(m->last);
   m->mem_budget = bytes;
   // the layout is chosen again at the next step
-  if (m->arena) {
+  if (m->arena || m->parena) {
     int rc = set_device(m);
     if (rc) return rc;
-    HIP_TRY(hipFree(m->arena));
-    m->arena = nullptr;
-    m->arena_bytes = 0;
-    m->cap_nloc = m->cap_nall = m->cap_ncell = -1;
-    m->fwd.valid = false;
+    if ((rc = free_arenas(m))) return rc;
   }
   return DP_OK;
 }
 
 int dp_memory_info(const dp_model *m, int64_t *workspace_bytes, int32_t *recompute) {
   if (!m || !workspace_bytes || !recompute) return fail(DP_ERR_ARG, "NULL argument");
-  *workspace_bytes = (int64_t)m->arena_bytes;
+  *workspace_bytes = (int64_t)(m->arena_bytes + m->parena_bytes);
   *recompute = m->recompute ? 1 : 0;
   return DP_OK;
 }

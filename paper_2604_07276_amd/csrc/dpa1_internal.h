@@ -45,7 +45,7 @@ struct DevFlags {
   int overflow_atom;   // smallest atom index with more than sel neighbours, INT_MAX if none
   int overflow_count;  // its neighbour count
   int bad_type_atom;   // smallest atom index with an invalid type, INT_MAX if none
-  int pad_;
+  int pair_overflow;   // the step's pair count when it exceeds the pair arena, else 0
 };
 
 // ---------------------------------------------------------------------------

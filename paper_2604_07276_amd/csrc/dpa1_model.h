@@ -110,9 +110,14 @@ struct dp_model {
   float *ebias = nullptr;       // [ntypes]
   std::vector<void *> weight_allocs;
   // workspace
-  void *arena = nullptr;
+  void *arena = nullptr;   // topology: per-atom and per-centre buffers
   size_t arena_bytes = 0;
   int cap_nloc = -1, cap_nall = -1, cap_ncell = -1;
+  void *parena = nullptr;  // per-pair buffers
+  size_t parena_bytes = 0;
+  long cap_pairs = -1;     // pair rows parena holds (plus 64 of slack), -1 if not laid out
+  int cap_pairs_nloc = -1; // topology capacity the pair arena was laid out with
+  long want_pairs = 0;     // pair count of a step that outgrew the arena
   double mem_budget = 0;   // workspace budget in bytes (0: unlimited)
   bool recompute = false;  // attention activations shared across layers, recomputed
   int shared_layer = -1;   // layer whose activations the shared buffers hold
@@ -148,6 +153,7 @@ struct dp_model {
 
   ~dp_model() {
     if (arena) (void)hipFree(arena);
+    if (parena) (void)hipFree(parena);
     for (void *p : weight_allocs) (void)hipFree(p);
     if (flags) (void)hipFree(flags);
     if (bbox) (void)hipFree(bbox);

@@ -215,7 +215,14 @@ int batch_gradient(dp_trainer *t, const double *d_frames, const int32_t *d_types
     if ((rc = dp_compute_device(m, xf, d_types, box, N, 0, t->Est + f, t->Fst, t->vir, nullptr,
                                 s)))
       return rc;
-    if ((rc = dp_sync(m))) return rc;
+    rc = dp_sync(m);
+    if (rc == DP_ERR_CAPACITY) {  // the frame outgrew the pair arena: again on the grown one
+      if ((rc = dp_compute_device(m, xf, d_types, box, N, 0, t->Est + f, t->Fst, t->vir,
+                                  nullptr, s)))
+        return rc;
+      rc = dp_sync(m);
+    }
+    if (rc) return rc;
     auto &w = m->w;
     launch_tr_seed(t->Fst, d_f_label + (size_t)3 * N * f, N, cf, t->delta,
                    t->sq_part + (size_t)nsq * f, s);

@@ -283,3 +283,30 @@ def test_replica_62672(model, protein, oracle_frame0, replica_oracle, precision)
         assert np.linalg.norm(dF_all, axis=1).max() <= BF_F_MAX
         assert de_s.mean() <= BF_E_TOL and rmse_s <= 2 * BF_F_RMSE
         assert np.linalg.norm(dF_s, axis=1).max() <= BF_F_MAX
+
+
+def test_replica_62672_memory_budget(weights_path, replica_oracle):
+    """The 62,672-atom replica under a memory budget below its full workspace:
+    attention activations shared across layers and recomputed in the adjoint,
+    results bit-identical to the unbudgeted step and within the FP32 bars of
+    the oracle sample."""
+    from paper_2604_07276_amd import binding
+    big, pr_e, sub, Fsub = replica_oracle
+    nb = len(big.coords)
+    say(f"case: 2x2x1 replica N={nb}, FP32, memory budget")
+    m = binding.Model(weights_path, RC, SEL)
+    try:
+        E1, F1, V1, ae1 = m.compute(big.coords, big.types, big.box, nb, 0, atom_energy=True)
+        full, rec = m.memory_info()
+        m.set_memory_budget(full - 1)
+        E2, F2, V2, ae2 = m.compute(big.coords, big.types, big.box, nb, 0, atom_energy=True)
+        small, rec2 = m.memory_info()
+    finally:
+        m.close()
+    say(f"[replica budget] workspace {full / 2**30:.2f} GiB (recompute={rec}) -> "
+        f"{small / 2**30:.2f} GiB (recompute={rec2})")
+    assert not rec and rec2 and small < full
+    assert E1 == E2 and np.array_equal(F1, F2) and np.array_equal(V1, V2)
+    assert np.array_equal(ae1, ae2)
+    assert np.abs(ae2[pr_e.centers] - pr_e.atom_energy).max() <= EI_TOL
+    assert np.abs(F2[sub] - Fsub).max() <= F_TOL

@@ -56,3 +56,46 @@ def test_recompute_under_budget_is_bit_identical(weights_path, precision):
     E3, F3, _, _ = m.compute(s.coords, s.types, s.box, n, 0)
     assert not m.memory_info()[1] and np.array_equal(F3, F1)
     m.close()
+
+
+def test_pair_capacity_grows_with_the_pair_count(weights_path):
+    """The per-pair workspace is laid out from the real pair count of the
+    first step (plus 1/8).  A later, denser step on the same handle: the host
+    entry point reruns it on a grown workspace, the device entry point reports
+    DP_ERR_CAPACITY at dp_sync and succeeds at the next call; both then equal
+    a fresh handle's result bit for bit."""
+    torch = _torch()
+    from paper_2604_07276_amd import binding
+    c = synth.open_cluster(150, 9.0, 5, seed=9)
+    x0, t = c.coords, c.types
+    x1 = 0.8 * x0  # about twice the neighbour pairs
+    n = len(x0)
+    print("case: pair capacity, open cluster of 150 atoms then the same cluster x0.8", flush=True)
+    fresh = binding.Model(weights_path, 6.0, 120)
+    ref = fresh.compute(x1, t, None, n, 0, atom_energy=True)
+    fresh.close()
+    m = binding.Model(weights_path, 6.0, 120)
+    m.compute(x0, t, None, n, 0)
+    b0, _ = m.memory_info()
+    got = m.compute(x1, t, None, n, 0, atom_energy=True)
+    b1, _ = m.memory_info()
+    assert b1 > b0
+    assert got[0] == ref[0] and all(np.array_equal(a, b) for a, b in zip(got[1:], ref[1:]))
+    m.close()
+    dev = torch.device("cuda:0")
+    d = binding.Model(weights_path, 6.0, 120)
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    f = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    v = torch.zeros(9, dtype=torch.float64, device=dev)
+    tt = torch.tensor(t, device=dev)
+    d.compute_device(torch.tensor(x0, device=dev), tt, None, n, 0, e, f, v)
+    d.sync()
+    xd = torch.tensor(x1, device=dev)
+    d.compute_device(xd, tt, None, n, 0, e, f, v)
+    with pytest.raises(binding.DPError) as ei:
+        d.sync()
+    assert ei.value.code == -8
+    d.compute_device(xd, tt, None, n, 0, e, f, v)
+    d.sync()
+    assert float(e.cpu()[0]) == ref[0] and np.array_equal(f.cpu().numpy(), ref[1])
+    d.close()
