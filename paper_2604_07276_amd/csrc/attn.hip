@@ -848,18 +848,29 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
   }
 }
 
-// Class lists: centre i with n = nnei[i] > 0 goes to class (n - 1) / 32.
-// Positions are taken with one atomic per wavefront and class, so the order
-// inside a list varies from run to run; every centre is computed on its own,
-// so results do not depend on it.
-__global__ void k_attn_classes(const int *__restrict__ nnei, int nloc, int *__restrict__ ccount,
-                               int *__restrict__ clist) {
+// Class lists: centre i with n = nnei[i] > 0 belongs to class (n - 1) / 32
+// (counted in ccount[4 + class]) and is listed in the smallest class of the
+// active set (bit c of `active`) that holds n neighbours; the host keeps the
+// top class active, so every centre is listed.  A class that is not active
+// is not launched: the host deactivates classes that were empty in an
+// earlier step, and a centre that falls into one after all is computed by
+// the next larger active class (more padding, the same result).  Positions
+// are taken with one atomic per wavefront and class, so the order inside a
+// list varies from run to run; every centre is computed on its own, so
+// results do not depend on it.
+__global__ void k_attn_classes(const int *__restrict__ nnei, int nloc, int active,
+                               int *__restrict__ ccount, int *__restrict__ clist) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int n = i < nloc ? nnei[i] : 0;
-  const int cls = n > 0 ? (n - 1) >> 5 : -1;
+  const int nat = n > 0 ? (n - 1) >> 5 : -1;
+  int cls = nat;
+  if (cls >= 0)
+    while (cls < 3 && !((active >> cls) & 1)) ++cls;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
+    const unsigned long long bn = __ballot(nat == c);
+    if (bn != 0ull && lane == __ffsll((long long)bn) - 1) atomicAdd(&ccount[4 + c], __popcll(bn));
     const unsigned long long b = __ballot(cls == c);
     if (b == 0ull) continue;
     const int leader = __ffsll((long long)b) - 1;
@@ -1145,10 +1156,11 @@ hipError_t attn_prepare() {
   return e;
 }
 
-void launch_attn_classes(const int *nnei, int nloc, int *ccount, int *clist, hipStream_t s) {
+void launch_attn_classes(const int *nnei, int nloc, int active, int *ccount, int *clist,
+                         hipStream_t s) {
   if (nloc <= 0) return;
   hipLaunchKernelGGL(k_attn_classes, dim3((nloc + 255) / 256), dim3(256), 0, s, nnei, nloc,
-                     ccount, clist);
+                     active, ccount, clist);
 }
 
 // class (compile-time NP) and precision (compile-time BFV) dispatch

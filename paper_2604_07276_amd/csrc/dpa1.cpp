@@ -360,7 +360,7 @@ size_t carve_topo(dp_model *m, char *base, int nloc, int nall, int ncell) {
   w.nlist = c.take<int>((size_t)nall * m->sel);
   w.nnei = c.take<int>(nall);
   w.pair_off = c.take<int>(nloc + 1);
-  w.ccount = c.take<int>(4);
+  w.ccount = c.take<int>(8);
   w.clist = c.take<int>(4 * (size_t)nloc);
   w.T = c.take<float>(NL * 4 * m->M);
   w.dmat = c.take<float>(NL * m->ldD);
@@ -565,7 +565,7 @@ __global__ void k_init_flags(DevFlags *f, int *ccount) {
     f->bad_type_atom = INT_MAX;
     f->pair_overflow = 0;
   }
-  if (threadIdx.x < 4) ccount[threadIdx.x] = 0;
+  if (threadIdx.x < 8) ccount[threadIdx.x] = 0;
 }
 // Capacity check of the pair arena (one block): a step with more neighbour
 // pairs than the arena holds records its count and gets no pair work at all
@@ -668,7 +668,19 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
                                          w.nnei, nloc, nall, m->cap_pairs, m->flags));
   }
   const int Pmax = (int)std::min<long>((long)nloc * sel, m->cap_pairs);
-  if (na > 0) RUN("attn_classes", launch_attn_classes(w.nnei, nloc, w.ccount, w.clist, s));
+  // attention classes to launch: those that held centres in a recent step
+  // (the host copy of the counts lags the device by a step or more; a stale
+  // choice costs padding, never correctness), always the top one
+  const int ncls = attn_class_count(sel);
+  int active = (1 << ncls) - 1;
+  if (m->ccount_host[4] >= 0) {
+    active = 1 << (ncls - 1);
+    for (int c = 0; c < ncls - 1; ++c)
+      if (m->ccount_host[4 + c] > 0) active |= 1 << c;
+  }
+  m->cls_active = active;
+  if (na > 0)
+    RUN("attn_classes", launch_attn_classes(w.nnei, nloc, active, w.ccount, w.clist, s));
   RUN("env_embed1",
       launch_env_embed1(d_coords, d_types, grid, nloc, sel, m->rcut, m->rcut_smth, w.nlist,
                         w.nnei, w.pair_off, m->type_table, m->ws, m->ntypes, m->emb[0],
@@ -697,9 +709,10 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
     // in BF16 mode QKV, o, dO and dQKV are stored in BF16 (matrix-core operands only)
     GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16, 0, m->M};
     RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
-    for (int cls = 0; cls < attn_class_count(sel); ++cls)
-      RUN(kAttnFwdName[cls],
-          launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
+    for (int cls = 0; cls < ncls; ++cls)
+      if ((active >> cls) & 1)
+        RUN(kAttnFwdName[cls],
+            launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
     GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
     RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
                                     w.G[a + 1], w.xhat[a], w.rstd[a], s));
@@ -725,6 +738,8 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
     RUN("reduce", launch_reduce(w.e, w.vir_part, nloc, d_energy, nullptr, d_atom_energy, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(m->flags_host, m->flags, sizeof(DevFlags), hipMemcpyDeviceToHost, s));
+  if (na > 0 && nloc > 0)
+    HIP_TRY(hipMemcpyAsync(m->ccount_host, w.ccount, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
   m->last = s;
   m->have_step = true;
   m->last_nloc = nloc;
@@ -808,8 +823,9 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       GemmArgs r1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16, 0, m->M};
       RUN("qkv_fwd_recompute", gemm_linear(r1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
       for (int cls = 0; cls < attn_class_count(sel); ++cls)
-        RUN("attn_fwd_recompute",
-            launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
+        if ((m->cls_active >> cls) & 1)
+          RUN("attn_fwd_recompute",
+              launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
       GemmArgs r2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
       RUN("oproj_ln_recompute", gemm_ln_res(r2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a],
                                             ldM, w.G[a + 1], w.xhat[a], w.rstd[a], s));
@@ -818,11 +834,13 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16, 0, m->M};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
-      RUN(kAttnBwdQName[cls],
+      if ((m->cls_active >> cls) & 1)
+        RUN(kAttnBwdQName[cls],
           launch_attn_bwd_q_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a], w.dqkv,
                                   w.astat, w.qside, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
-      RUN(kAttnBwdKName[cls],
+      if ((m->cls_active >> cls) & 1)
+        RUN(kAttnBwdKName[cls],
           launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dqkv, w.astat, w.qside,
                                   w.gw, w.gr, a != na - 1, s));
     GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
@@ -943,6 +961,8 @@ int dp_create(const char *weights_path, double rcut, int sel, dp_model **out) {
     hipError_t e = hipMalloc(&m->flags, sizeof(DevFlags));
     if (e == hipSuccess) e = hipMalloc(&m->bbox, 6 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc(&m->flags_host, sizeof(DevFlags));
+    if (e == hipSuccess) e = hipHostMalloc(&m->ccount_host, 8 * sizeof(int));
+    if (e == hipSuccess) m->ccount_host[4] = -1;  // no counts yet: every class active
     if (e == hipSuccess) e = hipStreamCreate(&m->own);
     if (e == hipSuccess) e = attn_prepare();
     if (e != hipSuccess) rc = fail(DP_ERR_DEVICE, "device setup failed: %s", hipGetErrorString(e));

@@ -153,7 +153,11 @@ constexpr int kAttnLamLd = 128;
 hipError_t attn_prepare();
 // Class lists from the neighbour counts: ccount [4] (zeroed beforehand),
 // clist [4][nloc].
-void launch_attn_classes(const int *nnei, int nloc, int *ccount, int *clist, hipStream_t s);
+// ccount [8]: centres listed per class [0..3], centres per neighbour-count
+// class [4..7]; active: bit set of the classes that are launched (the top
+// class of sel always among them).
+void launch_attn_classes(const int *nnei, int nloc, int active, int *ccount, int *clist,
+                         hipStream_t s);
 struct AttnArgs {
   const float *geom;
   const int *pair_off, *nnei, *clist, *ccount;

@@ -129,7 +129,7 @@ struct dp_model {
     std::vector<float *> h, te;        // embedding outputs / tanh parts
     std::vector<float *> qkv, o, xhat, rstd, G;  // per attention layer (G[a] input of layer a)
     std::vector<float *> lam, fstat;   // per attention layer: scaled logits, (m, 1/Z)
-    int *ccount, *clist;               // attention class counts [4] and lists [4][nloc]
+    int *ccount, *clist;               // attention class counts [8] and lists [4][nloc]
     float *T, *dmat, *e;
     std::vector<float *> z, tf;        // fitting outputs / tanh parts
     std::vector<float *> fa, fdz;      // fitting backward a_l and dz_l
@@ -138,6 +138,8 @@ struct dp_model {
   } w;
   dpa1::DevFlags *flags = nullptr;       // device
   dpa1::DevFlags *flags_host = nullptr;  // pinned
+  int *ccount_host = nullptr;            // pinned [8]: class counts of a recent step
+  int cls_active = 0;                    // attention classes launched by the last forward
   double *bbox = nullptr;          // device [6]: bounding box for open boundaries
   hipStream_t own = nullptr;
   hipStream_t last = nullptr;
@@ -158,6 +160,7 @@ struct dp_model {
     if (flags) (void)hipFree(flags);
     if (bbox) (void)hipFree(bbox);
     if (flags_host) (void)hipHostFree(flags_host);
+    if (ccount_host) (void)hipHostFree(ccount_host);
     if (own) (void)hipStreamDestroy(own);
   }
 };
