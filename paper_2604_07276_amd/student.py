@@ -12,9 +12,13 @@ frames with the teacher as its periodic judge and fallback:
 3. training: the library's trainer (exact energy+force loss gradient, Adam on
    FP32 masters, BF16 matrix-core operands by default), batches of 8 frames;
 4. serving: the student evaluates each held-out frame as one MD step; every
-   ``audit_every``-th step the teacher evaluates it too and the force RMSE
-   between the two is checked; above ``threshold`` the teacher takes over for
-   every later step.
+   ``audit_every``-th step the teacher evaluates it too and the student's
+   force error is checked against three bounds: the RMSE against an absolute
+   threshold (3e-2 eV/A), the RMSE relative to the teacher's own force RMS on
+   that frame (0.5: the student must explain at least 3/4 of the force
+   variance; an absolute bound alone passes a student that returns F = 0 when
+   the teacher's forces are small) and the largest component error (1 eV/A).
+   Past any of them the teacher takes over for every later step.
 
 Run: ``python -m paper_2604_07276_amd.student [--steps K] ...``; prints one
 JSON object.  Needs the built library and a GPU.
@@ -43,20 +47,26 @@ class AuditedPotential:
     """Serves steps with the student and lets the teacher audit every k-th step.
 
     ``student`` and ``teacher`` are callables coords -> (E, F) on device
-    tensors; ``error_fn(F_a, F_b) -> (rmse, max)``.  Once an audit finds the
-    force RMSE above ``threshold`` every later step is served by the teacher.
+    tensors (or host arrays); ``error_fn(F_a, F_b) -> (rmse, max)``.  An audit
+    fails when the force RMSE exceeds ``threshold`` (eV/A), or exceeds
+    ``rel_threshold`` times the teacher's force RMS on the audited step, or
+    when the largest component error exceeds ``max_threshold`` (eV/A); once
+    one fails, every later step is served by the teacher.
     """
 
-    def __init__(self, student, teacher, threshold: float, every: int = 10, error_fn=None):
+    def __init__(self, student, teacher, threshold: float, every: int = 10, error_fn=None,
+                 rel_threshold: float = float("inf"), max_threshold: float = float("inf")):
         if every < 1:
             raise ValueError("audit interval must be >= 1")
         self.student, self.teacher = student, teacher
         self.threshold = float(threshold)
+        self.rel_threshold = float(rel_threshold)
+        self.max_threshold = float(max_threshold)
         self.every = int(every)
         self.error_fn = error_fn or binding.force_error
         self.step_count = 0
         self.fallback = False
-        self.audits = []  # (step, rmse, max)
+        self.audits = []  # (step, rmse, max, teacher force rms)
 
     def __call__(self, coords):
         k = self.step_count
@@ -67,8 +77,11 @@ class AuditedPotential:
         if k % self.every == 0:
             Et, Ft = self.teacher(coords)
             rmse, mx = self.error_fn(F, Ft)
-            self.audits.append((k, rmse, mx))
-            if not rmse <= self.threshold:
+            scale = self.error_fn(Ft, 0 * Ft)[0]
+            self.audits.append((k, rmse, mx, scale))
+            ok = rmse <= self.threshold and rmse <= self.rel_threshold * scale and \
+                mx <= self.max_threshold
+            if not ok:
                 self.fallback = True
                 return Et, Ft, "teacher"
         return E, F, "student"
@@ -120,10 +133,12 @@ def time_steps(model, frames, types, box, reps: int, torch):
 
 def run(n_train=2000, n_eval=200, steps=2000, lr0=1e-3, lr1=1e-5, pref_e=1.0, pref_f=100.0,
         precision="bf16", threshold=3e-2, audit_every=10, seed=0, out_weights=None, log=None,
-        target="dpa1"):
+        target="dpa1", rel_threshold=0.5, max_threshold=1.0):
     """The pipeline above.  ``target`` "dpa1" labels with the DPA-1 teacher;
-    "student" labels with the student architecture under other weights (a
-    target the student can represent exactly: a check of the training)."""
+    "dpa1_noattn" with the same teacher widths without the attention layers
+    (the DP-SE descriptor the student shares); "student" with the student
+    architecture under other weights (a target the student can represent
+    exactly: a check of the training)."""
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("the student pipeline needs a GPU")
@@ -134,6 +149,8 @@ def run(n_train=2000, n_eval=200, steps=2000, lr0=1e-3, lr1=1e-5, pref_e=1.0, pr
     s_path = os.path.join(tmp, "student_seed1.bin")
     if target == "dpa1":
         synth.make_weights(t_path, seed=0)
+    elif target == "dpa1_noattn":
+        synth.make_weights(t_path, seed=0, shape=synth.ModelShape(n_attn=0))
     elif target == "student":
         synth.make_weights(t_path, seed=7, shape=synth.STUDENT_SHAPE)
     else:
@@ -197,13 +214,33 @@ def run(n_train=2000, n_eval=200, steps=2000, lr0=1e-3, lr1=1e-5, pref_e=1.0, pr
     te_eval = _evaluator(teacher, types, box, n, torch)
     ev = frames[n_train:]
     rm, mx, de = [], [], []
+    # the error split by the teacher's force size: the bulk of the atoms and
+    # the 1% with the largest teacher forces
+    f_mag = torch.linalg.norm(F_lab[:n_train], dim=2)
+    cut = float(torch.quantile(f_mag[: min(n_train, 50)].flatten().float(), 0.99))
+    bulk_sq = tail_sq = bulk_ref = tail_ref = 0.0
     for k in range(n_eval):
         E, F = st_eval(ev[k])
-        r, m = binding.force_error(F, F_lab[n_train + k])
+        Ft = F_lab[n_train + k]
+        r, m = binding.force_error(F, Ft)
         rm.append(r)
         mx.append(m)
         de.append(abs(float(E[0]) - float(E_lab[n_train + k])) / n)
-    pot = AuditedPotential(lambda x: st_eval(x), lambda x: te_eval(x), threshold, audit_every)
+        big = torch.linalg.norm(Ft, dim=1) > cut
+        d2 = ((F - Ft) ** 2).sum(1)
+        t2 = (Ft ** 2).sum(1)
+        tail_sq += float(d2[big].sum())
+        tail_ref += float(t2[big].sum())
+        bulk_sq += float(d2[~big].sum())
+        bulk_ref += float(t2[~big].sum())
+    # training-set error on up to 50 training frames (under- versus over-fitting)
+    tr_sq = tr_ref = 0.0
+    for k in range(min(n_train, 50)):
+        E, F = st_eval(frames[k])
+        tr_sq += float(((F - F_lab[k]) ** 2).sum())
+        tr_ref += float((F_lab[k] ** 2).sum())
+    pot = AuditedPotential(lambda x: st_eval(x), lambda x: te_eval(x), threshold, audit_every,
+                           rel_threshold=rel_threshold, max_threshold=max_threshold)
     sources = [pot(ev[k])[2] for k in range(n_eval)]
     ms_student = time_steps(student, ev, types, box, 50, torch)
     ms_teacher = time_steps(teacher, ev, types, box, 20, torch)
@@ -223,9 +260,17 @@ def run(n_train=2000, n_eval=200, steps=2000, lr0=1e-3, lr1=1e-5, pref_e=1.0, pr
         "held_out": {"force_rmse_eV_per_A": rmse, "force_max_abs_err_eV_per_A": float(max(mx)),
                      "teacher_force_rms_eV_per_A": f_rms,
                      "relative_force_rmse": rmse / f_rms,
+                     "relative_force_rmse_bulk": math.sqrt(bulk_sq / max(bulk_ref, 1e-300)),
+                     "relative_force_rmse_top1pct": math.sqrt(tail_sq / max(tail_ref, 1e-300)),
+                     "top1pct_share_of_teacher_force_sq": tail_ref / max(tail_ref + bulk_ref,
+                                                                         1e-300),
                      "energy_mae_eV_per_atom": float(np.mean(de))},
+        "train_set": {"frames": min(n_train, 50),
+                      "relative_force_rmse": math.sqrt(tr_sq / max(tr_ref, 1e-300))},
         "serving": {"audit_every": audit_every, "threshold_eV_per_A": threshold,
-                    "audits": [[k, round(r, 6), round(m, 6)] for k, r, m in pot.audits],
+                    "rel_threshold": rel_threshold, "max_threshold_eV_per_A": max_threshold,
+                    "audits": [[k, round(r, 6), round(m, 6), round(sc, 6)]
+                               for k, r, m, sc in pot.audits],
                     "fallback": pot.fallback,
                     "student_steps": sources.count("student"),
                     "teacher_steps": sources.count("teacher")},
@@ -249,14 +294,18 @@ def main(argv=None):
     ap.add_argument("--pref-f", type=float, default=100.0)
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="bf16")
     ap.add_argument("--threshold", type=float, default=3e-2)
+    ap.add_argument("--rel-threshold", type=float, default=0.5)
+    ap.add_argument("--max-threshold", type=float, default=1.0)
     ap.add_argument("--save", default=None, help="write the trained student weights here")
-    ap.add_argument("--target", choices=("dpa1", "student"), default="dpa1",
-                    help="label with the DPA-1 teacher, or with the student architecture "
-                         "under other weights (a representable target)")
+    ap.add_argument("--target", choices=("dpa1", "dpa1_noattn", "student"), default="dpa1",
+                    help="label with the DPA-1 teacher, with its widths without attention, or "
+                         "with the student architecture under other weights (a representable "
+                         "target)")
     args = ap.parse_args(argv)
     out = run(args.train_frames, args.eval_frames, args.steps, args.lr0, args.lr1, args.pref_e,
               args.pref_f, args.precision, args.threshold, out_weights=args.save, log=sys.stderr,
-              target=args.target)
+              target=args.target, rel_threshold=args.rel_threshold,
+              max_threshold=args.max_threshold)
     out["target"] = args.target
     print(json.dumps(out), flush=True)
     return 0

@@ -72,3 +72,43 @@ def test_pipeline_small_run():
     assert np.isfinite(out["held_out"]["force_rmse_eV_per_A"])
     assert out["serving"]["student_steps"] + out["serving"]["teacher_steps"] == 4
     assert out["throughput"]["speedup_vs_teacher"] > 1.0
+
+
+def test_relative_criterion_catches_a_zero_force_student():
+    """A student that returns F = 0 has an absolute force RMSE equal to the
+    teacher's force RMS; with small teacher forces that passes the absolute
+    3e-2 eV/A bound, and the relative bound must catch it at the first audit."""
+    rng = np.random.default_rng(0)
+    Ft = rng.normal(0.0, 0.02, size=(64, 3))
+
+    def teacher(x):
+        return 1.0, Ft
+
+    def student(x):
+        return 1.0, np.zeros_like(Ft)
+
+    absolute_only = AuditedPotential(student, teacher, threshold=3e-2, every=5, error_fn=_rmse)
+    assert [absolute_only(k)[2] for k in range(10)] == ["student"] * 10
+    pot = AuditedPotential(student, teacher, threshold=3e-2, every=5, error_fn=_rmse,
+                           rel_threshold=0.5)
+    src = [pot(k)[2] for k in range(10)]
+    assert src == ["teacher"] * 10 and pot.fallback
+    k, rmse, mx, scale = pot.audits[0]
+    assert k == 0 and abs(rmse - scale) < 1e-15 and rmse < 3e-2
+
+
+def test_max_error_bound_catches_a_single_bad_atom():
+    Ft = np.full((64, 3), 0.01)
+
+    def teacher(x):
+        return 1.0, Ft
+
+    def student(x):
+        F = Ft.copy()
+        F[7, 2] += 2.0  # one component off by 2 eV/A: RMSE 0.14, within the absolute
+        # and relative bounds set below; only the max-error bound fails
+        return 1.0, F
+
+    pot = AuditedPotential(student, teacher, threshold=1.0, every=1, error_fn=_rmse,
+                           rel_threshold=100.0, max_threshold=1.0)
+    assert pot(0)[2] == "teacher" and pot.fallback
