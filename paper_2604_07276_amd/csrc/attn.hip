@@ -553,10 +553,13 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
 //   Y = dH w_q w_k           -> drhat_q += sum_k Y rhat_k, drhat_k += sum_q Y rhat_q
 // Two kernels per class, both reading lam and (m, 1/Z) stored by the forward.
 // k_attn_bwd_q (wave = query tile): dA^T from V staged row-major, then dS,
-// dQ (K^T staged) and the query-side sums; it writes (m, 1/Z, D_q) and the
-// query-side sums per pair.  k_attn_bwd_k (wave = key tile): dA key-major
-// and dV from dO staged row-major, then dK (Q^T staged) and the key-side
-// sums; it adds both sides into dE/dsw and dE/drhat.
+// dQ (K^T staged) and the query-side sums; it writes dA in the layout of lam
+// (row = query, n columns), (m, 1/Z, D_q) and the query-side sums per pair.
+// k_attn_bwd_k (wave = key tile): reads dA key-major the way it reads lam
+// (one column of the centre's rows per lane) instead of forming it a second
+// time with a matrix product, forms dV from dO staged row-major, then dK
+// (Q^T staged) and the key-side sums; it adds both sides into dE/dsw and
+// dE/drhat.
 
 template <int NPAD, bool BF>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd_q(
@@ -564,7 +567,8 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     const float *__restrict__ geom, const int *__restrict__ pair_off,
     const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
     int sel, float shift, const float *__restrict__ lam, const float2 *__restrict__ fstat,
-    float *__restrict__ dqkv, float4 *__restrict__ astat, float4 *__restrict__ qside) {
+    float *__restrict__ dqkv, float4 *__restrict__ astat, float4 *__restrict__ qside,
+    float *__restrict__ dA) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;                     // [NPAD] rhat, sw
@@ -606,7 +610,14 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 96 ? 3 : 2) void k_attn_bwd
     stage_t_load<NPAD, BF>(qkv, 128, ld, base, n, tid, kpre);
 
     floatx4 da[NT];
-    if (wave < ntile) qk_lds<NT, BF>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
+    if (wave < ntile) {
+      qk_lds<NT, BF>(buf, r, g, dov, da);  // dA^T tiles: lane (query r, keys 4g + v)
+      if (qok) {  // dA row of this query, for the key-tile kernel
+        float *dp = dA + (size_t)(base + q) * kLamLd + 4 * g;
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) *(floatx4 *)(dp + 16 * kt) = da[kt];
+      }
+    }
     __syncthreads();
     stage_t_store<NPAD>(buf, tid, n, kpre);  // K^T
     __syncthreads();
@@ -680,9 +691,10 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     const float *__restrict__ qkv, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
     const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
-    float shift, const float *__restrict__ lam, float *__restrict__ dqkv,
-    const float4 *__restrict__ astat, const float4 *__restrict__ qsbuf,
-    float *__restrict__ gw, float *__restrict__ gr, int accumulate) {
+    float shift, const float *__restrict__ lam, const float *__restrict__ dA,
+    float *__restrict__ dqkv, const float4 *__restrict__ astat,
+    const float4 *__restrict__ qsbuf, float *__restrict__ gw, float *__restrict__ gr,
+    int accumulate) {
   constexpr int NT = NPAD / 16;
   extern __shared__ float4 smem[];
   float4 *kg = smem;                     // [NPAD] rhat, sw
@@ -708,8 +720,6 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     float gl;
     const float4 gv = gate_load(geom, base, n, tid, gl);
     const float4 av = astat[base + (tid < n ? tid : 0)];
-    floatx4 vreg[8];
-    load_rows<BF>(qkv, 256, ld, base, n, wave * 16 + r, g, vreg);
     const int ntile = (n + 15) >> 4;
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
@@ -720,27 +730,28 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
     float4 qpre[8];
     if constexpr (PREF) stage_t_load<NPAD, BF>(qkv, 0, ld, base, n, tid, qpre);  // Q rows of phase 2
 
-    // ---------------- phase 1: dA key-major, dV, dS and the key-side sums
+    // ---------------- phase 1: dV, dS and the key-side sums
     floatx4 ds[NT];
     float dwk = 0.f, drkx = 0.f, drky = 0.f, drkz = 0.f;
     if (wave < ntile) {
       const float4 gk = kg[kk];
       const float wk = kok ? gk.w : 0.f;
       const double wkd = kok ? kw[kk] : 0.0;
-      // lam of this key against the queries of one tile (lane: key r,
+      // lam and dA of this key against the queries of one tile (lane: key r,
       // queries 4g + v), read one query tile ahead
-      const float *lc = lam + (size_t)base * kLamLd + kk;
-      auto lam_tile = [&](int qt, float (&lv)[4]) {
+      const size_t col = (size_t)base * kLamLd + (kok ? kk : 0);
+      const float *lc = lam + col, *dc = dA + col;
+      auto lam_tile = [&](int qt, float (&lv)[4], float (&dv)[4]) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int qq = qt * 16 + 4 * g + v;
-          lv[v] = lc[(qq < n ? qq : 0) * kLamLd];
+          const size_t off = (size_t)(qq < n ? qq : 0) * kLamLd;
+          lv[v] = lc[off];
+          dv[v] = dc[off];
         }
       };
-      float lcur[4], lnxt[4];
-      lam_tile(0, lcur);
-      floatx4 dk[NT];
-      qk_lds<NT, BF>(buf, r, g, vreg, dk);  // dA: lane (key r, queries 4g + v)
+      float lcur[4], lnxt[4], dcur[4], dnxt[4];
+      lam_tile(0, lcur, dcur);
       floatx4 dvacc[8];
       floatx4 atp;  // BF16: A^T of the even tile of a pair
 #pragma unroll
@@ -755,7 +766,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
               accum_rows2(buf, qt - 1, r, g, atp, floatx4{0.f, 0.f, 0.f, 0.f}, dvacc);
           continue;
         }
-        if (qt + 1 < NT) lam_tile(qt + 1, lnxt);
+        if (qt + 1 < NT) lam_tile(qt + 1, lnxt, dnxt);
         floatx4 at;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -769,7 +780,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
           const float l = BF ? (lm + shift) * ww - shift : logit64(lm, kw[qq], wkd, shift);
           const float p = ok ? exp_hw(l - sq.x) * sq.y : 0.f;
           const float h = ww * c;
-          const float dav = dk[qt][v];
+          const float dav = ok ? dcur[v] : 0.f;
           const float dH = dav * p;
           const float dL = p * (dav * h - sq.z);
           at[v] = p * h;
@@ -788,7 +799,10 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
           accum_rows(buf, qt, r, g, at, dvacc);  // dV = A^T dO
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) lcur[v] = lnxt[v];
+        for (int v = 0; v < 4; ++v) {
+          lcur[v] = lnxt[v];
+          dcur[v] = dnxt[v];
+        }
         __builtin_amdgcn_sched_barrier(0);
       }
       if (kok) {
@@ -1192,7 +1206,7 @@ void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *
 
 void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
                              const float *dO, const float *lam, const float *fstat, float *dqkv,
-                             float *astat, float *qside, hipStream_t s) {
+                             float *astat, float *qside, float *dA, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
   const dim3 grid(grid_for(a.bf16 ? 4 : 1, cls));
@@ -1200,11 +1214,11 @@ void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const
                                             bwdq_lds<NP>(), s, qkv, o, dO, a.geom, a.pair_off,
                                             a.nnei, cl, cc, a.sel, a.shift, lam,
                                             (const float2 *)fstat, dqkv, (float4 *)astat,
-                                            (float4 *)qside));
+                                            (float4 *)qside, dA));
 }
 
 void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
-                             const float *lam, float *dqkv, const float *astat,
+                             const float *lam, const float *dA, float *dqkv, const float *astat,
                              const float *qside, float *gw, float *gr, int accumulate,
                              hipStream_t s) {
   if (a.nloc <= 0) return;
@@ -1212,7 +1226,7 @@ void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const
   const dim3 grid(grid_for(a.bf16 ? 5 : 2, cls));
   ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_bwd_k<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             bwdk_lds<NP>(), s, qkv, dO, a.geom, a.pair_off,
-                                            a.nnei, cl, cc, a.shift, lam, dqkv,
+                                            a.nnei, cl, cc, a.shift, lam, dA, dqkv,
                                             (const float4 *)astat, (const float4 *)qside, gw, gr,
                                             accumulate));
 }

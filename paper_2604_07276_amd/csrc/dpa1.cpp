@@ -432,6 +432,7 @@ size_t carve_pairs(dp_model *m, char *base, size_t P, bool shared) {
   w.g = c.take<float>(P * 4);
   w.astat = c.take<float>(P * 4);
   w.qside = c.take<float>(P * 4);
+  w.dA = m->n_attn > 0 ? c.take<float>(P * kAttnLamLd) : nullptr;
   w.du.assign(ne, nullptr);
   w.dh.assign(ne, nullptr);
   if (!fused)
@@ -837,11 +838,12 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       if ((m->cls_active >> cls) & 1)
         RUN(kAttnBwdQName[cls],
           launch_attn_bwd_q_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a], w.dqkv,
-                                  w.astat, w.qside, s));
+                                  w.astat, w.qside, w.dA, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       if ((m->cls_active >> cls) & 1)
         RUN(kAttnBwdKName[cls],
-          launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dqkv, w.astat, w.qside,
+          launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dA, w.dqkv, w.astat,
+                                  w.qside,
                                   w.gw, w.gr, a != na - 1, s));
     GemmArgs g2{w.dqkv, 3 * D, A.Wb_qkv, 3 * D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
     const int mode = a > 0 ? 0 : (emb_fused ? 2 : 1);

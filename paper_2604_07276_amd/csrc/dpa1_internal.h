@@ -171,13 +171,15 @@ void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *
                            float *fstat, hipStream_t s);
 // Backward, query tiles: dQ, (m, 1/Z, D_q) and the query-side gate/switch
 // gradients (astat, qside: per-pair float4 buffers read by the key-tile pass).
+// dA [P][kAttnLamLd]: dL/dA of every (query, key) pair of a centre, in the
+// layout of lam, written here and read by the key-tile pass.
 void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
                              const float *dO, const float *lam, const float *fstat, float *dqkv,
-                             float *astat, float *qside, hipStream_t s);
+                             float *astat, float *qside, float *dA, hipStream_t s);
 // Backward, key tiles: dK, dV and the total dE/dsw, dE/drhat per pair
 // (accumulated onto gw/gr when accumulate != 0).
 void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
-                             const float *lam, float *dqkv, const float *astat,
+                             const float *lam, const float *dA, float *dqkv, const float *astat,
                              const float *qside, float *gw, float *gr, int accumulate,
                              hipStream_t s);
 // Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].

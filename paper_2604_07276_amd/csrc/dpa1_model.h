@@ -134,6 +134,7 @@ struct dp_model {
     std::vector<float *> z, tf;        // fitting outputs / tanh parts
     std::vector<float *> fa, fdz;      // fitting backward a_l and dz_l
     float *dD, *dGa, *dGb, *dY, *dO, *dqkv, *dRt, *gw, *gr, *gs, *g, *astat, *qside;
+    float *dA;                         // attention dL/dA per (query, key), layout of lam
     std::vector<float *> du, dh;       // embedding backward
   } w;
   dpa1::DevFlags *flags = nullptr;       // device
