@@ -94,7 +94,9 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
     The FP32 inputs each kernel must read and the outputs it must write, at
     the real widths (M = embedding width, d = attention width), once each;
     the stored logits lam (n per query row) and softmax statistics are part
-    of the forward's output and the backward's input.  Returns
+    of the forward's output and the backward's input, and the probability
+    adjoint dA (n per query row) part of the query-tile adjoint's output and
+    the key-tile adjoint's input (stored instead of formed a second time).  Returns
     {kernel: (bytes per step, launches per step)}.
     """
     P = float(nnei.sum())
@@ -102,7 +104,9 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
     f4 = 4.0
     out = {
         "qkv_fwd": (L * P * f4 * (M + 3 * d), L),
-        "qkv_bwd": (L * P * f4 * (3 * d + M + 2 * M + 1 + 2 * M), L),
+        # dQKV, the residual gradient and xhat (or the embedding's tanh) and
+        # 1/std in; the gradient and the next layer's seed out
+        "qkv_bwd": (L * P * f4 * (3 * d + 2 * M + 1 + 2 * M), L),
         "oproj_ln_fwd": (L * P * f4 * (d + M + 2 * M + 1), L),
         "oproj_bwd": (L * P * f4 * (M + d), L),
     }
@@ -113,10 +117,12 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
         n2c = float((nn[sel_c] ** 2).sum())
         # fwd: Q, K, V, gate (rhat, sw) in; o, lam, (m, 1/Z) out
         out[f"attn_fwd_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + d + 2) + f4 * n2c), L)
-        # bwd_q: K, V, dO, o, gate, (m, 1/Z), lam in; dQ, (m, 1/Z, D_q), query sums out
-        out[f"attn_bwd_q_n{npad}"] = (L * (Pc * f4 * (5 * d + 4 + 2 + d + 4 + 4) + f4 * n2c), L)
-        # bwd_k: Q, V, dO, gate, stats, query sums, lam in; dK, dV, dE/dsw, dE/drhat out
-        out[f"attn_bwd_k_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + 4 + 4 + 2 * d + 4) + f4 * n2c), L)
+        # bwd_q: K, V, dO, o, gate, (m, 1/Z), lam in; dQ, (m, 1/Z, D_q), query
+        # sums and the probability adjoint dA (n per query row) out
+        out[f"attn_bwd_q_n{npad}"] = (L * (Pc * f4 * (5 * d + 4 + 2 + 4 + 4) + 2 * f4 * n2c), L)
+        # bwd_k: Q, dO, gate, stats, query sums, lam and dA in; dK, dV,
+        # dE/dsw, dE/drhat out
+        out[f"attn_bwd_k_n{npad}"] = (L * (Pc * f4 * (2 * d + 4 + 4 + 4 + 2 * d + 4) + 2 * f4 * n2c), L)
     return out
 
 

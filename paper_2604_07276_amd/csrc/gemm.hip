@@ -436,6 +436,99 @@ __global__ __launch_bounds__(256, 2) void k_gemm_lds(GemmArgs a, Epi epi) {
   }
 }
 
+// Resident-weight variant for the long-K FP32 adjoint of the QKV projection
+// (K = KCH*16 = 384 rows of W, Nreal <= NT*16 output columns): the whole
+// W^T[Nreal][K] block lives in LDS for the launch (one 8-wavefront workgroup
+// per CU), so the k loop has no barrier and reads no weights from L2.  Each
+// wavefront walks its own 64-row tiles independently and streams X through
+// a ring of three 16-deep chunks, two chunks ahead of the one it multiplies;
+// the ring runs on across tile boundaries, so the next tile's first chunks
+// arrive during the current tile's last ones and its epilogue.  Output
+// columns past Nreal read a clamped W row; the epilogue zeroes them.
+template <int MT, int NT, int KCH, class Epi>
+__global__ __launch_bounds__(512, 1) void k_gemm_wres(GemmArgs a, Epi epi) {
+  static_assert(KCH % 3 == 0, "the chunk ring is unrolled by three");
+  constexpr int K = KCH * 16;
+  constexpr int LDW = K + 4;
+  extern __shared__ float wsm[];  // [Nreal][LDW], then cs
+  const int M = a.Mptr ? *a.Mptr : a.Mmax;
+  const int nreal = a.Nreal;
+  for (int idx = threadIdx.x; idx < nreal * (K / 4); idx += blockDim.x) {
+    const int n = idx / (K / 4), c4 = idx % (K / 4);
+    *(float4 *)(wsm + n * LDW + 4 * c4) = *(const float4 *)(a.Wt + (size_t)n * a.K + 4 * c4);
+  }
+  float *cs = wsm + nreal * LDW;  // [Epi::kCols][NT * 16]
+  stage_cols<Epi, NT>(epi, 0, a.Npad, cs);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int ntt = a.Npad / 16;
+  const int stride = gridDim.x * 8 * 16 * MT;  // rows between a wave's consecutive tiles
+  int row0 = (blockIdx.x * 8 + wave) * 16 * MT;
+  if (row0 >= M) return;  // no barrier follows
+  int lane_it = lane;
+  asm volatile("" : "+v"(lane_it));
+  const int r = lane_it & 15;
+  const int g = lane_it >> 4;
+  const float *wl[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int n = nt * 16 + r < nreal ? nt * 16 + r : nreal - 1;
+    wl[nt] = wsm + n * LDW + 4 * g;
+  }
+  auto rows_of = [&](int base, const float *(&xp)[MT]) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = base + mt * 16 + r;
+      xp[mt] = a.X + (size_t)(row < M ? row : 0) * a.ldx + 4 * g;
+    }
+  };
+  const float *xc[MT], *xn[MT];
+  rows_of(row0, xc);
+  rows_of(row0 + stride, xn);
+  floatx4 xb[3][MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    xb[0][mt] = *(const floatx4 *)(xc[mt]);
+    xb[1][mt] = *(const floatx4 *)(xc[mt] + 16);
+  }
+  for (; row0 < M; row0 += stride) {
+    floatx4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int c = 0; c < KCH; c += 3) {
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        // chunk c + u sits in slot u; chunk c + u + 2 (of this tile, or of
+        // the next one past the last chunk) goes into the slot freed by the
+        // previous step
+        const int cp = c + u + 2;
+        const bool here = cp < KCH;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          xb[(u + 2) % 3][mt] = *(const floatx4 *)(here ? xc[mt] + 16 * cp : xn[mt] + 16 * (cp - KCH));
+        floatx4 w[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wl[nt] + 16 * (c + u));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(w[nt][t], xb[u][mt][t], acc[mt][nt]);
+      }
+    }
+    epi.template apply<MT, NT>(acc, row0, 0, ntt, lane, M, cs);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) xc[mt] = xn[mt];
+    rows_of(row0 + 2 * stride, xn);
+  }
+}
+
 // ------------------------------------------------------------------ epilogues
 //
 // Every epilogue issues all the global loads of a 16-row tile (clamped to
@@ -914,6 +1007,40 @@ void dispatch_nt(const GemmArgs &a, const Epi &e, int nt, hipStream_t s) {
   }
 }
 
+// LDS bytes of the resident-weight kernel: W^T[Nreal][K + 4] and the staged
+// column vectors.
+template <class Epi, int NT, int KCH>
+size_t wres_lds(int nreal) {
+  return sizeof(float) * ((size_t)nreal * (KCH * 16 + 4) + Epi::kCols * NT * 16);
+}
+
+// One workgroup of eight wavefronts per CU; the grid never exceeds the CU
+// count (a second wave of workgroups would start only after the first).
+template <class Epi, int NT, int KCH>
+bool launch_wres(const GemmArgs &a, const Epi &e, hipStream_t s) {
+  constexpr int MT = 4;
+  static int ready[64];  // 1: dynamic LDS limit raised on that device, -1: refused
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  const size_t lds = wres_lds<Epi, NT, KCH>(a.Nreal);
+  if (ready[dev] == 0) {
+    int maxl = 0;
+    ready[dev] = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                             hipSuccess &&
+                         hipFuncSetAttribute((const void *)k_gemm_wres<MT, NT, KCH, Epi>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             maxl) == hipSuccess
+                     ? maxl
+                     : -1;
+  }
+  if (ready[dev] < 0 || lds > (size_t)ready[dev]) return false;
+  const long tiles = (a.Mmax + 8L * 16 * MT - 1) / (8L * 16 * MT);
+  const long gx = tiles < cu_count() ? tiles : cu_count();
+  if (gx <= 0) return true;
+  hipLaunchKernelGGL((k_gemm_wres<MT, NT, KCH, Epi>), dim3((unsigned)gx), dim3(512), lds, s, a, e);
+  return true;
+}
+
 template <class Epi, int NT, int KCH>
 void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   constexpr int MT = 2;
@@ -959,8 +1086,15 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
       return launch_lds<Epi, 8, 8>(a, e, s);
     }
   }
-  // the long-K adjoint of the QKV projection: 64-row tiles halve the weight
-  // reads per row (two waves per SIMD, 238 registers, no spills)
+  // the FP32 adjoint of the QKV projection (K = 384, seven column tiles):
+  // the whole weight block resident in LDS when it fits
+  if constexpr (Epi::kLds == 0) {
+    if (a.Mmax >= 65536 && full_rows && !a.bf16 && a.K == 384 && nt == 7 && ntt == 7 &&
+        launch_wres<Epi, 7, 24>(a, e, s))
+      return;
+  }
+  // the long-K adjoint of the QKV projection otherwise: 64-row tiles halve
+  // the weight reads per row (two waves per SIMD, 238 registers, no spills)
   if (a.Mmax >= 65536 && full_rows && Epi::kLds == 0 && a.K >= 256) dispatch_nt<Epi, 4>(a, e, nt, s);
   else if (a.Mmax >= 65536) dispatch_nt<Epi, 2>(a, e, nt, s);
   else dispatch_nt<Epi, 1>(a, e, nt, s);
