@@ -79,6 +79,8 @@ def flop_model(nnei: np.ndarray, shape) -> dict:
         n2c = float((nn[sel_c] ** 2).sum())
         for name in ("attn_fwd", "attn_bwd_q", "attn_bwd_k"):
             out[f"{name}_n{npad}"] = (L * 2.0 * 2 * d * n2c, L)
+        # the fused FP32 adjoint (classes up to 96): dA, dQ, dV and dK
+        out[f"attn_bwd_n{npad}"] = (L * 2.0 * 4 * d * n2c, L)
     return out
 
 
@@ -123,6 +125,9 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
         # bwd_k: Q, dO, gate, stats, query sums, lam and dA in; dK, dV,
         # dE/dsw, dE/drhat out
         out[f"attn_bwd_k_n{npad}"] = (L * (Pc * f4 * (2 * d + 4 + 4 + 4 + 2 * d + 4) + 2 * f4 * n2c), L)
+        # fused adjoint: Q, K, V, dO, o, gate, (m, 1/Z), lam in; dQ, dK, dV,
+        # dE/dsw, dE/drhat out
+        out[f"attn_bwd_n{npad}"] = (L * (Pc * f4 * (5 * d + 4 + 2 + 3 * d + 4) + f4 * n2c), L)
     return out
 
 

@@ -862,13 +862,257 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 96 ? 3 : 2) : 2) void
   }
 }
 
+// ------------------------------------------------------------ fused adjoint
+//
+// FP32 classes of up to 96 neighbours: one workgroup per centre runs both
+// halves of the adjoint.  Phase Q (wavefront = query tile) forms dA^T, the
+// softmax adjoint, dS and dQ as the query-tile kernel does and leaves
+// A = P H and dS of the centre in LDS ([query][key], row stride NPAD + 4),
+// with the query-side sums and the key-side sums reduced over its 16
+// queries; phase K (wavefront = key tile) forms dV = A^T dO and dK = dS^T Q
+// from them.  Against the two-kernel form the centre's logits and gate
+// records are read once, and dA and the per-pair statistics never go to
+// memory.  dQ, dK and dV are accumulated in the same order as there; only
+// the key-side sums are added in another order.
+template <int NPAD>
+constexpr int fused_ld() { return NPAD + 4; }
+
+template <int NPAD>
+size_t bwdf_lds() {
+  constexpr int W = NPAD / 16;
+  return sizeof(float4) * NPAD * (2 + W)  // kg, qside, key-side sums per query tile
+         + sizeof(double) * NPAD          // kw
+         + sizeof(float) * stage_floats<NPAD>() + sizeof(float) * 2 * NPAD * fused_ld<NPAD>();
+}
+
+// Sum of 16 per-lane values over the 16 lanes of a lane group (those that
+// share lane / 16): after four halving steps lane r of the group holds the
+// total of value r (30 exchanges instead of 64).  Both halves are exchanged
+// and the lane keeps one sum: a select between two array elements would be
+// turned into an indexed access and push the array out of registers.
+__device__ __forceinline__ float reduce16_transposed(float (&v)[16], int r) {
+#pragma unroll
+  for (int s = 8; s >= 1; s >>= 1) {
+    const bool up = (r & s) != 0;
+#pragma unroll
+    for (int j = 0; j < s; ++j) {
+      const float lo = v[j], hi = v[j + s];
+      const float lo_t = lo + __shfl_xor(lo, s);
+      const float hi_t = hi + __shfl_xor(hi, s);
+      v[j] = up ? hi_t : lo_t;
+    }
+  }
+  return v[0];
+}
+
+template <int NPAD>
+__global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd_f(
+    const float *__restrict__ qkv, const float *__restrict__ o, const float *__restrict__ dO,
+    const float *__restrict__ geom, const int *__restrict__ pair_off,
+    const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
+    int sel, float shift, const float *__restrict__ lam, const float2 *__restrict__ fstat,
+    float *__restrict__ dqkv, float *__restrict__ gw, float *__restrict__ gr, int accumulate) {
+  constexpr int NT = NPAD / 16;
+  constexpr int LDF = fused_ld<NPAD>();
+  extern __shared__ float4 smem[];
+  float4 *kg = smem;                       // [NPAD] rhat, sw
+  float4 *qside = kg + NPAD;               // [NPAD] query-side sums of each neighbour
+  float4 *ksum = qside + NPAD;             // [NT][NPAD] key-side sums, per query tile
+  double *kw = (double *)(ksum + NT * NPAD);  // [NPAD] switch values in FP64
+  float *buf = (float *)(kw + NPAD);       // V rows, K^T, dO rows, Q^T in turn
+  float *As = buf + stage_floats<NPAD>();  // [NPAD][LDF] A = P H
+  float *Ds = As + NPAD * LDF;             // [NPAD][LDF] dS
+  const int ld = kQKV * 128;
+  const float inv_sqrt_d = 0.08838834764831845f;
+  const int cnt = *ccount;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int tid = fresh_tid();
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int i = clist[it];
+    const int n = nnei[i];
+    const int base = pair_off[i];
+    const int ntile = (n + 15) >> 4;
+    const int q = wave * 16 + r;
+    const bool qok = q < n;
+    float4 sv[8];
+    stage_rows_load<NPAD, false>(qkv, 256, ld, base, n, tid, sv);  // V
+    float gl;
+    const float4 gv = gate_load(geom, base, n, tid, gl);
+    floatx4 dov[8], ov[8];
+    load_rows<false>(dO, 0, 128, base, n, q, g, dov);
+    load_rows<false>(o, 0, 128, base, n, q, g, ov);
+    stage_rows_store<NPAD>(buf, tid, n, sv);
+    gate_store<NPAD>(kg, kw, tid, n, gv, gl);
+    __syncthreads();
+
+    // ---------------- phase Q: dA^T, dS, dQ, A and dS to LDS, both sides' sums
+    float dq = 0.f;
+    if (wave < ntile) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
+              dov[c][3] * ov[c][3];
+      dq = sum_groups(dq);
+    }
+    float4 kpre[8];  // K, read while dA^T is formed
+    stage_t_load<NPAD, false>(qkv, 128, ld, base, n, tid, kpre);
+    floatx4 da[NT];
+    if (wave < ntile) qk_lds<NT, false>(buf, r, g, dov, da);  // lane: query r, keys 4g + v
+    __syncthreads();
+    stage_t_store<NPAD>(buf, tid, n, kpre);  // K^T
+    __syncthreads();
+    float4 spre[8];  // dO rows of phase K, read during phase Q's products
+    stage_rows_load<NPAD, false>(dO, 0, 128, base, n, tid, spre);
+    if (wave < ntile) {
+      const int qr = qok ? q : 0;
+      const float4 gq = kg[q];
+      const float wq = qok ? gq.w : 0.f;
+      const double wqd = qok ? kw[q] : 0.0;
+      const float2 fs = fstat[base + qr];
+      const float m = fs.x, invz = fs.y;
+      const float *lp = lam + (size_t)(base + qr) * kLamLd + 4 * g;
+      floatx4 dqacc[8];
+#pragma unroll
+      for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
+      floatx4 lcur = *(const floatx4 *)lp, lnxt;
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) {
+        if (kt + 1 < NT) lnxt = *(const floatx4 *)(lp + 16 * (kt + 1));
+        floatx4 ds, at;
+        float ks[16];  // key-side terms: X w_q, Y rhat_q (x, y, z) for the four keys
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = kt * 16 + 4 * g + v;
+          const bool ok = qok && k < n;
+          const float4 gk = kg[k];
+          const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
+          const float ww = wq * gk.w;
+          const float lm = ok ? lcur[v] : 0.f;
+          const float l = logit64(lm, wqd, kw[k], shift);
+          const float p = ok ? exp_hw(l - m) * invz : 0.f;
+          const float h = ww * c;
+          const float dH = da[kt][v] * p;
+          const float dL = p * (da[kt][v] * h - dq);
+          ds[v] = dL * ww * inv_sqrt_d;
+          at[v] = p * h;
+          const float X = dL * (lm + shift) + dH * c;
+          const float Y = dH * ww;
+          dwq += X * gk.w;
+          drqx += Y * gk.x;
+          drqy += Y * gk.y;
+          drqz += Y * gk.z;
+          ks[v] = X * wq;
+          ks[4 + v] = Y * gq.x;
+          ks[8 + v] = Y * gq.y;
+          ks[12 + v] = Y * gq.z;
+        }
+        *(floatx4 *)(As + q * LDF + kt * 16 + 4 * g) = at;
+        *(floatx4 *)(Ds + q * LDF + kt * 16 + 4 * g) = ds;
+        // lane r now holds the wavefront's total of term r / 4 for key
+        // 4g + r % 4 of this tile
+        const float kt_sum = reduce16_transposed(ks, r);
+        ((float *)ksum)[(wave * NPAD + kt * 16 + 4 * g + (r & 3)) * 4 + (r >> 2)] = kt_sum;
+        accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);  // dQ = dS K
+        lcur = lnxt;
+      }
+      dwq = sum_groups(dwq);
+      drqx = sum_groups(drqx);
+      drqy = sum_groups(drqy);
+      drqz = sum_groups(drqz);
+      if (g == 0 && qok) qside[q] = make_float4(dwq, drqx, drqy, drqz);
+      if (qok) {
+        float *dp = dqkv + (size_t)(base + q) * ld + 4 * g;
+#pragma unroll
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dqacc[ft];
+      }
+    }
+    __syncthreads();
+    stage_rows_store<NPAD>(buf, tid, n, spre);  // dO rows
+    __syncthreads();
+
+    // ---------------- phase K: dV = A^T dO, dK = dS^T Q, key-side sums
+    float4 qpre[8];  // Q, read while dV is formed
+    stage_t_load<NPAD, false>(qkv, 0, ld, base, n, tid, qpre);
+    const int kk = wave * 16 + r;
+    const bool kok = kk < n;
+    if (wave < ntile) {
+      floatx4 dvacc[8];
+#pragma unroll
+      for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int qt = 0; qt < NT; ++qt) {
+        if (qt >= ntile) continue;
+        floatx4 at;  // lane: key r, queries 4g + v
+#pragma unroll
+        for (int v = 0; v < 4; ++v) at[v] = As[(qt * 16 + 4 * g + v) * LDF + kk];
+        accum_rows(buf, qt, r, g, at, dvacc);
+      }
+      if (kok) {
+        float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
+#pragma unroll
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
+      }
+    }
+    __syncthreads();
+    stage_t_store<NPAD>(buf, tid, n, qpre);  // Q^T
+    __syncthreads();
+    if (wave < ntile) {
+      floatx4 dkacc[8];
+#pragma unroll
+      for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int qt = 0; qt < NT; ++qt) {
+        if (qt >= ntile) continue;
+        floatx4 dsv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dsv[v] = Ds[(qt * 16 + 4 * g + v) * LDF + kk];
+        accum_lds<NPAD>(buf, qt, r, g, dsv, dkacc);
+      }
+      if (kok) {
+        float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+#pragma unroll
+        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+        if (g == 0) {
+          float4 t = qside[kk];
+          for (int w = 0; w < ntile; ++w) {
+            const float4 kv = ksum[w * NPAD + kk];
+            t.x += kv.x;
+            t.y += kv.y;
+            t.z += kv.z;
+            t.w += kv.w;
+          }
+          const size_t p = (size_t)(base + kk);
+          if (accumulate) {
+            gw[p] += t.x;
+            gr[4 * p + 0] += t.y;
+            gr[4 * p + 1] += t.z;
+            gr[4 * p + 2] += t.w;
+          } else {
+            gw[p] = t.x;
+            gr[4 * p + 0] = t.y;
+            gr[4 * p + 1] = t.z;
+            gr[4 * p + 2] = t.w;
+            gr[4 * p + 3] = 0.f;
+          }
+        }
+      }
+    }
+    __syncthreads();  // LDS is restaged for the next centre
+  }
+}
+
 // Class lists: centre i with n = nnei[i] > 0 belongs to class (n - 1) / 32
 // (counted in ccount[4 + class]) and is listed in the smallest class of the
 // active set (bit c of `active`) that holds n neighbours; the host keeps the
 // top class active, so every centre is listed.  A class that is not active
 // is not launched: the host deactivates classes that were empty in an
 // earlier step, and a centre that falls into one after all is computed by
-// the next larger active class (more padding, the same result).  Positions
+// the next larger active class (more padding, the same result: the host
+// keeps the largest class of the fused FP32 adjoint active, so the fallback
+// never changes the kind of adjoint).  Positions
 // are taken with one atomic per wavefront and class, so the order inside a
 // list varies from run to run; every centre is computed on its own, so
 // results do not depend on it.
@@ -1103,7 +1347,7 @@ size_t bwdk_lds() {
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.
 constexpr int kMaxDevices = 64;
-int g_grid[kMaxDevices][6][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16
+int g_grid[kMaxDevices][7][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16, fused FP32 adjoint
 
 int grid_for(int kind, int cls) {
   int dev = 0;
@@ -1144,6 +1388,13 @@ hipError_t prepare_class(int dev, int cus, int cls) {
   if (e == hipSuccess)
     e = occupancy_grid(k_attn_bwd_k<NPAD, BF>, th, bwdk_lds<NPAD>(), cus,
                        &g_grid[dev][k0 + 2][cls]);
+  if constexpr (!BF && NPAD <= 96) {
+    if (e == hipSuccess && bwdf_lds<NPAD>() > 65536)
+      e = hipFuncSetAttribute((const void *)k_attn_bwd_f<NPAD>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdf_lds<NPAD>());
+    if (e == hipSuccess)
+      e = occupancy_grid(k_attn_bwd_f<NPAD>, th, bwdf_lds<NPAD>(), cus, &g_grid[dev][6][cls]);
+  }
   return e;
 }
 
@@ -1215,6 +1466,25 @@ void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const
                                             a.nnei, cl, cc, a.sel, a.shift, lam,
                                             (const float2 *)fstat, dqkv, (float4 *)astat,
                                             (float4 *)qside, dA));
+}
+
+bool attn_bwd_fused(const AttnArgs &a, int cls) { return !a.bf16 && cls <= 2; }
+
+void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
+                                 const float *dO, const float *lam, const float *fstat,
+                                 float *dqkv, float *gw, float *gr, int accumulate,
+                                 hipStream_t s) {
+  if (a.nloc <= 0 || !attn_bwd_fused(a, cls)) return;
+  const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
+  const dim3 grid(grid_for(6, cls));
+#define ATTN_BWD_F(NP)                                                                         \
+  hipLaunchKernelGGL((k_attn_bwd_f<NP>), grid, dim3(NP / 16 * 64), bwdf_lds<NP>(), s, qkv, o, \
+                     dO, a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift, lam,              \
+                     (const float2 *)fstat, dqkv, gw, gr, accumulate)
+  if (cls == 0) ATTN_BWD_F(32);
+  else if (cls == 1) ATTN_BWD_F(64);
+  else ATTN_BWD_F(96);
+#undef ATTN_BWD_F
 }
 
 void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,

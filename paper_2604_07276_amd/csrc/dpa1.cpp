@@ -613,6 +613,8 @@ const char *const kAttnFwdName[4] = {"attn_fwd_n32", "attn_fwd_n64", "attn_fwd_n
                                      "attn_fwd_n128"};
 const char *const kAttnBwdQName[4] = {"attn_bwd_q_n32", "attn_bwd_q_n64", "attn_bwd_q_n96",
                                       "attn_bwd_q_n128"};
+const char *const kAttnBwdName[4] = {"attn_bwd_n32", "attn_bwd_n64", "attn_bwd_n96",
+                                     "attn_bwd_n128"};
 const char *const kAttnBwdKName[4] = {"attn_bwd_k_n32", "attn_bwd_k_n64", "attn_bwd_k_n96",
                                       "attn_bwd_k_n128"};
 
@@ -678,6 +680,15 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
     active = 1 << (ncls - 1);
     for (int c = 0; c < ncls - 1; ++c)
       if (m->ccount_host[4 + c] > 0) active |= 1 << c;
+    // the largest class with the fused FP32 adjoint stays launched, so that a
+    // centre is always computed by the same kind of adjoint (fused or not)
+    // and results do not depend on which classes were empty before
+    const AttnArgs probe{nullptr, nullptr, nullptr, nullptr, nullptr, nloc, sel, 0.f, m->bf16};
+    for (int c = ncls - 2; c >= 0; --c)
+      if (attn_bwd_fused(probe, c) && !attn_bwd_fused(probe, ncls - 1)) {
+        active |= 1 << c;
+        break;
+      }
   }
   m->cls_active = active;
   if (na > 0)
@@ -835,12 +846,17 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16, 0, m->M};
     RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
-      if ((m->cls_active >> cls) & 1)
+      if (((m->cls_active >> cls) & 1) && attn_bwd_fused(aa, cls))
+        RUN(kAttnBwdName[cls],
+          launch_attn_bwd_fused_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a],
+                                      w.dqkv, w.gw, w.gr, a != na - 1, s));
+    for (int cls = 0; cls < attn_class_count(sel); ++cls)
+      if (((m->cls_active >> cls) & 1) && !attn_bwd_fused(aa, cls))
         RUN(kAttnBwdQName[cls],
           launch_attn_bwd_q_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a], w.dqkv,
                                   w.astat, w.qside, w.dA, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
-      if ((m->cls_active >> cls) & 1)
+      if (((m->cls_active >> cls) & 1) && !attn_bwd_fused(aa, cls))
         RUN(kAttnBwdKName[cls],
           launch_attn_bwd_k_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.dA, w.dqkv, w.astat,
                                   w.qside,

@@ -182,6 +182,14 @@ void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const
                              const float *lam, const float *dA, float *dqkv, const float *astat,
                              const float *qside, float *gw, float *gr, int accumulate,
                              hipStream_t s);
+// Both halves of the backward in one kernel (FP32, classes of up to 96
+// neighbours; attn_bwd_fused tells whether a class has it): the outputs of
+// the query-tile and key-tile passes without dA, astat and qside.
+bool attn_bwd_fused(const AttnArgs &a, int cls);
+void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
+                                 const float *dO, const float *lam, const float *fstat,
+                                 float *dqkv, float *gw, float *gr, int accumulate,
+                                 hipStream_t s);
 // Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,
                      const int *nnei, int nloc, int sel, int M, int axis, float *T, float *dmat,
