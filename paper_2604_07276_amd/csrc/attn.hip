@@ -925,21 +925,30 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;
   const int cnt = *ccount;
+  // the V rows and gate records of a centre are loaded during the dK
+  // product of the previous one
+  float4 sv[8];
+  float4 gv;
+  float gl = 0.f;
+  int n_nx = 0, base_nx = 0;
+  if ((int)blockIdx.x < cnt) {
+    const int tid = fresh_tid();
+    const int i0 = clist[blockIdx.x];
+    n_nx = nnei[i0];
+    base_nx = pair_off[i0];
+    stage_rows_load<NPAD, false>(qkv, 256, ld, base_nx, n_nx, tid, sv);  // V
+    gv = gate_load(geom, base_nx, n_nx, tid, gl);
+  }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const int tid = fresh_tid();
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int r = lane & 15, g = lane >> 4;
-    const int i = clist[it];
-    const int n = nnei[i];
-    const int base = pair_off[i];
+    const int n = n_nx;
+    const int base = base_nx;
     const int ntile = (n + 15) >> 4;
     const int q = wave * 16 + r;
     const bool qok = q < n;
-    float4 sv[8];
-    stage_rows_load<NPAD, false>(qkv, 256, ld, base, n, tid, sv);  // V
-    float gl;
-    const float4 gv = gate_load(geom, base, n, tid, gl);
     floatx4 dov[8], ov[8];
     load_rows<false>(dO, 0, 128, base, n, q, g, dov);
     load_rows<false>(o, 0, 128, base, n, q, g, ov);
@@ -963,8 +972,6 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
     __syncthreads();
     stage_t_store<NPAD>(buf, tid, n, kpre);  // K^T
     __syncthreads();
-    float4 spre[8];  // dO rows of phase K, read during phase Q's products
-    stage_rows_load<NPAD, false>(dO, 0, 128, base, n, tid, spre);
     if (wave < ntile) {
       const int qr = qok ? q : 0;
       const float4 gq = kg[q];
@@ -1030,7 +1037,14 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
       }
     }
     __syncthreads();
-    stage_rows_store<NPAD>(buf, tid, n, spre);  // dO rows
+    {
+      // dO rows for phase K: each wavefront writes the rows it holds (zeros
+      // past n) instead of reading them from memory a second time
+      float *xr = buf + q * kLDR + 4 * g;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        *(floatx4 *)(xr + 16 * c) = qok ? dov[c] : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
     __syncthreads();
 
     // ---------------- phase K: dV = A^T dO, dK = dS^T Q, key-side sums
@@ -1059,6 +1073,16 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
     __syncthreads();
     stage_t_store<NPAD>(buf, tid, n, qpre);  // Q^T
     __syncthreads();
+    {
+      const int itn = it + (int)gridDim.x;
+      if (itn < cnt) {
+        const int inx = clist[itn];
+        n_nx = nnei[inx];
+        base_nx = pair_off[inx];
+        stage_rows_load<NPAD, false>(qkv, 256, ld, base_nx, n_nx, tid, sv);  // next V
+        gv = gate_load(geom, base_nx, n_nx, tid, gl);
+      }
+    }
     if (wave < ntile) {
       floatx4 dkacc[8];
 #pragma unroll
@@ -1349,11 +1373,15 @@ size_t bwdk_lds() {
 constexpr int kMaxDevices = 64;
 int g_grid[kMaxDevices][7][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16, fused FP32 adjoint
 
-int grid_for(int kind, int cls) {
+// Blocks of the grid of a class that held no centres in a recent step: an
+// empty launch of the full persistent grid costs ~20 us.
+constexpr int kSmallGrid = 32;
+
+int grid_for(int kind, int cls, int small = 0) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
-  const int gsz = g_grid[dev][kind][cls];
-  return gsz > 0 ? gsz : 1024;
+  const int gsz = g_grid[dev][kind][cls] > 0 ? g_grid[dev][kind][cls] : 1024;
+  return ((small >> cls) & 1) && gsz > kSmallGrid ? kSmallGrid : gsz;
 }
 
 template <class K>
@@ -1449,7 +1477,7 @@ void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *
                            float *fstat, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(a.bf16 ? 3 : 0, cls));
+  const dim3 grid(grid_for(a.bf16 ? 3 : 0, cls, a.small));
   ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_fwd<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             fwd_lds<NP>(), s, qkv, a.geom, a.pair_off, a.nnei,
                                             cl, cc, a.sel, a.shift, out, lam, (float2 *)fstat));
@@ -1460,7 +1488,7 @@ void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const
                              float *astat, float *qside, float *dA, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(a.bf16 ? 4 : 1, cls));
+  const dim3 grid(grid_for(a.bf16 ? 4 : 1, cls, a.small));
   ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_bwd_q<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             bwdq_lds<NP>(), s, qkv, o, dO, a.geom, a.pair_off,
                                             a.nnei, cl, cc, a.sel, a.shift, lam,
@@ -1476,7 +1504,7 @@ void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, c
                                  hipStream_t s) {
   if (a.nloc <= 0 || !attn_bwd_fused(a, cls)) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(6, cls));
+  const dim3 grid(grid_for(6, cls, a.small));
 #define ATTN_BWD_F(NP)                                                                         \
   hipLaunchKernelGGL((k_attn_bwd_f<NP>), grid, dim3(NP / 16 * 64), bwdf_lds<NP>(), s, qkv, o, \
                      dO, a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift, lam,              \
@@ -1493,7 +1521,7 @@ void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const
                              hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(a.bf16 ? 5 : 2, cls));
+  const dim3 grid(grid_for(a.bf16 ? 5 : 2, cls, a.small));
   ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_bwd_k<NP, BFV>), grid, dim3(NP / 16 * 64),
                                             bwdk_lds<NP>(), s, qkv, dO, a.geom, a.pair_off,
                                             a.nnei, cl, cc, a.shift, lam, dA, dqkv,

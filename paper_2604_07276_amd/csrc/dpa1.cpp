@@ -690,7 +690,12 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
         break;
       }
   }
+  // the top class is always launched (nothing above it takes its centres);
+  // when it held none recently, on a small grid
+  int small = 0;
+  if (m->ccount_host[4] >= 0 && m->ccount_host[4 + ncls - 1] == 0) small = 1 << (ncls - 1);
   m->cls_active = active;
+  m->cls_small = small;
   if (na > 0)
     RUN("attn_classes", launch_attn_classes(w.nnei, nloc, active, w.ccount, w.clist, s));
   RUN("env_embed1",
@@ -715,7 +720,8 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   }
   // attention layers
   const int D = m->dattn, ldM = m->ldM;
-  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift, m->bf16};
+  const AttnArgs aa{w.geom, w.pair_off, w.nnei,       w.clist,      w.ccount,
+                    nloc,   sel,        (float)m->shift, m->bf16, m->cls_small};
   for (int a = 0; a < na; ++a) {
     const auto &A = m->attn[a];
     // in BF16 mode QKV, o, dO and dQKV are stored in BF16 (matrix-core operands only)
@@ -774,7 +780,8 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
   const int D = m->dattn, ldM = m->ldM;
-  const AttnArgs aa{w.geom, w.pair_off, w.nnei, w.clist, w.ccount, nloc, sel, (float)m->shift, m->bf16};
+  const AttnArgs aa{w.geom, w.pair_off, w.nnei,       w.clist,      w.ccount,
+                    nloc,   sel,        (float)m->shift, m->bf16, m->cls_small};
   const bool emb_fused = ne == 3 && emb_fused_supported(m->lde[0], m->lde[1], m->lde[2]);
   EmbLaunch el{};
   if (emb_fused)

@@ -164,6 +164,9 @@ struct AttnArgs {
   int nloc, sel;
   float shift;
   int bf16;  // 1: BF16 matrix-core operands (FP32 accumulate)
+  // bit c: class c held no centres in a recent step; its persistent grid is
+  // kept to a few blocks (any count is still processed, only more slowly)
+  int small = 0;
 };
 // Forward: O = (P o H) V per centre; stores lam = QK^T/sqrt(d) per pair row
 // ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).

@@ -141,6 +141,7 @@ struct dp_model {
   dpa1::DevFlags *flags_host = nullptr;  // pinned
   int *ccount_host = nullptr;            // pinned [8]: class counts of a recent step
   int cls_active = 0;                    // attention classes launched by the last forward
+  int cls_small = 0;                     // of those, the ones launched on a small grid
   double *bbox = nullptr;          // device [6]: bounding box for open boundaries
   hipStream_t own = nullptr;
   hipStream_t last = nullptr;
