@@ -81,6 +81,9 @@ def flop_model(nnei: np.ndarray, shape) -> dict:
             out[f"{name}_n{npad}"] = (L * 2.0 * 2 * d * n2c, L)
         # the fused FP32 adjoint (classes up to 96): dA, dQ, dV and dK
         out[f"attn_bwd_n{npad}"] = (L * 2.0 * 4 * d * n2c, L)
+        # the FP32 forward with the output projection: Q K^T, A V and o W_O
+        Pc = float(nn[sel_c].sum())
+        out[f"attn_fwd_ln_n{npad}"] = (L * (2.0 * 2 * d * n2c + 2.0 * d * M * Pc), L)
     return out
 
 
@@ -125,9 +128,15 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
         # bwd_k: Q, dO, gate, stats, query sums, lam and dA in; dK, dV,
         # dE/dsw, dE/drhat out
         out[f"attn_bwd_k_n{npad}"] = (L * (Pc * f4 * (2 * d + 4 + 4 + 4 + 2 * d + 4) + 2 * f4 * n2c), L)
-        # fused adjoint: Q, K, V, dO, o, gate, (m, 1/Z), lam in; dQ, dK, dV,
+        # fused adjoint: Q, K, V, dO, gate, (m, 1/Z), lam in; dQ, dK, dV,
         # dE/dsw, dE/drhat out
-        out[f"attn_bwd_n{npad}"] = (L * (Pc * f4 * (5 * d + 4 + 2 + 3 * d + 4) + f4 * n2c), L)
+        out[f"attn_bwd_n{npad}"] = (L * (Pc * f4 * (4 * d + 4 + 2 + 3 * d + 4) + f4 * n2c), L)
+        # forward with the output projection: QKV, gate, residual row in;
+        # logits, statistics, the layer output, xhat and 1/std out (and o
+        # for the 128 class, whose adjoint reads it)
+        o_out = d if npad > 96 else 0
+        out[f"attn_fwd_ln_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + M + 2 + 2 * M + 1 + o_out)
+                                            + f4 * n2c), L)
     return out
 
 
@@ -155,9 +164,11 @@ def kernel_sources(kernel: str) -> list:
     projections: gemm.hip and that header; others: every source)."""
     csrc = os.path.join(ROOT, "paper_2604_07276_amd", "csrc")
     if kernel.startswith("attn_"):
-        return [os.path.join(csrc, "attn.hip"), os.path.join(csrc, "dpa1_internal.h")]
+        return [os.path.join(csrc, "attn.hip"), os.path.join(csrc, "dpa1_internal.h"),
+                os.path.join(csrc, "ln_res.h")]
     if kernel.startswith(("qkv_", "oproj_")):
-        return [os.path.join(csrc, "gemm.hip"), os.path.join(csrc, "dpa1_internal.h")]
+        return [os.path.join(csrc, "gemm.hip"), os.path.join(csrc, "dpa1_internal.h"),
+                os.path.join(csrc, "ln_res.h")]
     return sorted(f for f in glob.glob(os.path.join(csrc, "*"))
                   if f.endswith((".hip", ".cpp", ".h")))
 

@@ -24,6 +24,7 @@
 #include <cfloat>
 
 #include "dpa1_internal.h"
+#include "ln_res.h"
 
 namespace dpa1 {
 
@@ -398,21 +399,41 @@ constexpr int stage_floats() {
 // leave the registers for it).
 
 constexpr int kLamLd = kAttnLamLd;
+constexpr int kOpCols = kAttnOpCols;   // output columns of the fused projection
+constexpr int kOpTiles = kOpCols / 16;
 
-template <int NPAD, bool BF>
+// OP (FP32): the output projection and its layer norm are applied here
+// (W_O^T, 7 column tiles, staged in LDS once per workgroup; the epilogue is
+// the one the projection GEMM uses), so the attention output o goes to
+// memory only where the two-kernel adjoint of the 128 class reads it.
+template <int NPAD, bool BF, bool OP>
 __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) : 2) void k_attn_fwd(
     const float *__restrict__ qkv, const float *__restrict__ geom,
     const int *__restrict__ pair_off, const int *__restrict__ nnei,
     const int *__restrict__ clist, const int *__restrict__ ccount, int sel, float shift,
-    float *__restrict__ out, float *__restrict__ lam, float2 *__restrict__ fstat) {
+    float *__restrict__ out, float *__restrict__ lam, float2 *__restrict__ fstat,
+    AttnOut op) {
   constexpr int NT = NPAD / 16;
+  constexpr bool STORE_O = !OP || NPAD > 96;
   extern __shared__ float4 smem[];
   float4 *kg = smem;
   double *kw = (double *)(smem + NPAD);  // [NPAD] switch values in FP64
   float *buf = (float *)(kw + NPAD);     // K rows, then V^T
+  float *wo = buf + stage_floats<NPAD>();  // OP: W_O^T [kOpCols][kLDR]
+  float *cso = wo + kOpCols * kLDR;        // OP: bias, gamma, beta [3][kOpCols]
   const int ld = kQKV * 128;
   const float inv_sqrt_d = 0.08838834764831845f;  // 1/sqrt(128)
   const int cnt = *ccount;
+  if constexpr (OP) {
+    for (int idx = threadIdx.x; idx < kOpCols * 32; idx += blockDim.x) {
+      const int row = idx >> 5, c4 = idx & 31;
+      *(float4 *)(wo + row * kLDR + 4 * c4) = *(const float4 *)(op.Wt_o + row * 128 + 4 * c4);
+    }
+    for (int idx = threadIdx.x; idx < 3 * kOpCols; idx += blockDim.x) {
+      const int k = idx / kOpCols, n = idx % kOpCols;
+      cso[idx] = (k == 0 ? op.bias : (k == 1 ? op.gamma : op.beta))[n];
+    }
+  }
   // FP32: the staging loads of a centre are issued during the A V phase of the
   // previous one (BF16 holds more registers per tile and loads per centre)
   constexpr bool PREF = !BF;
@@ -533,10 +554,35 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
           accum_lds<NPAD>(buf, kt, r, g, at, oacc);
         }
       }
-      if (qok) {
-        float *op = pt_at<BF>(out, (size_t)(base + q) * 128 + 4 * g);
+      if (STORE_O && qok) {
+        float *opp = pt_at<BF>(out, (size_t)(base + q) * 128 + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) stp4<BF>(op, 16 * ft, oacc[ft]);
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(opp, 16 * ft, oacc[ft]);
+      }
+      if constexpr (OP) {
+        // y = o W_O in the projection GEMM's order (feature chunk, step,
+        // column tile), then G_out = G_in + gamma LN(y + b) + beta
+        const size_t rb = (size_t)(base + (qok ? q : 0)) * kOpCols;
+        floatx4 gi[kOpTiles];
+#pragma unroll
+        for (int nt = 0; nt < kOpTiles; ++nt) gi[nt] = *(const floatx4 *)(op.gin + rb + 16 * nt + 4 * g);
+        floatx4 y[kOpTiles];
+#pragma unroll
+        for (int nt = 0; nt < kOpTiles; ++nt) y[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float *wl = wo + r * kLDR + 4 * g;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          floatx4 w[kOpTiles];
+#pragma unroll
+          for (int nt = 0; nt < kOpTiles; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * kLDR + 16 * c);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int nt = 0; nt < kOpTiles; ++nt) y[nt] = mfma4(w[nt][t], oacc[c][t], y[nt]);
+        }
+        lnres::apply_tile<kOpTiles>(y, gi, g, kOpTiles, op.Nreal, op.eps, cso, kOpCols, qok,
+                                    base + q, rb, op.gout, op.xhat, op.rstd);
       }
     }
     __syncthreads();  // LDS is restaged for the next centre
@@ -907,7 +953,7 @@ __device__ __forceinline__ float reduce16_transposed(float (&v)[16], int r) {
 
 template <int NPAD>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd_f(
-    const float *__restrict__ qkv, const float *__restrict__ o, const float *__restrict__ dO,
+    const float *__restrict__ qkv, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
     const int *__restrict__ nnei, const int *__restrict__ clist, const int *__restrict__ ccount,
     int sel, float shift, const float *__restrict__ lam, const float2 *__restrict__ fstat,
@@ -949,22 +995,13 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
     const int ntile = (n + 15) >> 4;
     const int q = wave * 16 + r;
     const bool qok = q < n;
-    floatx4 dov[8], ov[8];
+    floatx4 dov[8];
     load_rows<false>(dO, 0, 128, base, n, q, g, dov);
-    load_rows<false>(o, 0, 128, base, n, q, g, ov);
     stage_rows_store<NPAD>(buf, tid, n, sv);
     gate_store<NPAD>(kg, kw, tid, n, gv, gl);
     __syncthreads();
 
     // ---------------- phase Q: dA^T, dS, dQ, A and dS to LDS, both sides' sums
-    float dq = 0.f;
-    if (wave < ntile) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        dq += dov[c][0] * ov[c][0] + dov[c][1] * ov[c][1] + dov[c][2] * ov[c][2] +
-              dov[c][3] * ov[c][3];
-      dq = sum_groups(dq);
-    }
     float4 kpre[8];  // K, read while dA^T is formed
     stage_t_load<NPAD, false>(qkv, 128, ld, base, n, tid, kpre);
     floatx4 da[NT];
@@ -980,26 +1017,53 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
       const float2 fs = fstat[base + qr];
       const float m = fs.x, invz = fs.y;
       const float *lp = lam + (size_t)(base + qr) * kLamLd + 4 * g;
+      // pass 1: probabilities P (kept in registers) and logits lam (to Ds) of the
+      // query's row, and D_q = sum_k P H dA (= dO . o, without o)
+      float dq = 0.f;
+      floatx4 pk[NT];  // P of the query's row (pass 1 -> pass 2)
+      {
+        floatx4 lcur = *(const floatx4 *)lp, lnxt;
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) {
+          if (kt + 1 < NT) lnxt = *(const floatx4 *)(lp + 16 * (kt + 1));
+          floatx4 lv;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int k = kt * 16 + 4 * g + v;
+            const bool ok = qok && k < n;
+            const float4 gk = kg[k];
+            const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
+            const float lm = ok ? lcur[v] : 0.f;
+            const float l = logit64(lm, wqd, kw[k], shift);
+            const float p = ok ? exp_hw(l - m) * invz : 0.f;
+            dq += p * (wq * gk.w * c) * da[kt][v];
+            pk[kt][v] = p;
+            lv[v] = lm;
+          }
+          *(floatx4 *)(Ds + q * LDF + kt * 16 + 4 * g) = lv;
+          lcur = lnxt;
+        }
+        dq = sum_groups(dq);
+      }
       floatx4 dqacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
       float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
-      floatx4 lcur = *(const floatx4 *)lp, lnxt;
+      // pass 2: the softmax adjoint; A = P H and dS replace P and lam
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) {
-        if (kt + 1 < NT) lnxt = *(const floatx4 *)(lp + 16 * (kt + 1));
+        const floatx4 pv = pk[kt];
+        const floatx4 lv = *(const floatx4 *)(Ds + q * LDF + kt * 16 + 4 * g);
         floatx4 ds, at;
         float ks[16];  // key-side terms: X w_q, Y rhat_q (x, y, z) for the four keys
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = kt * 16 + 4 * g + v;
-          const bool ok = qok && k < n;
           const float4 gk = kg[k];
           const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
           const float ww = wq * gk.w;
-          const float lm = ok ? lcur[v] : 0.f;
-          const float l = logit64(lm, wqd, kw[k], shift);
-          const float p = ok ? exp_hw(l - m) * invz : 0.f;
+          const float lm = lv[v];
+          const float p = pv[v];
           const float h = ww * c;
           const float dH = da[kt][v] * p;
           const float dL = p * (da[kt][v] * h - dq);
@@ -1023,7 +1087,6 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
         const float kt_sum = reduce16_transposed(ks, r);
         ((float *)ksum)[(wave * NPAD + kt * 16 + 4 * g + (r & 3)) * 4 + (r >> 2)] = kt_sum;
         accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);  // dQ = dS K
-        lcur = lnxt;
       }
       dwq = sum_groups(dwq);
       drqx = sum_groups(drqx);
@@ -1356,9 +1419,10 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
 // slots; each class runs a kernel sized for it, over its own centre list, so
 // the common case does not pay for the largest LDS size and an empty class
 // costs one wave of exiting blocks.
-template <int NPAD>
+template <int NPAD, bool OP = false>
 size_t fwd_lds() {
-  return (sizeof(float4) + sizeof(double)) * NPAD + sizeof(float) * stage_floats<NPAD>();
+  return (sizeof(float4) + sizeof(double)) * NPAD + sizeof(float) * stage_floats<NPAD>() +
+         (OP ? sizeof(float) * (kOpCols * kLDR + 3 * kOpCols) : 0);
 }
 template <int NPAD>
 size_t bwdq_lds() {
@@ -1371,7 +1435,8 @@ size_t bwdk_lds() {
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.
 constexpr int kMaxDevices = 64;
-int g_grid[kMaxDevices][7][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16, fused FP32 adjoint
+int g_grid[kMaxDevices][8][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16; fused FP32
+                                // adjoint; FP32 forward with the output projection
 
 // Blocks of the grid of a class that held no centres in a recent step: an
 // empty launch of the full persistent grid costs ~20 us.
@@ -1399,7 +1464,7 @@ hipError_t prepare_class(int dev, int cus, int cls) {
   const int k0 = BF ? 3 : 0;  // grid table rows: fp32 fwd, bwd_q, bwd_k, then bf16
   hipError_t e = hipSuccess;
   if (NPAD > 64) {
-    e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD, BF>,
+    e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD, BF, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<NPAD>());
     if (e == hipSuccess)
       e = hipFuncSetAttribute((const void *)k_attn_bwd_q<NPAD, BF>,
@@ -1409,13 +1474,23 @@ hipError_t prepare_class(int dev, int cus, int cls) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdk_lds<NPAD>());
   }
   if (e == hipSuccess)
-    e = occupancy_grid(k_attn_fwd<NPAD, BF>, th, fwd_lds<NPAD>(), cus, &g_grid[dev][k0][cls]);
+    e = occupancy_grid(k_attn_fwd<NPAD, BF, false>, th, fwd_lds<NPAD>(), cus,
+                       &g_grid[dev][k0][cls]);
   if (e == hipSuccess)
     e = occupancy_grid(k_attn_bwd_q<NPAD, BF>, th, bwdq_lds<NPAD>(), cus,
                        &g_grid[dev][k0 + 1][cls]);
   if (e == hipSuccess)
     e = occupancy_grid(k_attn_bwd_k<NPAD, BF>, th, bwdk_lds<NPAD>(), cus,
                        &g_grid[dev][k0 + 2][cls]);
+  if constexpr (!BF) {
+    if (e == hipSuccess && fwd_lds<NPAD, true>() > 65536)
+      e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)fwd_lds<NPAD, true>());
+    if (e == hipSuccess)
+      e = occupancy_grid(k_attn_fwd<NPAD, false, true>, th, fwd_lds<NPAD, true>(), cus,
+                         &g_grid[dev][7][cls]);
+  }
   if constexpr (!BF && NPAD <= 96) {
     if (e == hipSuccess && bwdf_lds<NPAD>() > 65536)
       e = hipFuncSetAttribute((const void *)k_attn_bwd_f<NPAD>,
@@ -1474,13 +1549,22 @@ void launch_attn_classes(const int *nnei, int nloc, int active, int *ccount, int
   }
 
 void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *out, float *lam,
-                           float *fstat, hipStream_t s) {
+                           float *fstat, const AttnOut *op, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
+  if (op && !a.bf16) {
+    const dim3 grid(grid_for(6 + 1, cls, a.small));
+    ATTN_CLASS_SWITCH1(cls, hipLaunchKernelGGL((k_attn_fwd<NP, false, true>), grid,
+                                               dim3(NP / 16 * 64), (fwd_lds<NP, true>()), s, qkv,
+                                               a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift,
+                                               out, lam, (float2 *)fstat, *op));
+    return;
+  }
   const dim3 grid(grid_for(a.bf16 ? 3 : 0, cls, a.small));
-  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_fwd<NP, BFV>), grid, dim3(NP / 16 * 64),
+  ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_fwd<NP, BFV, false>), grid, dim3(NP / 16 * 64),
                                             fwd_lds<NP>(), s, qkv, a.geom, a.pair_off, a.nnei,
-                                            cl, cc, a.sel, a.shift, out, lam, (float2 *)fstat));
+                                            cl, cc, a.sel, a.shift, out, lam, (float2 *)fstat,
+                                            AttnOut{}));
 }
 
 void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
@@ -1498,16 +1582,15 @@ void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const
 
 bool attn_bwd_fused(const AttnArgs &a, int cls) { return !a.bf16 && cls <= 2; }
 
-void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
-                                 const float *dO, const float *lam, const float *fstat,
-                                 float *dqkv, float *gw, float *gr, int accumulate,
-                                 hipStream_t s) {
+void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
+                                 const float *lam, const float *fstat, float *dqkv, float *gw,
+                                 float *gr, int accumulate, hipStream_t s) {
   if (a.nloc <= 0 || !attn_bwd_fused(a, cls)) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
   const dim3 grid(grid_for(6, cls, a.small));
 #define ATTN_BWD_F(NP)                                                                         \
-  hipLaunchKernelGGL((k_attn_bwd_f<NP>), grid, dim3(NP / 16 * 64), bwdf_lds<NP>(), s, qkv, o, \
-                     dO, a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift, lam,              \
+  hipLaunchKernelGGL((k_attn_bwd_f<NP>), grid, dim3(NP / 16 * 64), bwdf_lds<NP>(), s, qkv, dO, \
+                     a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift, lam,                  \
                      (const float2 *)fstat, dqkv, gw, gr, accumulate)
   if (cls == 0) ATTN_BWD_F(32);
   else if (cls == 1) ATTN_BWD_F(64);

@@ -611,12 +611,21 @@ __global__ void k_bbox(const double *x, int n, double *out) {
 // timer names of the per-class attention launches (class c covers n in (32c, 32c + 32])
 const char *const kAttnFwdName[4] = {"attn_fwd_n32", "attn_fwd_n64", "attn_fwd_n96",
                                      "attn_fwd_n128"};
+const char *const kAttnFwdLnName[4] = {"attn_fwd_ln_n32", "attn_fwd_ln_n64", "attn_fwd_ln_n96",
+                                       "attn_fwd_ln_n128"};
 const char *const kAttnBwdQName[4] = {"attn_bwd_q_n32", "attn_bwd_q_n64", "attn_bwd_q_n96",
                                       "attn_bwd_q_n128"};
 const char *const kAttnBwdName[4] = {"attn_bwd_n32", "attn_bwd_n64", "attn_bwd_n96",
                                      "attn_bwd_n128"};
 const char *const kAttnBwdKName[4] = {"attn_bwd_k_n32", "attn_bwd_k_n64", "attn_bwd_k_n96",
                                       "attn_bwd_k_n128"};
+
+// The FP32 attention forward applies the output projection and layer norm
+// itself when the embedding width pads to kAttnOpCols columns and the
+// attention width is 128 (the shapes its kernel is built for).
+bool attn_fwd_fuses_projection(const dp_model *m) {
+  return !m->bf16 && m->ldM == kAttnOpCols && m->dattn == 128;
+}
 
 #define RUN(name, call)                                           \
   do {                                                            \
@@ -727,13 +736,19 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
     // in BF16 mode QKV, o, dO and dQKV are stored in BF16 (matrix-core operands only)
     GemmArgs g1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16, 0, m->M};
     RUN("qkv_fwd", gemm_linear(g1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
+    const AttnOut op{A.Wt_o, A.b_o,      A.gamma,   A.beta,    (float)m->ln_eps,
+                     w.G[a], w.G[a + 1], w.xhat[a], w.rstd[a], m->M};
+    const bool fuse_op = attn_fwd_fuses_projection(m);
     for (int cls = 0; cls < ncls; ++cls)
       if ((active >> cls) & 1)
-        RUN(kAttnFwdName[cls],
-            launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
-    GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
-    RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
-                                    w.G[a + 1], w.xhat[a], w.rstd[a], s));
+        RUN(fuse_op ? kAttnFwdLnName[cls] : kAttnFwdName[cls],
+            launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a],
+                                  fuse_op ? &op : nullptr, s));
+    if (!fuse_op) {
+      GemmArgs g2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
+      RUN("oproj_ln_fwd", gemm_ln_res(g2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a], ldM,
+                                      w.G[a + 1], w.xhat[a], w.rstd[a], s));
+    }
   }
   // descriptor and fitting
   RUN("desc_fwd", launch_desc_fwd(w.geom, w.G[na], ldM, w.pair_off, w.nnei, nloc, sel, m->M,
@@ -841,13 +856,19 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       // from its stored input G[a] (the same kernels, so the same values)
       GemmArgs r1{w.G[a], ldM, A.Wt_qkv, ldM, 3 * D, 3 * D, Pptr, Pmax, m->bf16, 0, m->M};
       RUN("qkv_fwd_recompute", gemm_linear(r1, A.b_qkv, w.qkv[a], 3 * D, s, m->bf16));
+      const AttnOut op{A.Wt_o, A.b_o,      A.gamma,   A.beta,    (float)m->ln_eps,
+                       w.G[a], w.G[a + 1], w.xhat[a], w.rstd[a], m->M};
+      const bool fuse_op = attn_fwd_fuses_projection(m);
       for (int cls = 0; cls < attn_class_count(sel); ++cls)
         if ((m->cls_active >> cls) & 1)
           RUN("attn_fwd_recompute",
-              launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a], s));
-      GemmArgs r2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
-      RUN("oproj_ln_recompute", gemm_ln_res(r2, A.b_o, A.gamma, A.beta, (float)m->ln_eps, w.G[a],
-                                            ldM, w.G[a + 1], w.xhat[a], w.rstd[a], s));
+              launch_attn_fwd_class(cls, aa, w.qkv[a], w.o[a], w.lam[a], w.fstat[a],
+                                    fuse_op ? &op : nullptr, s));
+      if (!fuse_op) {
+        GemmArgs r2{w.o[a], D, A.Wt_o, D, ldM, m->M, Pptr, Pmax, m->bf16, m->bf16};
+        RUN("oproj_ln_recompute", gemm_ln_res(r2, A.b_o, A.gamma, A.beta, (float)m->ln_eps,
+                                              w.G[a], ldM, w.G[a + 1], w.xhat[a], w.rstd[a], s));
+      }
       m->shared_layer = a;
     }
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16, 0, m->M};
@@ -855,8 +876,8 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       if (((m->cls_active >> cls) & 1) && attn_bwd_fused(aa, cls))
         RUN(kAttnBwdName[cls],
-          launch_attn_bwd_fused_class(cls, aa, w.qkv[a], w.o[a], w.dO, w.lam[a], w.fstat[a],
-                                      w.dqkv, w.gw, w.gr, a != na - 1, s));
+          launch_attn_bwd_fused_class(cls, aa, w.qkv[a], w.dO, w.lam[a], w.fstat[a], w.dqkv,
+                                      w.gw, w.gr, a != na - 1, s));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       if (((m->cls_active >> cls) & 1) && !attn_bwd_fused(aa, cls))
         RUN(kAttnBwdQName[cls],

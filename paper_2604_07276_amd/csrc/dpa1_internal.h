@@ -168,10 +168,26 @@ struct AttnArgs {
   // kept to a few blocks (any count is still processed, only more slowly)
   int small = 0;
 };
+// Output projection and layer norm of an attention layer, applied by the
+// FP32 forward itself: W_O^T [kAttnOpCols][128]; bias, gamma, beta with
+// kAttnOpCols entries (zeros past Nreal); gin, gout, xhat rows of
+// kAttnOpCols floats, rstd one per pair.
+constexpr int kAttnOpCols = 112;
+struct AttnOut {
+  const float *Wt_o, *bias, *gamma, *beta;
+  float eps;
+  const float *gin;
+  float *gout, *xhat, *rstd;
+  int Nreal;
+};
 // Forward: O = (P o H) V per centre; stores lam = QK^T/sqrt(d) per pair row
-// ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).
+// ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).  With op (FP32
+// only) it also applies the output projection and layer norm (gout, xhat,
+// rstd as the projection GEMM writes them) and stores O only for the
+// 128-neighbour class, whose two-kernel adjoint reads it; with op == nullptr
+// it stores O for every class.
 void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *out, float *lam,
-                           float *fstat, hipStream_t s);
+                           float *fstat, const AttnOut *op, hipStream_t s);
 // Backward, query tiles: dQ, (m, 1/Z, D_q) and the query-side gate/switch
 // gradients (astat, qside: per-pair float4 buffers read by the key-tile pass).
 // dA [P][kAttnLamLd]: dL/dA of every (query, key) pair of a centre, in the
@@ -187,12 +203,12 @@ void launch_attn_bwd_k_class(int cls, const AttnArgs &a, const float *qkv, const
                              hipStream_t s);
 // Both halves of the backward in one kernel (FP32, classes of up to 96
 // neighbours; attn_bwd_fused tells whether a class has it): the outputs of
-// the query-tile and key-tile passes without dA, astat and qside.
+// the query-tile and key-tile passes without dA, astat and qside, and
+// without reading O (D_q = sum_k A dA instead of dO . o).
 bool attn_bwd_fused(const AttnArgs &a, int cls);
-void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *o,
-                                 const float *dO, const float *lam, const float *fstat,
-                                 float *dqkv, float *gw, float *gr, int accumulate,
-                                 hipStream_t s);
+void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
+                                 const float *lam, const float *fstat, float *dqkv, float *gw,
+                                 float *gr, int accumulate, hipStream_t s);
 // Descriptor: T = R~^T G / sel (4 x M), D = T^T T[:, :axis] -> dmat [nloc x M*axis].
 void launch_desc_fwd(const float *geom, const float *G, int ldg, const int *pair_off,
                      const int *nnei, int nloc, int sel, int M, int axis, float *T, float *dmat,

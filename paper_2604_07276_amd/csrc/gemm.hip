@@ -16,6 +16,7 @@
 // transposed, Wt[n][k]); the k index of a 16-wide chunk is permuted
 // identically on both operands, which leaves the contraction unchanged.
 #include "dpa1_internal.h"
+#include "ln_res.h"
 
 namespace dpa1 {
 
@@ -678,8 +679,6 @@ struct EpiLNRes {
   __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
                                         int lane, int M, const float *cs) const {
     const int r = lane & 15, g = lane >> 4;
-    const float invn = 1.0f / (float)Nreal;
-    constexpr int CW = NT * 16;  // staged columns per vector
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = row0 + mt * 16 + r;
@@ -691,50 +690,8 @@ struct EpiLNRes {
         const int tile = nt < ntt ? nt : 0;
         gi[nt] = *(const floatx4 *)(gin + rb + tile * 16 + 4 * g);
       }
-      float s1 = 0.f;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const floatx4 b = *(const floatx4 *)(cs + nt * 16 + 4 * g);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int n = nt * 16 + 4 * g + v;
-          const bool in = nt < ntt && n < Nreal;
-          acc[mt][nt][v] = in ? acc[mt][nt][v] + b[v] : 0.f;
-          s1 += acc[mt][nt][v];
-        }
-      }
-      const float mean = row_sum16(s1) * invn;
-      float s2 = 0.f;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int n = nt * 16 + 4 * g + v;
-          const float c = acc[mt][nt][v] - mean;
-          s2 += (nt < ntt && n < Nreal) ? c * c : 0.f;
-        }
-      }
-      const float var = row_sum16(s2) * invn;
-      const float rs = 1.0f / sqrtf(var + eps);
-      if (!ok) continue;
-      if (g == 0) rstd[row] = rs;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        if (nt >= ntt) continue;
-        const int n0 = nt * 16 + 4 * g;
-        const floatx4 gm = *(const floatx4 *)(cs + CW + n0);
-        const floatx4 bt = *(const floatx4 *)(cs + 2 * CW + n0);
-        floatx4 go, xh;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool in = n0 + v < Nreal;
-          const float x = (acc[mt][nt][v] - mean) * rs;
-          xh[v] = in ? x : 0.f;
-          go[v] = in ? gi[nt][v] + gm[v] * x + bt[v] : 0.f;
-        }
-        *(floatx4 *)(gout + rb + n0) = go;
-        *(floatx4 *)(xhat + rb + n0) = xh;
-      }
+      lnres::apply_tile<NT>(acc[mt], gi, g, ntt, Nreal, eps, cs, NT * 16, ok, row, rb, gout,
+                            xhat, rstd);
     }
   }
 };
