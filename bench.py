@@ -105,27 +105,30 @@ def step_flop_total(flops: dict) -> float:
     return sum(fl for k, (fl, _) in flops.items() if not k.startswith(FUSED_VARIANTS))
 
 
-def byte_model(nnei: np.ndarray, shape) -> dict:
+def byte_model(nnei: np.ndarray, shape, bf16: bool = False) -> dict:
     """Algorithmic HBM bytes per step of the attention and projection kernels.
 
-    The FP32 inputs each kernel must read and the outputs it must write, at
-    the real widths (M = embedding width, d = attention width), once each;
-    the stored logits lam (n per query row) and softmax statistics are part
-    of the forward's output and the backward's input, and the probability
+    The inputs each kernel must read and the outputs it must write, at the
+    real widths (M = embedding width, d = attention width), once each; the
+    stored logits lam (n per query row) and softmax statistics are part of
+    the forward's output and the backward's input, and the probability
     adjoint dA (n per query row) part of the query-tile adjoint's output and
-    the key-tile adjoint's input (stored instead of formed a second time).  Returns
-    {kernel: (bytes per step, launches per step)}.
+    the key-tile adjoint's input (stored instead of formed a second time).
+    Elements are 4 bytes, except that with bf16 the four pair tensors the
+    BF16 mode stores in BF16 (QKV, the attention output o, dO and dQKV) take
+    2.  Returns {kernel: (bytes per step, launches per step)}.
     """
     P = float(nnei.sum())
     M, d, L = shape["M"], shape["dattn"], shape["n_attn"]
     f4 = 4.0
+    t = 2.0 if bf16 else 4.0  # bytes per element of QKV, o, dO, dQKV
     out = {
-        "qkv_fwd": (L * P * f4 * (M + 3 * d), L),
+        "qkv_fwd": (L * P * (f4 * M + t * 3 * d), L),
         # dQKV, the residual gradient and xhat (or the embedding's tanh) and
         # 1/std in; the gradient and the next layer's seed out
-        "qkv_bwd": (L * P * f4 * (3 * d + 2 * M + 1 + 2 * M), L),
-        "oproj_ln_fwd": (L * P * f4 * (d + M + 2 * M + 1), L),
-        "oproj_bwd": (L * P * f4 * (M + d), L),
+        "qkv_bwd": (L * P * (t * 3 * d + f4 * (2 * M + 1 + 2 * M)), L),
+        "oproj_ln_fwd": (L * P * (t * d + f4 * (M + 2 * M + 1)), L),
+        "oproj_bwd": (L * P * (f4 * M + t * d), L),
     }
     nn = nnei.astype(np.float64)
     for c, npad in enumerate((32, 64, 96, 128)):
@@ -133,13 +136,13 @@ def byte_model(nnei: np.ndarray, shape) -> dict:
         Pc = float(nn[sel_c].sum())
         n2c = float((nn[sel_c] ** 2).sum())
         # fwd: Q, K, V, gate (rhat, sw) in; o, lam, (m, 1/Z) out
-        out[f"attn_fwd_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + d + 2) + f4 * n2c), L)
+        out[f"attn_fwd_n{npad}"] = (L * (Pc * (t * (3 * d + d) + f4 * (4 + 2)) + f4 * n2c), L)
         # bwd_q: K, V, dO, o, gate, (m, 1/Z), lam in; dQ, (m, 1/Z, D_q), query
         # sums and the probability adjoint dA (n per query row) out
-        out[f"attn_bwd_q_n{npad}"] = (L * (Pc * f4 * (5 * d + 4 + 2 + 4 + 4) + 2 * f4 * n2c), L)
+        out[f"attn_bwd_q_n{npad}"] = (L * (Pc * (t * 5 * d + f4 * (4 + 2 + 4 + 4)) + 2 * f4 * n2c), L)
         # bwd_k: Q, dO, gate, stats, query sums, lam and dA in; dK, dV,
         # dE/dsw, dE/drhat out
-        out[f"attn_bwd_k_n{npad}"] = (L * (Pc * f4 * (2 * d + 4 + 4 + 4 + 2 * d + 4) + 2 * f4 * n2c), L)
+        out[f"attn_bwd_k_n{npad}"] = (L * (Pc * (t * 4 * d + f4 * (4 + 4 + 4 + 4)) + 2 * f4 * n2c), L)
         # fused adjoint: Q, K, V, dO, gate, (m, 1/Z), lam in; dQ, dK, dV,
         # dE/dsw, dE/drhat out
         out[f"attn_bwd_n{npad}"] = (L * (Pc * f4 * (4 * d + 4 + 2 + 3 * d + 4) + f4 * n2c), L)
@@ -474,8 +477,8 @@ def main():
         model.sync()
         kt16 = model.kernel_times()
         model.set_timing(False)
-        bf16_roof = roofline_block(kt16, flops, {}, {}, step_flops, bf16_ms,
-                                   BF16_MFMA_PEAK_TFLOPS, measured=False)
+        bf16_roof = roofline_block(kt16, flops, byte_model(nnei, shape, bf16=True), {},
+                                   step_flops, bf16_ms, BF16_MFMA_PEAK_TFLOPS, measured=False)
         del bf16_roof["geometry_kernels_hbm"]
     model.set_precision(binding.PREC_FP32)
 

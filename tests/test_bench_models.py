@@ -55,3 +55,20 @@ def test_fused_adjoint_bytes_drop_the_stored_intermediates():
     fused = sum(b[f"attn_bwd_n{c}"][0] for c in (32, 64, 96, 128))
     # dA, the statistics and the query sums no longer pass through memory
     assert fused < two
+
+
+def test_bf16_byte_model_halves_only_the_bf16_stored_tensors():
+    nn = _nnei(4)
+    b32 = bench.byte_model(nn, SHAPE)
+    b16 = bench.byte_model(nn, SHAPE, bf16=True)
+    L, d, M = SHAPE["n_attn"], SHAPE["dattn"], SHAPE["M"]
+    P = float(nn.sum())
+    # QKV written in BF16, X read in FP32
+    assert abs((b32["qkv_fwd"][0] - b16["qkv_fwd"][0]) - L * P * 2 * 3 * d) < 1e-6 * b32["qkv_fwd"][0]
+    # the projection adjoint reads dY (FP32) and writes dO (BF16)
+    assert abs((b32["oproj_bwd"][0] - b16["oproj_bwd"][0]) - L * P * 2 * d) < 1e-6 * b32["oproj_bwd"][0]
+    # logits and statistics stay FP32 in the attention kernels
+    for c in (32, 64, 96, 128):
+        assert b16[f"attn_fwd_n{c}"][0] < b32[f"attn_fwd_n{c}"][0] or b32[f"attn_fwd_n{c}"][0] == 0
+    assert bench.byte_model(nn, SHAPE)["qkv_bwd"][0] == b32["qkv_bwd"][0]
+    assert M == 100
