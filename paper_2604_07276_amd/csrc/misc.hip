@@ -164,25 +164,53 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ x, Ce
 
 // Fixed-order FP64 reductions of the energy and the virial, plus the FP64
 // copy of the atomic energies.
-__global__ __launch_bounds__(1024) void k_reduce(const float *__restrict__ e,
+__global__ __launch_bounds__(512) void k_reduce(const float *__restrict__ e,
                                                  const double *__restrict__ vir_part, int nloc,
                                                  double *__restrict__ energy,
                                                  double *__restrict__ virial,
                                                  double *__restrict__ atom_energy) {
   // energy == nullptr skips the energy, virial == nullptr the virial
-  __shared__ double red[10][16];
+  constexpr int T = 512, W = T / 64;
+  __shared__ double red[10][W];
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
   double acc[10];
   for (int c = 0; c < 10; ++c) acc[c] = 0.0;
-  for (int i = t; i < nloc; i += 1024) {
+  // four atoms per thread and pass, their loads issued before any is added
+  // (one load in flight per thread made the pass a chain of HBM latencies)
+  constexpr int U = 4;
+  for (int i0 = t; i0 < nloc; i0 += T * U) {
     if (energy) {
-      const double ei = (double)e[i];
-      acc[0] += ei;
-      if (atom_energy) atom_energy[i] = ei;
+      float ev[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + T * u;
+        ev[u] = i < nloc ? e[i] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + T * u;
+        acc[0] += (double)ev[u];
+        if (atom_energy && i < nloc) atom_energy[i] = (double)ev[u];
+      }
     }
-    if (virial)
-      for (int c = 0; c < 9; ++c) acc[1 + c] += vir_part[9 * (size_t)i + c];
+    if (virial) {
+      double vv[U][9];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + T * u < nloc ? i0 + T * u : 0;
+        const bool ok = i0 + T * u < nloc;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const double v = vir_part[9 * (size_t)i + c];
+          vv[u][c] = ok ? v : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[1 + c] += vv[u][c];
+    }
   }
   for (int c = 0; c < 10; ++c) {
     const double v = wave_sum(acc[c]);
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const float *__restrict__ e,
     double tot[10];
     for (int c = 0; c < 10; ++c) {
       tot[c] = 0.0;
-      for (int w = 0; w < 16; ++w) tot[c] += red[c][w];
+      for (int w = 0; w < W; ++w) tot[c] += red[c][w];
     }
     if (energy) energy[0] = tot[0];
     if (virial)
@@ -229,7 +257,7 @@ void launch_forces(const double *coords, CellGrid grid, int nloc, int nall, int 
 
 void launch_reduce(const float *e, const double *vir_part, int nloc, double *energy,
                    double *virial, double *atom_energy, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, e, vir_part, nloc, energy, virial,
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(512), 0, s, e, vir_part, nloc, energy, virial,
                      atom_energy);
 }
 
