@@ -79,29 +79,48 @@ __global__ void k_cell_bin(const double *__restrict__ x, int nall, CellGrid g,
 }
 
 // Single-block exclusive scan: out[0..n) exclusive prefix sums, out[n] total.
+// Thread t owns the contiguous chunk [t per, (t + 1) per); its loads are
+// issued eight at a time, and the chunk totals are scanned within each
+// wavefront with shuffles and across the sixteen wavefronts in LDS.
 __global__ __launch_bounds__(1024) void k_scan(const int *__restrict__ in, int n,
                                                int *__restrict__ out) {
-  __shared__ int part[1024];
+  __shared__ int wtot[16];
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const int per = (n + 1023) / 1024;
   const int b = t * per;
   const int e = min(b + per, n);
   int s = 0;
-  for (int k = b; k < e; ++k) s += in[k];
-  part[t] = s;
+  for (int k0 = b; k0 < e; k0 += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k0 + u < e ? in[k0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  // inclusive scan of the chunk totals within the wavefront
+  int inc = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wtot[wave] = inc;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  int before = 0;  // totals of the earlier wavefronts
+  for (int w = 0; w < wave; ++w) before += wtot[w];
+  int run = before + inc - s;  // exclusive prefix of this chunk
+  for (int k0 = b; k0 < e; k0 += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k0 + u < e ? in[k0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u < e) out[k0 + u] = run;
+      run += v[u];
+    }
   }
-  int run = part[t] - s;  // exclusive prefix of this chunk
-  for (int k = b; k < e; ++k) {
-    out[k] = run;
-    run += in[k];
-  }
-  if (t == 1023) out[n] = part[1023];
+  if (t == 1023) out[n] = before + inc;
 }
 
 __global__ void k_cell_fill(const int *__restrict__ atom_cell, int nall,
@@ -161,30 +180,53 @@ __global__ __launch_bounds__(kWave *kNlistWaves) void k_nlist(
   const int ny = dim_offsets(g, 1, cy, oy);
   const int nz = dim_offsets(g, 2, cz, oz);
   int count = 0;
-  for (int a = 0; a < nz; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nx; ++c) {
-        const int cell = (oz[a] * g.nc[1] + oy[b]) * g.nc[0] + ox[c];
-        const int beg = cell_start[cell];
-        const int end = cell_start[cell + 1];
-        for (int base = beg; base < end; base += kWave) {
-          const int idx = base + lane;
-          bool hit = false;
-          int j = -1;
-          if (idx < end) {
-            j = cell_atoms[idx];
-            if (j != k && (!ghost || j < nloc)) {
-              double d[3];
-              pair_vec(x, k, j, g, d);
-              hit = norm2(d) < rc2;
-            }
-          }
-          const unsigned long long m = __ballot(hit);
-          const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
-          if (hit && pos < kListCap) list[wave][pos] = j;
-          count += __popcll(m);
+  // candidates of the atom range [beg, end) of cell_atoms, 64 at a time
+  auto scan = [&](int beg, int end) {
+    for (int base = beg; base < end; base += kWave) {
+      const int idx = base + lane;
+      bool hit = false;
+      int j = -1;
+      if (idx < end) {
+        j = cell_atoms[idx];
+        if (j != k && (!ghost || j < nloc)) {
+          double d[3];
+          pair_vec(x, k, j, g, d);
+          hit = norm2(d) < rc2;
         }
       }
+      const unsigned long long m = __ballot(hit);
+      const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+      if (hit && pos < kListCap) list[wave][pos] = j;
+      count += __popcll(m);
+    }
+  };
+  // The cells of one (y, z) row are consecutive in the cell order, so their
+  // atoms are one contiguous range of cell_atoms unless the row wraps: the
+  // row's cells are visited in ascending index and merged while their atom
+  // ranges touch (a few passes of 64 candidates per row instead of one per
+  // cell; the list is sorted afterwards, so the visiting order is free).
+  for (int a = 0; a < nz; ++a)
+    for (int b = 0; b < ny; ++b) {
+      const int row = (oz[a] * g.nc[1] + oy[b]) * g.nc[0];
+      int cs[3];
+      for (int c = 0; c < nx; ++c) cs[c] = row + ox[c];
+      // ascending (at most three entries)
+      if (nx > 1 && cs[0] > cs[1]) { const int t = cs[0]; cs[0] = cs[1]; cs[1] = t; }
+      if (nx > 2 && cs[1] > cs[2]) { const int t = cs[1]; cs[1] = cs[2]; cs[2] = t; }
+      if (nx > 1 && cs[0] > cs[1]) { const int t = cs[0]; cs[0] = cs[1]; cs[1] = t; }
+      int beg = cell_start[cs[0]], end = cell_start[cs[0] + 1];
+      for (int c = 1; c < nx; ++c) {
+        const int cb = cell_start[cs[c]], ce = cell_start[cs[c] + 1];
+        if (cb == end) {
+          end = ce;
+        } else {
+          scan(beg, end);
+          beg = cb;
+          end = ce;
+        }
+      }
+      scan(beg, end);
+    }
   const int n = count < sel ? count : sel;
   if (count > sel) {
     if (lane == 0) {
