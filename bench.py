@@ -145,7 +145,7 @@ def byte_model(nnei: np.ndarray, shape, bf16: bool = False) -> dict:
         out[f"attn_bwd_k_n{npad}"] = (L * (Pc * (t * 4 * d + f4 * (4 + 4 + 4 + 4)) + 2 * f4 * n2c), L)
         # fused adjoint: Q, K, V, dO, gate, (m, 1/Z), lam in; dQ, dK, dV,
         # dE/dsw, dE/drhat out
-        out[f"attn_bwd_n{npad}"] = (L * (Pc * f4 * (4 * d + 4 + 2 + 3 * d + 4) + f4 * n2c), L)
+        out[f"attn_bwd_n{npad}"] = (L * (Pc * (t * (4 * d + 3 * d) + f4 * (4 + 2 + 4)) + f4 * n2c), L)
         # forward with the output projection: QKV, gate, residual row in;
         # logits, statistics, the layer output, xhat and 1/std out (and o
         # for the 128 class, whose adjoint reads it)

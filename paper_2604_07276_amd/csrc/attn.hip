@@ -951,7 +951,10 @@ __device__ __forceinline__ float reduce16_transposed(float (&v)[16], int r) {
   return v[0];
 }
 
-template <int NPAD>
+// BF: BF16 matrix-core operands (tiles taken in pairs, every class has an
+// even number) and BF16 storage of QKV, dO and dQKV, as in the two-kernel
+// form; LDS and the elementwise work stay FP32.
+template <int NPAD, bool BF>
 __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd_f(
     const float *__restrict__ qkv, const float *__restrict__ dO,
     const float *__restrict__ geom, const int *__restrict__ pair_off,
@@ -982,7 +985,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
     const int i0 = clist[blockIdx.x];
     n_nx = nnei[i0];
     base_nx = pair_off[i0];
-    stage_rows_load<NPAD, false>(qkv, 256, ld, base_nx, n_nx, tid, sv);  // V
+    stage_rows_load<NPAD, BF>(qkv, 256, ld, base_nx, n_nx, tid, sv);  // V
     gv = gate_load(geom, base_nx, n_nx, tid, gl);
   }
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
@@ -996,16 +999,16 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
     const int q = wave * 16 + r;
     const bool qok = q < n;
     floatx4 dov[8];
-    load_rows<false>(dO, 0, 128, base, n, q, g, dov);
+    load_rows<BF>(dO, 0, 128, base, n, q, g, dov);
     stage_rows_store<NPAD>(buf, tid, n, sv);
     gate_store<NPAD>(kg, kw, tid, n, gv, gl);
     __syncthreads();
 
     // ---------------- phase Q: dA^T, dS, dQ, A and dS to LDS, both sides' sums
     float4 kpre[8];  // K, read while dA^T is formed
-    stage_t_load<NPAD, false>(qkv, 128, ld, base, n, tid, kpre);
+    stage_t_load<NPAD, BF>(qkv, 128, ld, base, n, tid, kpre);
     floatx4 da[NT];
-    if (wave < ntile) qk_lds<NT, false>(buf, r, g, dov, da);  // lane: query r, keys 4g + v
+    if (wave < ntile) qk_lds<NT, BF>(buf, r, g, dov, da);  // lane: query r, keys 4g + v
     __syncthreads();
     stage_t_store<NPAD>(buf, tid, n, kpre);  // K^T
     __syncthreads();
@@ -1034,7 +1037,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
             const float4 gk = kg[k];
             const float c = gq.x * gk.x + gq.y * gk.y + gq.z * gk.z;
             const float lm = ok ? lcur[v] : 0.f;
-            const float l = logit64(lm, wqd, kw[k], shift);
+            const float l = BF ? (lm + shift) * (wq * gk.w) - shift : logit64(lm, wqd, kw[k], shift);
             const float p = ok ? exp_hw(l - m) * invz : 0.f;
             dq += p * (wq * gk.w * c) * da[kt][v];
             pk[kt][v] = p;
@@ -1049,6 +1052,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dqacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
       float dwq = 0.f, drqx = 0.f, drqy = 0.f, drqz = 0.f;
+      floatx4 dsp;  // BF16: dS of the even tile of a pair
       // pass 2: the softmax adjoint; A = P H and dS replace P and lam
 #pragma unroll
       for (int kt = 0; kt < NT; ++kt) {
@@ -1086,7 +1090,12 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
         // 4g + r % 4 of this tile
         const float kt_sum = reduce16_transposed(ks, r);
         ((float *)ksum)[(wave * NPAD + kt * 16 + 4 * g + (r & 3)) * 4 + (r >> 2)] = kt_sum;
-        accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);  // dQ = dS K
+        if constexpr (BF) {  // dQ = dS K, tiles taken in pairs
+          if (kt % 2 == 0) dsp = ds;
+          else accum_lds2<NPAD>(buf, kt - 1, r, g, dsp, ds, dqacc);
+        } else {
+          accum_lds<NPAD>(buf, kt, r, g, ds, dqacc);  // dQ = dS K
+        }
       }
       dwq = sum_groups(dwq);
       drqx = sum_groups(drqx);
@@ -1094,9 +1103,9 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
       drqz = sum_groups(drqz);
       if (g == 0 && qok) qside[q] = make_float4(dwq, drqx, drqy, drqz);
       if (qok) {
-        float *dp = dqkv + (size_t)(base + q) * ld + 4 * g;
+        float *dp = pt_at<BF>(dqkv, (size_t)(base + q) * ld + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dqacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(dp, 16 * ft, dqacc[ft]);
       }
     }
     __syncthreads();
@@ -1112,25 +1121,37 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
 
     // ---------------- phase K: dV = A^T dO, dK = dS^T Q, key-side sums
     float4 qpre[8];  // Q, read while dV is formed
-    stage_t_load<NPAD, false>(qkv, 0, ld, base, n, tid, qpre);
+    stage_t_load<NPAD, BF>(qkv, 0, ld, base, n, tid, qpre);
     const int kk = wave * 16 + r;
     const bool kok = kk < n;
     if (wave < ntile) {
       floatx4 dvacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dvacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      floatx4 atp;  // BF16: A^T of the even tile of a pair
 #pragma unroll
       for (int qt = 0; qt < NT; ++qt) {
-        if (qt >= ntile) continue;
+        if (qt >= ntile) {
+          // BF16: an unpaired last tile meets a zero partner
+          if constexpr (BF)
+            if (qt % 2 == 1 && qt - 1 < ntile)
+              accum_rows2(buf, qt - 1, r, g, atp, floatx4{0.f, 0.f, 0.f, 0.f}, dvacc);
+          continue;
+        }
         floatx4 at;  // lane: key r, queries 4g + v
 #pragma unroll
         for (int v = 0; v < 4; ++v) at[v] = As[(qt * 16 + 4 * g + v) * LDF + kk];
-        accum_rows(buf, qt, r, g, at, dvacc);
+        if constexpr (BF) {
+          if (qt % 2 == 0) atp = at;
+          else accum_rows2(buf, qt - 1, r, g, atp, at, dvacc);
+        } else {
+          accum_rows(buf, qt, r, g, at, dvacc);
+        }
       }
       if (kok) {
-        float *dp = dqkv + (size_t)(base + kk) * ld + 256 + 4 * g;
+        float *dp = pt_at<BF>(dqkv, (size_t)(base + kk) * ld + 256 + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dvacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(dp, 16 * ft, dvacc[ft]);
       }
     }
     __syncthreads();
@@ -1142,7 +1163,7 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
         const int inx = clist[itn];
         n_nx = nnei[inx];
         base_nx = pair_off[inx];
-        stage_rows_load<NPAD, false>(qkv, 256, ld, base_nx, n_nx, tid, sv);  // next V
+        stage_rows_load<NPAD, BF>(qkv, 256, ld, base_nx, n_nx, tid, sv);  // next V
         gv = gate_load(geom, base_nx, n_nx, tid, gl);
       }
     }
@@ -1150,18 +1171,36 @@ __global__ __launch_bounds__(NPAD / 16 * 64, NPAD <= 64 ? 2 : 1) void k_attn_bwd
       floatx4 dkacc[8];
 #pragma unroll
       for (int ft = 0; ft < 8; ++ft) dkacc[ft] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (BF) {
+        // tiles in pairs; dS of query tiles at or past ntile (not written for
+        // this centre) is zero
 #pragma unroll
-      for (int qt = 0; qt < NT; ++qt) {
-        if (qt >= ntile) continue;
-        floatx4 dsv;
+        for (int qt = 0; qt < NT; qt += 2) {
+          if (qt >= ntile) continue;
+          floatx4 d0, d1;
+          const bool ok1 = qt + 1 < ntile;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dsv[v] = Ds[(qt * 16 + 4 * g + v) * LDF + kk];
-        accum_lds<NPAD>(buf, qt, r, g, dsv, dkacc);
+          for (int v = 0; v < 4; ++v) {
+            d0[v] = Ds[(qt * 16 + 4 * g + v) * LDF + kk];
+            const float x1 = Ds[((qt + 1) * 16 + 4 * g + v) * LDF + kk];
+            d1[v] = ok1 ? x1 : 0.f;
+          }
+          accum_lds2<NPAD>(buf, qt, r, g, d0, d1, dkacc);
+        }
+      } else {
+#pragma unroll
+        for (int qt = 0; qt < NT; ++qt) {
+          if (qt >= ntile) continue;
+          floatx4 dsv;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dsv[v] = Ds[(qt * 16 + 4 * g + v) * LDF + kk];
+          accum_lds<NPAD>(buf, qt, r, g, dsv, dkacc);
+        }
       }
       if (kok) {
-        float *dp = dqkv + (size_t)(base + kk) * ld + 128 + 4 * g;
+        float *dp = pt_at<BF>(dqkv, (size_t)(base + kk) * ld + 128 + 4 * g);
 #pragma unroll
-        for (int ft = 0; ft < 8; ++ft) *(floatx4 *)(dp + 16 * ft) = dkacc[ft];
+        for (int ft = 0; ft < 8; ++ft) stp4<BF>(dp, 16 * ft, dkacc[ft]);
         if (g == 0) {
           float4 t = qside[kk];
           for (int w = 0; w < ntile; ++w) {
@@ -1435,8 +1474,9 @@ size_t bwdk_lds() {
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.
 constexpr int kMaxDevices = 64;
-int g_grid[kMaxDevices][8][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16; fused FP32
-                                // adjoint; FP32 forward with the output projection
+int g_grid[kMaxDevices][9][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16; fused FP32
+                                // adjoint; FP32 forward with the output projection; fused
+                                // BF16 adjoint
 
 // Blocks of the grid of a class that held no centres in a recent step: an
 // empty launch of the full persistent grid costs ~20 us.
@@ -1491,12 +1531,13 @@ hipError_t prepare_class(int dev, int cus, int cls) {
       e = occupancy_grid(k_attn_fwd<NPAD, false, true>, th, fwd_lds<NPAD, true>(), cus,
                          &g_grid[dev][7][cls]);
   }
-  if constexpr (!BF && NPAD <= 96) {
+  if constexpr (NPAD <= 96) {
     if (e == hipSuccess && bwdf_lds<NPAD>() > 65536)
-      e = hipFuncSetAttribute((const void *)k_attn_bwd_f<NPAD>,
+      e = hipFuncSetAttribute((const void *)k_attn_bwd_f<NPAD, BF>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwdf_lds<NPAD>());
     if (e == hipSuccess)
-      e = occupancy_grid(k_attn_bwd_f<NPAD>, th, bwdf_lds<NPAD>(), cus, &g_grid[dev][6][cls]);
+      e = occupancy_grid(k_attn_bwd_f<NPAD, BF>, th, bwdf_lds<NPAD>(), cus,
+                         &g_grid[dev][BF ? 8 : 6][cls]);
   }
   return e;
 }
@@ -1580,21 +1621,27 @@ void launch_attn_bwd_q_class(int cls, const AttnArgs &a, const float *qkv, const
                                             (float4 *)qside, dA));
 }
 
-bool attn_bwd_fused(const AttnArgs &a, int cls) { return !a.bf16 && cls <= 2; }
+bool attn_bwd_fused(const AttnArgs &, int cls) { return cls <= 2; }
 
 void launch_attn_bwd_fused_class(int cls, const AttnArgs &a, const float *qkv, const float *dO,
                                  const float *lam, const float *fstat, float *dqkv, float *gw,
                                  float *gr, int accumulate, hipStream_t s) {
   if (a.nloc <= 0 || !attn_bwd_fused(a, cls)) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  const dim3 grid(grid_for(6, cls, a.small));
-#define ATTN_BWD_F(NP)                                                                         \
-  hipLaunchKernelGGL((k_attn_bwd_f<NP>), grid, dim3(NP / 16 * 64), bwdf_lds<NP>(), s, qkv, dO, \
-                     a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift, lam,                  \
+  const dim3 grid(grid_for(a.bf16 ? 8 : 6, cls, a.small));
+#define ATTN_BWD_F(NP, BFV)                                                                    \
+  hipLaunchKernelGGL((k_attn_bwd_f<NP, BFV>), grid, dim3(NP / 16 * 64), bwdf_lds<NP>(), s, qkv, \
+                     dO, a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift, lam,              \
                      (const float2 *)fstat, dqkv, gw, gr, accumulate)
-  if (cls == 0) ATTN_BWD_F(32);
-  else if (cls == 1) ATTN_BWD_F(64);
-  else ATTN_BWD_F(96);
+  if (a.bf16) {
+    if (cls == 0) ATTN_BWD_F(32, true);
+    else if (cls == 1) ATTN_BWD_F(64, true);
+    else ATTN_BWD_F(96, true);
+  } else {
+    if (cls == 0) ATTN_BWD_F(32, false);
+    else if (cls == 1) ATTN_BWD_F(64, false);
+    else ATTN_BWD_F(96, false);
+  }
 #undef ATTN_BWD_F
 }
 
