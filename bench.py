@@ -150,7 +150,7 @@ def byte_model(nnei: np.ndarray, shape, bf16: bool = False) -> dict:
         # logits, statistics, the layer output, xhat and 1/std out (and o
         # for the 128 class, whose adjoint reads it)
         o_out = d if npad > 96 else 0
-        out[f"attn_fwd_ln_n{npad}"] = (L * (Pc * f4 * (3 * d + 4 + M + 2 + 2 * M + 1 + o_out)
+        out[f"attn_fwd_ln_n{npad}"] = (L * (Pc * (t * (3 * d + o_out) + f4 * (4 + M + 2 + 2 * M + 1))
                                             + f4 * n2c), L)
     return out
 

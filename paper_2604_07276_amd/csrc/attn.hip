@@ -402,12 +402,12 @@ constexpr int kLamLd = kAttnLamLd;
 constexpr int kOpCols = kAttnOpCols;   // output columns of the fused projection
 constexpr int kOpTiles = kOpCols / 16;
 
-// OP (FP32): the output projection and its layer norm are applied here
+// OP: the output projection and its layer norm are applied here
 // (W_O^T, 7 column tiles, staged in LDS once per workgroup; the epilogue is
 // the one the projection GEMM uses), so the attention output o goes to
 // memory only where the two-kernel adjoint of the 128 class reads it.
 template <int NPAD, bool BF, bool OP>
-__global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) : 2) void k_attn_fwd(
+__global__ __launch_bounds__(NPAD / 16 * 64, BF && !OP ? (NPAD <= 64 ? 4 : (NPAD <= 96 ? 3 : 2)) : 2) void k_attn_fwd(
     const float *__restrict__ qkv, const float *__restrict__ geom,
     const int *__restrict__ pair_off, const int *__restrict__ nnei,
     const int *__restrict__ clist, const int *__restrict__ ccount, int sel, float shift,
@@ -570,16 +570,33 @@ __global__ __launch_bounds__(NPAD / 16 * 64, BF ? (NPAD <= 64 ? 4 : (NPAD <= 96 
 #pragma unroll
         for (int nt = 0; nt < kOpTiles; ++nt) y[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         const float *wl = wo + r * kLDR + 4 * g;
+        if constexpr (BF) {
+          // feature chunks 2h and 2h + 1 in one 16x16x32 step
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          floatx4 w[kOpTiles];
+          for (int h = 0; h < 4; ++h) {
+            const bf16x8 ob = to_bf16x8(oacc[2 * h], oacc[2 * h + 1]);
+            bf16x8 w[kOpTiles];
 #pragma unroll
-          for (int nt = 0; nt < kOpTiles; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * kLDR + 16 * c);
-          __builtin_amdgcn_sched_barrier(0);
+            for (int nt = 0; nt < kOpTiles; ++nt)
+              w[nt] = to_bf16x8(*(const floatx4 *)(wl + nt * 16 * kLDR + 32 * h),
+                                *(const floatx4 *)(wl + nt * 16 * kLDR + 32 * h + 16));
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
+            for (int nt = 0; nt < kOpTiles; ++nt) y[nt] = mfma_bf16x2(w[nt], ob, y[nt]);
+          }
+        } else {
 #pragma unroll
-            for (int nt = 0; nt < kOpTiles; ++nt) y[nt] = mfma4(w[nt][t], oacc[c][t], y[nt]);
+          for (int c = 0; c < 8; ++c) {
+            floatx4 w[kOpTiles];
+#pragma unroll
+            for (int nt = 0; nt < kOpTiles; ++nt)
+              w[nt] = *(const floatx4 *)(wl + nt * 16 * kLDR + 16 * c);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int nt = 0; nt < kOpTiles; ++nt) y[nt] = mfma4(w[nt][t], oacc[c][t], y[nt]);
+          }
         }
         lnres::apply_tile<kOpTiles>(y, gi, g, kOpTiles, op.Nreal, op.eps, cso, kOpCols, qok,
                                     base + q, rb, op.gout, op.xhat, op.rstd);
@@ -1474,9 +1491,9 @@ size_t bwdk_lds() {
 
 // Persistent grid sizes: resident blocks per CU times CUs, per device.
 constexpr int kMaxDevices = 64;
-int g_grid[kMaxDevices][9][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16; fused FP32
-                                // adjoint; FP32 forward with the output projection; fused
-                                // BF16 adjoint
+int g_grid[kMaxDevices][10][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16; fused FP32
+                                 // adjoint; FP32 forward with the output projection; fused
+                                 // BF16 adjoint; BF16 forward with the output projection
 
 // Blocks of the grid of a class that held no centres in a recent step: an
 // empty launch of the full persistent grid costs ~20 us.
@@ -1522,15 +1539,12 @@ hipError_t prepare_class(int dev, int cus, int cls) {
   if (e == hipSuccess)
     e = occupancy_grid(k_attn_bwd_k<NPAD, BF>, th, bwdk_lds<NPAD>(), cus,
                        &g_grid[dev][k0 + 2][cls]);
-  if constexpr (!BF) {
-    if (e == hipSuccess && fwd_lds<NPAD, true>() > 65536)
-      e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD, false, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)fwd_lds<NPAD, true>());
-    if (e == hipSuccess)
-      e = occupancy_grid(k_attn_fwd<NPAD, false, true>, th, fwd_lds<NPAD, true>(), cus,
-                         &g_grid[dev][7][cls]);
-  }
+  if (e == hipSuccess && fwd_lds<NPAD, true>() > 65536)
+    e = hipFuncSetAttribute((const void *)k_attn_fwd<NPAD, BF, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_lds<NPAD, true>());
+  if (e == hipSuccess)
+    e = occupancy_grid(k_attn_fwd<NPAD, BF, true>, th, fwd_lds<NPAD, true>(), cus,
+                       &g_grid[dev][BF ? 9 : 7][cls]);
   if constexpr (NPAD <= 96) {
     if (e == hipSuccess && bwdf_lds<NPAD>() > 65536)
       e = hipFuncSetAttribute((const void *)k_attn_bwd_f<NPAD, BF>,
@@ -1593,12 +1607,12 @@ void launch_attn_fwd_class(int cls, const AttnArgs &a, const float *qkv, float *
                            float *fstat, const AttnOut *op, hipStream_t s) {
   if (a.nloc <= 0) return;
   const int *cl = a.clist + (size_t)cls * a.nloc, *cc = a.ccount + cls;
-  if (op && !a.bf16) {
-    const dim3 grid(grid_for(6 + 1, cls, a.small));
-    ATTN_CLASS_SWITCH1(cls, hipLaunchKernelGGL((k_attn_fwd<NP, false, true>), grid,
-                                               dim3(NP / 16 * 64), (fwd_lds<NP, true>()), s, qkv,
-                                               a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift,
-                                               out, lam, (float2 *)fstat, *op));
+  if (op) {
+    const dim3 grid(grid_for(a.bf16 ? 9 : 7, cls, a.small));
+    ATTN_CLASS_SWITCH(cls, hipLaunchKernelGGL((k_attn_fwd<NP, BFV, true>), grid,
+                                              dim3(NP / 16 * 64), (fwd_lds<NP, true>()), s, qkv,
+                                              a.geom, a.pair_off, a.nnei, cl, cc, a.sel, a.shift,
+                                              out, lam, (float2 *)fstat, *op));
     return;
   }
   const dim3 grid(grid_for(a.bf16 ? 3 : 0, cls, a.small));

@@ -620,11 +620,11 @@ const char *const kAttnBwdName[4] = {"attn_bwd_n32", "attn_bwd_n64", "attn_bwd_n
 const char *const kAttnBwdKName[4] = {"attn_bwd_k_n32", "attn_bwd_k_n64", "attn_bwd_k_n96",
                                       "attn_bwd_k_n128"};
 
-// The FP32 attention forward applies the output projection and layer norm
-// itself when the embedding width pads to kAttnOpCols columns and the
-// attention width is 128 (the shapes its kernel is built for).
+// The attention forward applies the output projection and layer norm itself
+// when the embedding width pads to kAttnOpCols columns and the attention
+// width is 128 (the shapes its kernel is built for).
 bool attn_fwd_fuses_projection(const dp_model *m) {
-  return !m->bf16 && m->ldM == kAttnOpCols && m->dattn == 128;
+  return m->ldM == kAttnOpCols && m->dattn == 128;
 }
 
 #define RUN(name, call)                                           \

@@ -169,7 +169,7 @@ struct AttnArgs {
   int small = 0;
 };
 // Output projection and layer norm of an attention layer, applied by the
-// FP32 forward itself: W_O^T [kAttnOpCols][128]; bias, gamma, beta with
+// forward itself (in BF16 mode with BF16 operands): W_O^T [kAttnOpCols][128]; bias, gamma, beta with
 // kAttnOpCols entries (zeros past Nreal); gin, gout, xhat rows of
 // kAttnOpCols floats, rstd one per pair.
 constexpr int kAttnOpCols = 112;
@@ -181,8 +181,8 @@ struct AttnOut {
   int Nreal;
 };
 // Forward: O = (P o H) V per centre; stores lam = QK^T/sqrt(d) per pair row
-// ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).  With op (FP32
-// only) it also applies the output projection and layer norm (gout, xhat,
+// ([P][kAttnLamLd]) and (m, 1/Z) per pair (fstat, float2).  With op it
+// also applies the output projection and layer norm (gout, xhat,
 // rstd as the projection GEMM writes them) and stores O only for the
 // 128-neighbour class, whose two-kernel adjoint reads it; with op == nullptr
 // it stores O for every class.
