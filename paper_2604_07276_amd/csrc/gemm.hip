@@ -532,6 +532,85 @@ __global__ __launch_bounds__(512, 1) void k_gemm_wres(GemmArgs a, Epi epi) {
   }
 }
 
+// FP32 product with several column blocks (the QKV projection: 24 tiles)
+// whose data fills only the first four columns of its last k chunk: the
+// whole W^T block (CB x NT x 16 rows of 16 (KCH - 1) + 4 staged columns,
+// 160 KB for 384 x 100) is resident in LDS for the launch, one
+// eight-wavefront workgroup per CU.  Each wavefront holds a 32-row tile of X
+// in registers and produces its CB column blocks one after the other, so X
+// is read from memory once instead of once per column block; the next row
+// tile is loaded while the current one is multiplied.  Tiles are taken in
+// wave-major order (the last round's tiles land on different CUs).
+template <int NT, int CB, int KCH, class Epi>
+__global__ __launch_bounds__(512, 1) void k_gemm_cols(GemmArgs a, Epi epi) {
+  static_assert(Epi::kCols == 1, "one staged column vector");
+  constexpr int MT = 2;
+  constexpr int KS = 16 * (KCH - 1) + 4;  // staged depth
+  constexpr int LDW = KS + 4;
+  constexpr int NC = CB * NT * 16;  // staged output columns
+  extern __shared__ float wsm[];    // [NC][LDW], then the column vector [NC]
+  const int M = a.Mptr ? *a.Mptr : a.Mmax;
+  for (int idx = threadIdx.x; idx < NC * (KS / 4); idx += blockDim.x) {
+    const int row = idx / (KS / 4), c4 = idx % (KS / 4);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < a.Npad) v = *(const float4 *)(a.Wt + (size_t)row * a.K + 4 * c4);
+    *(float4 *)(wsm + row * LDW + 4 * c4) = v;
+  }
+  float *cs = wsm + NC * LDW;
+  stage_cols<Epi, CB * NT>(epi, 0, a.Npad, cs);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  const int g = lane >> 4;
+  const int ntt = a.Npad / 16;
+  const int stride = gridDim.x * 8 * 16 * MT;  // rows between a wave's consecutive tiles
+  int row0 = (wave * gridDim.x + blockIdx.x) * 16 * MT;
+  floatx4 xr[MT][KCH], xn[MT][KCH];
+  if (row0 < M) load_x_tile<MT, KCH, 0, 1>(a, row0, M, r, g, xr);
+  for (; row0 < M; row0 += stride) {
+    if (row0 + stride < M) load_x_tile<MT, KCH, 0, 1>(a, row0 + stride, M, r, g, xn);
+#pragma unroll 1
+    for (int cb = 0; cb < CB; ++cb) {
+      floatx4 acc[MT][NT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const float *wb = wsm + (cb * NT * 16 + r) * LDW;
+#pragma unroll
+      for (int c = 0; c < KCH; ++c) {
+        if (c == KCH - 1) {
+          // one step: depth 16 c + g on both operands
+          const float *wt = wb + 16 * c + g;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const float wv = wt[nt * 16 * LDW];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv, xr[mt][c][0], acc[mt][nt]);
+          }
+          continue;
+        }
+        floatx4 w[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) w[nt] = *(const floatx4 *)(wb + nt * 16 * LDW + 16 * c + 4 * g);
+        __builtin_amdgcn_sched_barrier(0);  // one chunk of weights live at a time
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(w[nt][t], xr[mt][c][t], acc[mt][nt]);
+      }
+      epi.template apply<MT, NT>(acc, row0, cb * NT, ntt, lane, M, cs + cb * NT * 16);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int c = 0; c < KCH; ++c) xr[mt][c] = xn[mt][c];
+  }
+}
+
 // ------------------------------------------------------------------ epilogues
 //
 // Every epilogue issues all the global loads of a 16-row tile (clamped to
@@ -1000,6 +1079,33 @@ bool launch_wres(const GemmArgs &a, const Epi &e, hipStream_t s) {
   return true;
 }
 
+// One workgroup of eight wavefronts per CU (the grid never exceeds the CU
+// count).  Returns false when the weight block does not fit the device's LDS.
+template <class Epi, int NT, int CB, int KCH>
+bool launch_cols(const GemmArgs &a, const Epi &e, hipStream_t s) {
+  constexpr int KS = 16 * (KCH - 1) + 4, NC = CB * NT * 16;
+  static int ready[64];  // dynamic LDS limit: 0 unknown, -1 refused, else bytes
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  const size_t lds = sizeof(float) * ((size_t)NC * (KS + 4) + NC);
+  if (ready[dev] == 0) {
+    int maxl = 0;
+    ready[dev] = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                             hipSuccess &&
+                         hipFuncSetAttribute((const void *)k_gemm_cols<NT, CB, KCH, Epi>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             maxl) == hipSuccess
+                     ? maxl
+                     : -1;
+  }
+  if (ready[dev] < 0 || lds > (size_t)ready[dev]) return false;
+  const long tiles = (a.Mmax + 8L * 32 - 1) / (8L * 32);
+  const long gx = tiles < cu_count() ? tiles : cu_count();
+  if (gx <= 0) return true;
+  hipLaunchKernelGGL((k_gemm_cols<NT, CB, KCH, Epi>), dim3((unsigned)gx), dim3(512), lds, s, a, e);
+  return true;
+}
+
 template <class Epi, int NT, int KCH>
 void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
   constexpr int MT = 2;
@@ -1037,6 +1143,13 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
   // column blocks of at most four tiles: more wavefronts per SIMD to cover
   // the load latency of each k step (measured best against 1, 2 and 8)
   if (!full_rows && a.Mmax < 65536 && nt > 4) nt = 4;
+  // the FP32 QKV projection (384 output columns over a 100-wide embedding):
+  // the whole weight block resident, X read once
+  if constexpr (Epi::kLds == 1 && Epi::kCols == 1) {
+    if (a.Mmax >= 65536 && !a.bf16 && a.K == 112 && ntt == 24 && a.kreal > 96 &&
+        a.kreal <= 100 && launch_cols<Epi, 8, 3, 7>(a, e, s))
+      return;
+  }
   if constexpr (Epi::kLds != 0) {
     if (a.Mmax >= 65536 && (a.K == 112 || a.K == 128) && (nt == 7 || nt == 8)) {
       if (nt == 7 && a.K == 112) return launch_lds<Epi, 7, 7>(a, e, s);
