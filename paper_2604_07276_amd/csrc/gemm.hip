@@ -532,7 +532,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_wres(GemmArgs a, Epi epi) {
   }
 }
 
-// FP32 product with several column blocks (the QKV projection: 24 tiles)
+// Product with several column blocks (the QKV projection: 24 tiles)
 // whose data fills only the first four columns of its last k chunk: the
 // whole W^T block (CB x NT x 16 rows of 16 (KCH - 1) + 4 staged columns,
 // 160 KB for 384 x 100) is resident in LDS for the launch, one
@@ -541,7 +541,10 @@ __global__ __launch_bounds__(512, 1) void k_gemm_wres(GemmArgs a, Epi epi) {
 // is read from memory once instead of once per column block; the next row
 // tile is loaded while the current one is multiplied.  Tiles are taken in
 // wave-major order (the last round's tiles land on different CUs).
-template <int NT, int CB, int KCH, class Epi>
+// BF = 1: BF16 operands (X still FP32 in memory), chunks 2p and 2p + 1 in
+// one 16x16x32 step, the lone last chunk (four real columns, held by lane
+// group 0 only) paired with zeros.
+template <int NT, int CB, int KCH, class Epi, int BF>
 __global__ __launch_bounds__(512, 1) void k_gemm_cols(GemmArgs a, Epi epi) {
   static_assert(Epi::kCols == 1, "one staged column vector");
   constexpr int MT = 2;
@@ -566,6 +569,65 @@ __global__ __launch_bounds__(512, 1) void k_gemm_cols(GemmArgs a, Epi epi) {
   const int ntt = a.Npad / 16;
   const int stride = gridDim.x * 8 * 16 * MT;  // rows between a wave's consecutive tiles
   int row0 = (wave * gridDim.x + blockIdx.x) * 16 * MT;
+  if constexpr (BF != 0) {
+    constexpr int KP = (KCH + 1) / 2;
+    static_assert(KCH % 2 == 1, "the last chunk is the lone one");
+    floatx4 xn[MT][KCH];
+    bf16x8 xc[MT][KP];
+    const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto to_pairs = [&]() {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int p = 0; p < KP; ++p)
+          xc[mt][p] = to_bf16x8(xn[mt][2 * p], 2 * p + 1 < KCH ? xn[mt][2 * p + 1] : z);
+    };
+    if (row0 < M) {
+      load_x_tile<MT, KCH, 1, 4>(a, row0, M, r, g, xn);
+      to_pairs();
+    }
+    for (; row0 < M; row0 += stride) {
+      const bool next = row0 + stride < M;
+      if (next) load_x_tile<MT, KCH, 1, 4>(a, row0 + stride, M, r, g, xn);
+#pragma unroll 1
+      for (int cb = 0; cb < CB; ++cb) {
+        floatx4 acc[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = z;
+        const float *wb = wsm + (cb * NT * 16 + r) * LDW + 4 * g;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+          bf16x8 w[NT];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const float *wp = wb + nt * 16 * LDW + 32 * p;
+            floatx4 w0, w1;
+            if (2 * p + 1 < KCH) {
+              w0 = *(const floatx4 *)wp;
+              w1 = *(const floatx4 *)(wp + 16);
+            } else {
+              // last chunk: staged columns 16 (KCH - 1) .. + 3 only (lane
+              // group 0); the other groups read group 0's address
+              const floatx4 v = *(const floatx4 *)(wp - 4 * g);
+              w0 = g == 0 ? v : z;
+              w1 = z;
+            }
+            w[nt] = to_bf16x8(w0, w1);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16x2(w[nt], xc[mt][p], acc[mt][nt]);
+        }
+        epi.template apply<MT, NT>(acc, row0, cb * NT, ntt, lane, M, cs + cb * NT * 16);
+      }
+      if (next) to_pairs();
+    }
+    return;
+  }
   floatx4 xr[MT][KCH], xn[MT][KCH];
   if (row0 < M) load_x_tile<MT, KCH, 0, 1>(a, row0, M, r, g, xr);
   for (; row0 < M; row0 += stride) {
@@ -1081,7 +1143,7 @@ bool launch_wres(const GemmArgs &a, const Epi &e, hipStream_t s) {
 
 // One workgroup of eight wavefronts per CU (the grid never exceeds the CU
 // count).  Returns false when the weight block does not fit the device's LDS.
-template <class Epi, int NT, int CB, int KCH>
+template <class Epi, int NT, int CB, int KCH, int BF>
 bool launch_cols(const GemmArgs &a, const Epi &e, hipStream_t s) {
   constexpr int KS = 16 * (KCH - 1) + 4, NC = CB * NT * 16;
   static int ready[64];  // dynamic LDS limit: 0 unknown, -1 refused, else bytes
@@ -1092,7 +1154,7 @@ bool launch_cols(const GemmArgs &a, const Epi &e, hipStream_t s) {
     int maxl = 0;
     ready[dev] = hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
                              hipSuccess &&
-                         hipFuncSetAttribute((const void *)k_gemm_cols<NT, CB, KCH, Epi>,
+                         hipFuncSetAttribute((const void *)k_gemm_cols<NT, CB, KCH, Epi, BF>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              maxl) == hipSuccess
                      ? maxl
@@ -1102,7 +1164,8 @@ bool launch_cols(const GemmArgs &a, const Epi &e, hipStream_t s) {
   const long tiles = (a.Mmax + 8L * 32 - 1) / (8L * 32);
   const long gx = tiles < cu_count() ? tiles : cu_count();
   if (gx <= 0) return true;
-  hipLaunchKernelGGL((k_gemm_cols<NT, CB, KCH, Epi>), dim3((unsigned)gx), dim3(512), lds, s, a, e);
+  hipLaunchKernelGGL((k_gemm_cols<NT, CB, KCH, Epi, BF>), dim3((unsigned)gx), dim3(512), lds, s,
+                     a, e);
   return true;
 }
 
@@ -1146,8 +1209,9 @@ void run(const GemmArgs &a, const Epi &e, bool full_rows, hipStream_t s) {
   // the FP32 QKV projection (384 output columns over a 100-wide embedding):
   // the whole weight block resident, X read once
   if constexpr (Epi::kLds == 1 && Epi::kCols == 1) {
-    if (a.Mmax >= 65536 && !a.bf16 && a.K == 112 && ntt == 24 && a.kreal > 96 &&
-        a.kreal <= 100 && launch_cols<Epi, 8, 3, 7>(a, e, s))
+    if (a.Mmax >= 65536 && !(a.bf16 && a.xbf16) && a.K == 112 && ntt == 24 && a.kreal > 96 &&
+        a.kreal <= 100 &&
+        (a.bf16 ? launch_cols<Epi, 8, 3, 7, 1>(a, e, s) : launch_cols<Epi, 8, 3, 7, 0>(a, e, s)))
       return;
   }
   if constexpr (Epi::kLds != 0) {
