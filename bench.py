@@ -84,6 +84,9 @@ def flop_model(nnei: np.ndarray, shape) -> dict:
         # the FP32 forward with the output projection: Q K^T, A V and o W_O
         Pc = float(nn[sel_c].sum())
         out[f"attn_fwd_ln_n{npad}"] = (L * (2.0 * 2 * d * n2c + 2.0 * d * M * Pc), L)
+    # the descriptor adjoint fused with the last layer's projection adjoint
+    if L > 0:
+        out["desc_oproj_bwd"] = (out["desc_bwd"][0] + out["oproj_bwd"][0] / L, 1)
     return out
 
 
@@ -94,9 +97,10 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 
 
 # kernels that do the work of several entries of flop_model at once (the
-# fused attention forward and adjoints); the step's algorithmic total counts
-# that work once, through the entries of the separate kernels
-FUSED_VARIANTS = ("attn_bwd_n", "attn_fwd_ln_n")
+# fused attention forward and adjoints, the descriptor adjoint with the last
+# projection adjoint); the step's algorithmic total counts that work once,
+# through the entries of the separate kernels
+FUSED_VARIANTS = ("attn_bwd_n", "attn_fwd_ln_n", "desc_oproj_bwd")
 
 
 def step_flop_total(flops: dict) -> float:

@@ -1471,6 +1471,277 @@ __global__ __launch_bounds__(256) void k_desc_bwd(
   }
 }
 
+// The descriptor adjoint fused with the adjoint of the last attention
+// layer's output projection (Sec. II-B, DPA-1).  Per centre dT is formed as
+// in k_desc_bwd; then each wavefront takes 16-neighbour tiles and forms, per
+// pair, the residual-path gradient dG = R~ dT / sel, dR~ = dT G / sel, the
+// layer-norm adjoint d(acc) of the pre-norm projection output, and finally
+// dO = d(acc) W_O^T on the matrix cores with W_O^T resident in LDS.  d(acc)
+// is produced in registers already in the operand layout of that product
+// (lane l: pair l % 16, features 16 c + 4 (l / 16) + {0..3}), so it never
+// reaches memory.  Blocks walk over centres (persistent grid), so W_O^T is
+// staged once per workgroup.
+//
+// Shape: ldg = 112 (seven 16-feature chunks) and 96 < M <= 100, so the last
+// chunk holds M - 96 real features: lane group g carries feature 96 + g of
+// it, in one matrix-core step of depth four (FP32) or in the first operand
+// slot of the last chunk pair (BF16).
+constexpr int kDoN = 128;            // attention width: rows of W_O^T, columns of dO
+constexpr int kDoK = 112;            // padded feature width of G
+constexpr int kDoLdw = kDoK + 4;     // LDS row stride of W_O^T
+constexpr int kDoDs = 17;            // LDS row stride of a centre's dD (axis <= 16)
+constexpr int kDoLds = kDoN * kDoLdw + 4 * 128 * 2 + 16 * 16 * 4 + 128 + 1712;  // floats
+
+struct DescOprojArgs {
+  const float *geom, *G, *T, *dD;
+  const int *pair_off, *nnei;
+  int nloc, sel, M, axis, ldd;
+  const float *gamma, *xhat, *rstd;
+  const float *Wt;  // [kDoN][kDoK]: W_O^T of the last attention layer
+  float *dG, *dRt;
+  float *dO;        // [pairs][kDoN]: FP32, or BF16 (rounded to nearest even) when BF
+};
+
+template <bool BF>
+__global__ __launch_bounds__(256, 2) void k_desc_oproj_bwd(DescOprojArgs a) {
+  extern __shared__ float sm[];
+  float *wsm = sm;                        // [kDoN][kDoLdw]
+  float *Ts = wsm + kDoN * kDoLdw;        // [4][128]
+  float *dTs = Ts + 4 * 128;              // [4][128]
+  float *part = dTs + 4 * 128;            // [16][16][4]
+  float *gam = part + 16 * 16 * 4;        // [128], zeros past M
+  float *dDs = gam + 128;                 // [M][kDoDs]: the centre's dD
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int M = a.M, axis = a.axis;
+  for (int idx = tid; idx < kDoN * (kDoK / 4); idx += 256) {
+    const int n = idx / (kDoK / 4), c4 = idx % (kDoK / 4);
+    *(float4 *)(wsm + n * kDoLdw + 4 * c4) = *(const float4 *)(a.Wt + (size_t)n * kDoK + 4 * c4);
+  }
+  if (tid < 128) gam[tid] = tid < M ? a.gamma[tid] : 0.f;
+  const float inv = 1.0f / (float)a.sel;
+  const float invm = 1.0f / (float)M;
+  const int f6 = 96 + g;                  // this lane's feature of the last chunk
+  const bool in6 = f6 < M;
+  // A centre's dD row (ldd <= 512 float4) and T column tid arrive in
+  // registers one centre ahead (issued while the current centre's tiles run)
+  // and are then staged in LDS.
+  const int nq = a.ldd >> 2;
+  float4 dq[2];
+  float tq[4];
+  auto fetch = [&](int i) {
+    const float4 *src = (const float4 *)(a.dD + (size_t)i * a.ldd);
+    dq[0] = src[tid < nq ? tid : 0];
+    dq[1] = src[tid + 256 < nq ? tid + 256 : 0];
+    const float *tp = a.T + (size_t)i * 4 * M + (tid < M ? tid : 0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tq[c] = tp[c * M];
+  };
+  // One tile's pair rows (rows past n read the centre's first pair).  A
+  // wavefront issues its first tile of a centre before the centre's dT is
+  // formed and each next tile while the current one is on the matrix cores.
+  floatx4 gv[6], xv[6];
+  float g6, x6, rs;
+  float4 gq;
+  auto load_tile = [&](int t, int base, int n) {
+    const int j = 16 * t + r;
+    const size_t p = (size_t)base + (j < n ? j : 0);
+    gq = *(const float4 *)(a.geom + p * kGeom);  // s, rx, ry, rz
+    rs = a.rstd[p];
+    const float *gp = a.G + p * kDoK + 4 * g;
+    const float *xp = a.xhat + p * kDoK + 4 * g;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      gv[c] = *(const floatx4 *)(gp + 16 * c);
+      xv[c] = *(const floatx4 *)(xp + 16 * c);
+    }
+    g6 = a.G[p * kDoK + f6];
+    x6 = a.xhat[p * kDoK + f6];
+  };
+  if (blockIdx.x < a.nloc) fetch(blockIdx.x);
+  for (int i = blockIdx.x; i < a.nloc; i += gridDim.x) {
+    const int n = a.nnei[i];
+    const int base = a.pair_off[i];
+    const int ntile = (n + 15) >> 4;
+    if (wave < ntile) load_tile(wave, base, n);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = tid + 256 * k;
+      if (q < nq) {
+        const float v4[4] = {dq[k].x, dq[k].y, dq[k].z, dq[k].w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int e = 4 * q + v, m = e / axis;
+          if (m < M) dDs[m * kDoDs + (e - m * axis)] = v4[v];
+        }
+      }
+    }
+    if (tid < 128)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Ts[c * 128 + tid] = tid < M ? tq[c] : 0.f;
+    __syncthreads();  // also: every wavefront is done with the previous centre's dTs
+    if (i + (int)gridDim.x < a.nloc) fetch(i + gridDim.x);
+    {
+      const int aa = tid & 15, pp = tid >> 4;
+      float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+      if (aa < axis) {
+        for (int mm = pp; mm < M; mm += 16) {
+          const float x = dDs[mm * kDoDs + aa];
+          q0 += x * Ts[0 * 128 + mm];
+          q1 += x * Ts[1 * 128 + mm];
+          q2 += x * Ts[2 * 128 + mm];
+          q3 += x * Ts[3 * 128 + mm];
+        }
+      }
+      *(float4 *)(part + (pp * 16 + aa) * 4) = make_float4(q0, q1, q2, q3);
+    }
+    __syncthreads();
+    if (tid < 128) {
+      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      if (tid < M) {
+        for (int c = 0; c < axis; ++c) {
+          const float x = dDs[tid * kDoDs + c];
+          d0 += x * Ts[0 * 128 + c];
+          d1 += x * Ts[1 * 128 + c];
+          d2 += x * Ts[2 * 128 + c];
+          d3 += x * Ts[3 * 128 + c];
+        }
+        if (tid < axis && tid < 16) {
+          for (int pp = 0; pp < 16; ++pp) {
+            const float4 q = *(const float4 *)(part + (pp * 16 + tid) * 4);
+            d0 += q.x;
+            d1 += q.y;
+            d2 += q.z;
+            d3 += q.w;
+          }
+        }
+      }
+      dTs[0 * 128 + tid] = d0 * inv;
+      dTs[1 * 128 + tid] = d1 * inv;
+      dTs[2 * 128 + tid] = d2 * inv;
+      dTs[3 * 128 + tid] = d3 * inv;
+    }
+    __syncthreads();
+    for (int t = wave; t < ntile; t += 4) {
+      const int j = 16 * t + r;
+      const bool ok = j < n;
+      const size_t p = (size_t)base + (ok ? j : 0);
+      const float R0 = gq.x, R1 = gq.x * gq.y, R2 = gq.x * gq.z, R3 = gq.x * gq.w;
+      floatx4 dy[6];
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int f = 16 * c + 4 * g;
+        const floatx4 t0 = *(const floatx4 *)(dTs + 0 * 128 + f);
+        const floatx4 t1 = *(const floatx4 *)(dTs + 1 * 128 + f);
+        const floatx4 t2 = *(const floatx4 *)(dTs + 2 * 128 + f);
+        const floatx4 t3 = *(const floatx4 *)(dTs + 3 * 128 + f);
+        const floatx4 gm = *(const floatx4 *)(gam + f);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          dy[c][v] = R0 * t0[v] + R1 * t1[v] + R2 * t2[v] + R3 * t3[v];
+          a0 += gv[c][v] * t0[v];
+          a1 += gv[c][v] * t1[v];
+          a2 += gv[c][v] * t2[v];
+          a3 += gv[c][v] * t3[v];
+          const float dx = gm[v] * dy[c][v];
+          s1 += dx;
+          s2 += dx * xv[c][v];
+        }
+      }
+      float dy6;
+      {
+        const float t0 = dTs[0 * 128 + f6], t1 = dTs[1 * 128 + f6];
+        const float t2 = dTs[2 * 128 + f6], t3 = dTs[3 * 128 + f6];
+        const float gmv = in6 ? g6 : 0.f;
+        dy6 = in6 ? R0 * t0 + R1 * t1 + R2 * t2 + R3 * t3 : 0.f;
+        a0 += gmv * t0;
+        a1 += gmv * t1;
+        a2 += gmv * t2;
+        a3 += gmv * t3;
+        const float dx = gam[f6] * dy6;
+        s1 += dx;
+        s2 += in6 ? dx * x6 : 0.f;
+      }
+      a0 = sum_groups(a0);
+      a1 = sum_groups(a1);
+      a2 = sum_groups(a2);
+      a3 = sum_groups(a3);
+      s1 = sum_groups(s1);
+      s2 = sum_groups(s2);
+      if (ok) {
+        float *dgp = a.dG + p * kDoK;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) *(floatx4 *)(dgp + 16 * c + 4 * g) = dy[c];
+        dgp[f6] = dy6;
+        if (g > 0) *(floatx4 *)(dgp + 96 + 4 * g) = floatx4{0.f, 0.f, 0.f, 0.f};  // 100..111
+        if (g == 0) *(float4 *)(a.dRt + 4 * p) = make_float4(a0, a1, a2, a3);
+      }
+      // layer-norm adjoint, in place of dy
+      const float m1 = s1 * invm, m2 = s2 * invm;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const floatx4 gm = *(const floatx4 *)(gam + 16 * c + 4 * g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dy[c][v] = rs * (gm[v] * dy[c][v] - m1 - xv[c][v] * m2);
+      }
+      const float x6a = in6 ? rs * (gam[f6] * dy6 - m1 - x6 * m2) : 0.f;
+      if (t + 4 < ntile) load_tile(t + 4, base, n);
+      floatx4 acc[8];
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      // the weight offsets are laundered per tile so that the compiler does
+      // not hoist all of W_O^T into registers across tiles
+      int woff = r * kDoLdw + 4 * g, w6off = r * kDoLdw + f6;
+      asm volatile("" : "+v"(woff), "+v"(w6off));
+      const float *wl = wsm + woff;
+      if constexpr (BF) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const bf16x8 xb = to_bf16x8(dy[2 * q], dy[2 * q + 1]);
+#pragma unroll
+          for (int nt = 0; nt < 8; ++nt) {
+            const floatx4 w0 = *(const floatx4 *)(wl + nt * 16 * kDoLdw + 32 * q);
+            const floatx4 w1 = *(const floatx4 *)(wl + nt * 16 * kDoLdw + 32 * q + 16);
+            acc[nt] = mfma_bf16x2(to_bf16x8(w0, w1), xb, acc[nt]);
+          }
+        }
+        const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+        const bf16x8 xb = to_bf16x8(floatx4{x6a, 0.f, 0.f, 0.f}, z);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+          const float w6 = wsm[w6off + nt * 16 * kDoLdw];
+          acc[nt] = mfma_bf16x2(to_bf16x8(floatx4{w6, 0.f, 0.f, 0.f}, z), xb, acc[nt]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          floatx4 w[8];
+#pragma unroll
+          for (int nt = 0; nt < 8; ++nt) w[nt] = *(const floatx4 *)(wl + nt * 16 * kDoLdw + 16 * c);
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int nt = 0; nt < 8; ++nt) acc[nt] = mfma4(w[nt][v], dy[c][v], acc[nt]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+          acc[nt] = mfma4(wsm[w6off + nt * 16 * kDoLdw], x6a, acc[nt]);
+      }
+      if (ok) {
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+          const size_t o = p * kDoN + nt * 16 + 4 * g;
+          if constexpr (BF)
+            *(bf16x4 *)((__bf16 *)a.dO + o) = to_bf16(acc[nt]);
+          else
+            *(floatx4 *)(a.dO + o) = acc[nt];
+        }
+      }
+    }
+  }
+}
+
 // Centres are grouped by neighbour count into classes of 32, 64, 96 and 128
 // slots; each class runs a kernel sized for it, over its own centre list, so
 // the common case does not pay for the largest LDS size and an empty class
@@ -1494,6 +1765,8 @@ constexpr int kMaxDevices = 64;
 int g_grid[kMaxDevices][10][4];  // fwd, bwd_q, bwd_k in FP32, then in BF16; fused FP32
                                  // adjoint; FP32 forward with the output projection; fused
                                  // BF16 adjoint; BF16 forward with the output projection
+
+int g_desc_grid[kMaxDevices][2];  // fused descriptor / projection adjoint: FP32, BF16
 
 // Blocks of the grid of a class that held no centres in a recent step: an
 // empty launch of the full persistent grid costs ~20 us.
@@ -1576,6 +1849,17 @@ hipError_t attn_prepare() {
   if (e == hipSuccess) e = prepare_class<64, true>(dev, cus, 1);
   if (e == hipSuccess) e = prepare_class<96, true>(dev, cus, 2);
   if (e == hipSuccess) e = prepare_class<128, true>(dev, cus, 3);
+  const int lds = (int)(sizeof(float) * kDoLds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_desc_oproj_bwd<false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_desc_oproj_bwd<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = occupancy_grid(k_desc_oproj_bwd<false>, 256, lds, cus, &g_desc_grid[dev][0]);
+  if (e == hipSuccess)
+    e = occupancy_grid(k_desc_oproj_bwd<true>, 256, lds, cus, &g_desc_grid[dev][1]);
   return e;
 }
 
@@ -1711,6 +1995,31 @@ void launch_desc_bwd(const float *geom, const float *G, int ldg, const float *T,
       DESC_BWD(8, 2);
   }
 #undef DESC_BWD
+}
+
+bool desc_oproj_fusable(int ldg, int M, int axis, int D) {
+  return ldg == kDoK && M > 96 && M <= 100 && axis >= 1 && axis <= 16 && D == kDoN;
+}
+
+void launch_desc_oproj_bwd(const float *geom, const float *G, const float *T, const float *dD,
+                           const int *pair_off, const int *nnei, int nloc, int sel, int M,
+                           int axis, const float *gamma, const float *xhat, const float *rstd,
+                           const float *Wt, float *dG, float *dRt, float *dO, int bf16,
+                           hipStream_t s) {
+  if (nloc <= 0) return;
+  const DescOprojArgs a{geom, G,     T,         dD,   pair_off, nnei, nloc, sel,
+                        M,    axis,  pad16(M * axis), gamma, xhat, rstd, Wt,  dG,
+                        dRt,  dO};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  int grid = g_desc_grid[dev][bf16 ? 1 : 0];
+  if (grid <= 0) grid = 512;
+  if (grid > nloc) grid = nloc;
+  const size_t lds = sizeof(float) * kDoLds;
+  if (bf16)
+    hipLaunchKernelGGL(k_desc_oproj_bwd<true>, dim3(grid), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_desc_oproj_bwd<false>, dim3(grid), dim3(256), lds, s, a);
 }
 
 }  // namespace dpa1

@@ -831,7 +831,14 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
   // (the fused embedding adjoint takes no seed buffer: the modes that would
   // write one are not used then)
   float *emb_du_top = emb_fused ? w.dY : w.du[ne - 1];
-  {
+  const bool desc_fused = na > 0 && desc_oproj_fusable(ldM, m->M, m->axis, D);
+  if (desc_fused) {
+    const auto &A = m->attn[na - 1];
+    RUN("desc_oproj_bwd",
+        launch_desc_oproj_bwd(w.geom, w.G[na], w.T, w.dD, w.pair_off, w.nnei, nloc, sel, m->M,
+                              m->axis, A.gamma, w.xhat[na - 1], w.rstd[na - 1], A.Wb_o, dG_cur,
+                              w.dRt, w.dO, m->bf16, s));
+  } else {
     const int ln_mode = na > 0 ? 0 : (emb_fused ? 2 : 1);
     const float *gam = na > 0 ? m->attn[na - 1].gamma : nullptr;
     const float *xh = na > 0 ? w.xhat[na - 1] : nullptr;
@@ -872,7 +879,8 @@ int enqueue_backward(dp_model *m, const double *wgt, double sign, double *d_out,
       m->shared_layer = a;
     }
     GemmArgs g1{w.dY, ldM, A.Wb_o, ldM, D, D, Pptr, Pmax, m->bf16, 0, m->M};
-    RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s, m->bf16));
+    if (!(desc_fused && a == na - 1))  // else dO came with the descriptor adjoint
+      RUN("oproj_bwd", gemm_linear(g1, nullptr, w.dO, D, s, m->bf16));
     for (int cls = 0; cls < attn_class_count(sel); ++cls)
       if (((m->cls_active >> cls) & 1) && attn_bwd_fused(aa, cls))
         RUN(kAttnBwdName[cls],

@@ -220,6 +220,17 @@ void launch_desc_bwd(const float *geom, const float *G, int ldg, const float *T,
                      int M, int axis, int ln_mode, const float *gamma, const float *xhat,
                      const float *rstd, const float *t_emb, float *dG, float *dnext,
                      float *dRt, hipStream_t s);
+// The descriptor adjoint with the layer-norm adjoint of the last attention
+// layer (ln_mode 0 above) fused with that layer's output-projection adjoint:
+// dG and dR~ as launch_desc_bwd, and dO = d(acc) W_O^T (Wt: [D][ldg], the
+// weights the projection adjoint GEMM takes) written in place of d(acc)
+// (FP32, or BF16 with bf16).  Shapes: desc_oproj_fusable.
+bool desc_oproj_fusable(int ldg, int M, int axis, int D);
+void launch_desc_oproj_bwd(const float *geom, const float *G, const float *T, const float *dD,
+                           const int *pair_off, const int *nnei, int nloc, int sel, int M,
+                           int axis, const float *gamma, const float *xhat, const float *rstd,
+                           const float *Wt, float *dG, float *dRt, float *dO, int bf16,
+                           hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // energies, pair gradients, forces, virial (misc.hip)

@@ -48,6 +48,17 @@ def test_step_total_counts_fused_work_once():
     assert abs(core - SHAPE["n_attn"] * 6 * 2 * SHAPE["dattn"] * n2) <= 1e-9 * core
 
 
+def test_fused_descriptor_adjoint_counts_one_projection_layer():
+    nn = _nnei(4)
+    f = bench.flop_model(nn, SHAPE)
+    fused, launches = f["desc_oproj_bwd"]
+    one_layer = f["oproj_bwd"][0] / SHAPE["n_attn"]
+    assert launches == 1
+    assert abs(fused - (f["desc_bwd"][0] + one_layer)) <= 1e-9 * fused
+    # 2 d M per pair for the projection adjoint of one layer
+    assert abs(one_layer - 2.0 * SHAPE["dattn"] * SHAPE["M"] * float(nn.sum())) <= 1e-9 * one_layer
+
+
 def test_fused_adjoint_bytes_drop_the_stored_intermediates():
     nn = _nnei(3)
     b = bench.byte_model(nn, SHAPE)
