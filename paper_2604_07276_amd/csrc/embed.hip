@@ -38,13 +38,14 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi
   return __builtin_shufflevector(to_bf16(lo), to_bf16(hi), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k]  (W row-major [NTILE*16][KCH*16]).
+// acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k]  (W row-major [NTILE*16][LDW],
+// in global memory or in LDS).
 // KT < 4 (FP32 only): x and W hold data only in the first 4 KT columns of the
 // last 16-wide chunk (zeros past them), which then takes KT MFMA steps
 // instead of four: in step s lane group g carries depth 16 (KCH - 1) + 4 s + g
 // on both operands (W loaded at that depth, x taken from the lane that holds
 // it: lane r + 16 s, element g).
-template <int KCH, int NTILE, bool BF, int KT>
+template <int KCH, int NTILE, bool BF, int KT, int LDW = KCH * 16>
 __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
                                       const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
 #pragma unroll
@@ -60,7 +61,7 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
           float wt[NTILE], xt[MT];
 #pragma unroll
           for (int nt = 0; nt < NTILE; ++nt)
-            wt[nt] = W[(size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * st + g];
+            wt[nt] = W[(size_t)(nt * 16 + r) * LDW + 16 * c + 4 * st + g];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
             const int src = r + 16 * st;
@@ -85,7 +86,7 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
       for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(x[mt][c], pair ? x[mt][pair ? c + 1 : c] : z);
 #pragma unroll
       for (int nt = 0; nt < NTILE; ++nt) {
-        const float *wp = W + (size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * g;
+        const float *wp = W + (size_t)(nt * 16 + r) * LDW + 16 * c + 4 * g;
         const floatx4 w0 = *(const floatx4 *)wp;
         const floatx4 w1 = pair ? *(const floatx4 *)(wp + 16) : z;
         const bf16x8 wb = to_bf16x8(w0, w1);
@@ -98,7 +99,7 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
     floatx4 w[NTILE];
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt)
-      w[nt] = *(const floatx4 *)(W + (size_t)(nt * 16 + r) * (KCH * 16) + 16 * c + 4 * g);
+      w[nt] = *(const floatx4 *)(W + (size_t)(nt * 16 + r) * LDW + 16 * c + 4 * g);
     {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
@@ -119,14 +120,6 @@ __device__ __forceinline__ float res_fwd(const float *rowp, int mode, int fin, i
   const float v = rowp[mode == RES_DOUBLE && n >= fin ? n - fin : n];
   return mode == RES_NONE ? 0.f : v;
 }
-// gradient flowing back through the residual into input column k
-__device__ __forceinline__ float res_bwd(const float *rowp, int mode, int fin, int fout, int k) {
-  const bool two = mode == RES_DOUBLE && k + fin < fout;
-  const float v1 = rowp[k];
-  const float v2 = rowp[two ? k + fin : k];
-  return mode == RES_NONE ? 0.f : v1 + (two ? v2 : 0.f);
-}
-
 // Block-shared copies of the small per-column vectors (biases, ws): staged
 // once per block, so that no global load sits inside the per-element code.
 template <int N>
@@ -161,23 +154,46 @@ __device__ __forceinline__ void load_h1(const float *h1, int row0, int P, int r,
 }
 
 // Persistent over row tiles (the grid holds what the device keeps resident,
-// three workgroups per CU).  Loading the next tile's h1 rows ahead costs the
-// registers of the third workgroup and measured slower.
+// two workgroups per CU), with W2^T and W3^T staged in LDS once per
+// workgroup (row stride padded by 4 floats).
 // T0, T1, T2: MFMA steps of the last depth chunk in contractions over the
 // widths n0, n1, n2 (4: the whole chunk; fewer when the real width leaves the
 // rest of the chunk zero, FP32 only).
+template <int C0, int C1, int C2>
+constexpr int emb_fwd_lds_floats() {
+  return 4 * MT * 16 * (C1 * 16 + 1) + C1 * 16 * (C0 * 16 + 4) + C2 * 16 * (C1 * 16 + 4) +
+         C1 * 16 + C2 * 16;
+}
+
+template <int N, int K>
+__device__ __forceinline__ void stage_w(const float *__restrict__ W, float *dst) {
+  for (int idx = threadIdx.x; idx < N * (K / 4); idx += blockDim.x) {
+    const int row = idx / (K / 4), c4 = idx % (K / 4);
+    *(float4 *)(dst + row * (K + 4) + 4 * c4) = *(const float4 *)(W + (size_t)row * K + 4 * c4);
+  }
+}
+
 template <int C0, int C1, int C2, bool BF, int T0, int T1, int T2>
-__global__ __launch_bounds__(256, 3) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
-  constexpr int LD1 = C1 * 16, LD2 = C2 * 16;
-  __shared__ float xs[4][MT * 16][LD1 + 1];  // per wave: rows of h1 then h2
-  __shared__ float b2s[LD1], b3s[LD2];
+__global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
+  constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
+  extern __shared__ float esm[];
+  float(*xs)[MT * 16][LD1 + 1] = (float(*)[MT * 16][LD1 + 1])esm;  // per wave: h1, then h2 rows
+  float *w2s = esm + 4 * MT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
+  float *w3s = w2s + LD1 * (LD0 + 4);          // [LD2][LD1 + 4]
+  float *b2s = w3s + LD2 * (LD1 + 4);
+  float *b3s = b2s + LD1;
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int stride = gridDim.x * 4 * 16 * MT;
   int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
+  stage_w<LD1, LD0>(a.W2t, w2s);
+  stage_w<LD2, LD1>(a.W3t, w3s);
   __syncthreads();
+  // the next tile's h1 rows are loaded while the current tile is multiplied
+  floatx4 xn[MT][C0];
+  if (row0 < P) load_h1<C0>(a.h1, row0, P, lane & 15, lane >> 4, xn);
   for (; row0 < P; row0 += stride) {
     // per-lane indices are taken afresh in every iteration from a value the
     // optimiser cannot see through, so that the addresses derived from them
@@ -187,7 +203,11 @@ __global__ __launch_bounds__(256, 3) void k_emb_fwd(EmbArgs a, float *__restrict
     const int r = lane_it & 15, g = lane_it >> 4;
     float(*xw)[LD1 + 1] = xs[wave];
     floatx4 x0[MT][C0];
-    load_h1<C0>(a.h1, row0, P, r, g, x0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int c = 0; c < C0; ++c) x0[mt][c] = xn[mt][c];
+    if (row0 + stride < P) load_h1<C0>(a.h1, row0 + stride, P, r, g, xn);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -196,7 +216,7 @@ __global__ __launch_bounds__(256, 3) void k_emb_fwd(EmbArgs a, float *__restrict
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
     floatx4 acc1[MT][C1];
-    layer<C0, C1, BF, T0>(a.W2t, r, g, x0, acc1);
+    layer<C0, C1, BF, T0, LD0 + 4>(w2s, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
     floatx4 x1[MT][C1];
 #pragma unroll
@@ -218,7 +238,7 @@ __global__ __launch_bounds__(256, 3) void k_emb_fwd(EmbArgs a, float *__restrict
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
     floatx4 acc2[MT][C2];
-    layer<C1, C2, BF, T1>(a.W3t, r, g, x1, acc2);
+    layer<C1, C2, BF, T1, LD1 + 4>(w3s, r, g, x1, acc2);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -240,26 +260,115 @@ __global__ __launch_bounds__(256, 3) void k_emb_fwd(EmbArgs a, float *__restrict
   }
 }
 
+// acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k] with W given by its transpose
+// Wt[k][n] (row stride LDT, in LDS): the adjoint products read the forward's
+// staged operand.  Same operand values and MFMA order as layer() on W.
+template <int KCH, int NTILE, bool BF, int KT, int LDT>
+__device__ __forceinline__ void layer_t(const float *Wt, int r, int g,
+                                        const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < KCH; ++c) {
+    if constexpr (!BF && KT < 4) {
+      if (c == KCH - 1) {
+#pragma unroll
+        for (int st = 0; st < KT; ++st) {
+          float wt[NTILE], xt[MT];
+#pragma unroll
+          for (int nt = 0; nt < NTILE; ++nt) wt[nt] = Wt[(16 * c + 4 * st + g) * LDT + nt * 16 + r];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const int src = r + 16 * st;
+            const float e0 = __shfl(x[mt][c][0], src), e1 = __shfl(x[mt][c][1], src);
+            const float e2 = __shfl(x[mt][c][2], src), e3 = __shfl(x[mt][c][3], src);
+            xt[mt] = g == 0 ? e0 : (g == 1 ? e1 : (g == 2 ? e2 : e3));
+          }
+#pragma unroll
+          for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wt[nt], xt[mt], acc[mt][nt]);
+        }
+        continue;
+      }
+    }
+    if constexpr (BF) {
+      if (c % 2 == 1) continue;  // taken with chunk c - 1
+      const bool pair = c + 1 < KCH;
+      const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+      bf16x8 xb[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(x[mt][c], pair ? x[mt][pair ? c + 1 : c] : z);
+#pragma unroll
+      for (int nt = 0; nt < NTILE; ++nt) {
+        const float *wp = Wt + (16 * c + 4 * g) * LDT + nt * 16 + r;
+        floatx4 w0, w1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          w0[v] = wp[v * LDT];
+          w1[v] = pair ? wp[(16 + v) * LDT] : 0.f;
+        }
+        const bf16x8 wb = to_bf16x8(w0, w1);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, xb[mt], acc[mt][nt], 0, 0, 0);
+      }
+      continue;
+    }
+    floatx4 w[NTILE];
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w[nt][v] = Wt[(16 * c + 4 * g + v) * LDT + nt * 16 + r];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int nt = 0; nt < NTILE; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(w[nt][t], x[mt][c][t], acc[mt][nt]);
+  }
+}
+
+template <int C0, int C1, int C2>
+constexpr int emb_bwd_lds_floats() {
+  return emb_fwd_lds_floats<C0, C1, C2>() + C0 * 16;
+}
+
+// Adjoint of layers 2-3 with their forward recomputed, persistent like the
+// forward, with W2^T and W3^T staged in LDS (the adjoint products read them
+// transposed).  The residual rules of these widths are doubling or none (the
+// padded widths differ, so never identity); a doubling residual sends
+// d_out[k] + d_out[k + fin] back to input column k, which is formed in the
+// wave's LDS rows by storing d_out[k] and then adding d_out[k + fin] in
+// place, so a row needs only the input width.
 template <int C0, int C1, int C2, bool BF, int T0, int T1, int T2>
 __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__restrict__ dG0,
                                                     float *__restrict__ gs) {
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
-  __shared__ float xs[4][MT * 16][LD2 + 1];  // per wave: h1, h2, dG0, dh2 rows in turn
-  __shared__ float b2s[LD1], b3s[LD2], wss[LD0];
+  extern __shared__ float esm[];
+  float(*xs)[MT * 16][LD1 + 1] = (float(*)[MT * 16][LD1 + 1])esm;  // per wave: h1, then folds
+  float *w2s = esm + 4 * MT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
+  float *w3s = w2s + LD1 * (LD0 + 4);          // [LD2][LD1 + 4]
+  float *b2s = w3s + LD2 * (LD1 + 4);
+  float *b3s = b2s + LD1;
+  float *wss = b3s + LD2;
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int stride = gridDim.x * 4 * 16 * MT;
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
   stage_vec<LD0>(a.ws, wss);
+  stage_w<LD1, LD0>(a.W2t, w2s);
+  stage_w<LD2, LD1>(a.W3t, w3s);
   __syncthreads();
-  // persistent over row tiles, as the forward (no prefetch: the registers
-  // are taken by the adjoint; per-lane indices taken afresh as there)
+  // per-lane indices taken afresh in every iteration, as in the forward
   for (int row0 = (blockIdx.x * 4 + wave) * 16 * MT; row0 < P; row0 += stride) {
   int lane_it = lane;
   asm volatile("" : "+v"(lane_it));
   const int r = lane_it & 15, g = lane_it >> 4;
-  float(*xw)[LD2 + 1] = xs[wave];
+  float(*xw)[LD1 + 1] = xs[wave];
   __builtin_amdgcn_wave_barrier();
   // ---- recompute the forward
   floatx4 x0[MT][C0];
@@ -273,7 +382,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   floatx4 t1[MT][C1], x1[MT][C1];
   {
     floatx4 acc1[MT][C1];
-    layer<C0, C1, BF, T0>(a.W2t, r, g, x0, acc1);
+    layer<C0, C1, BF, T0, LD0 + 4>(w2s, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -291,7 +400,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   floatx4 d2[MT][C2];  // tanh output of layer 3, then dE/du3
   {
     floatx4 acc2[MT][C2];
-    layer<C1, C2, BF, T1>(a.W3t, r, g, x1, acc2);
+    layer<C1, C2, BF, T1, LD1 + 4>(w3s, r, g, x1, acc2);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -303,7 +412,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
           d2[mt][nt][v] = n < a.n2 ? t : 0.f;
         }
   }
-  // ---- adjoint: du3 = dG0 (1 - t3^2); dG0 rows also go to LDS for the residual
+  // ---- adjoint: du3 = dG0 (1 - t3^2); the wave's rows get dG0[k] + dG0[k + n1]
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
@@ -317,10 +426,20 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
     for (int nt = 0; nt < C2; ++nt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        xw[mt * 16 + r][nt * 16 + 4 * g + v] = gv[nt][v];
+        if (nt < C1) xw[mt * 16 + r][nt * 16 + 4 * g + v] = gv[nt][v];
         const float t = d2[mt][nt][v];
         d2[mt][nt][v] = gv[nt][v] * (1.0f - t * t);
       }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (a.res3 == RES_DOUBLE) {
+#pragma unroll
+      for (int nt = 0; nt < C2; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = nt * 16 + 4 * g + v;
+          if (n >= a.n1 && n < a.n2) xw[mt * 16 + r][n - a.n1] += gv[nt][v];
+        }
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -328,7 +447,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   floatx4 du2[MT][C1];
   {
     floatx4 acc[MT][C1];
-    layer<C2, C1, BF, T2>(a.W3b, r, g, d2, acc);
+    layer_t<C2, C1, BF, T2, LD1 + 4>(w3s, r, g, d2, acc);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -336,24 +455,38 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = nt * 16 + 4 * g + v;
-          const float dd = acc[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res3, a.n1, a.n2, k);
+          const float res = a.res3 == RES_NONE ? 0.f : xw[mt * 16 + r][k];
+          const float dd = acc[mt][nt][v] + res;
           const float d = k < a.n1 ? dd : 0.f;
           acc[mt][nt][v] = d;  // dh2
           const float t = t1[mt][nt][v];
           du2[mt][nt][v] = d * (1.0f - t * t);
         }
+    // the wave's rows get dh2[k] + dh2[k + n0]
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < C1; ++nt)
+      for (int nt = 0; nt < C0; ++nt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = acc[mt][nt][v];
+    __builtin_amdgcn_wave_barrier();
+    if (a.res2 == RES_DOUBLE) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < C1; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = nt * 16 + 4 * g + v;
+            if (n >= a.n0 && n < a.n1) xw[mt * 16 + r][n - a.n0] += acc[mt][nt][v];
+          }
+    }
     __builtin_amdgcn_wave_barrier();
   }
   // dh1 = du2 W2^T + res^T(dh2) ; du1 = dh1 (1 - h1^2) ; gs = du1 . ws
   floatx4 acc0[MT][C0];
-  layer<C1, C0, BF, T1>(a.W2b, r, g, du2, acc0);
+  layer_t<C1, C0, BF, T1, LD0 + 4>(w2s, r, g, du2, acc0);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     float s = 0.f;
@@ -362,7 +495,8 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int k = nt * 16 + 4 * g + v;
-        const float d = acc0[mt][nt][v] + res_bwd(xw[mt * 16 + r], a.res2, a.n0, a.n1, k);
+        const float res = a.res2 == RES_NONE ? 0.f : xw[mt * 16 + r][k];
+        const float d = acc0[mt][nt][v] + res;
         const float h = x0[mt][nt][v];
         const float term = d * (1.0f - h * h) * wss[k];
         s += k < a.n0 ? term : 0.f;
@@ -389,9 +523,9 @@ namespace {
 
 // Blocks of kernel k that the device holds at once (the persistent grid).
 template <class K>
-unsigned resident_blocks(K k) {
+unsigned resident_blocks(K k, size_t lds = 0) {
   int nb = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess || nb <= 0)
     nb = 2;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -402,20 +536,32 @@ unsigned resident_blocks(K k) {
 
 template <int C0, int C1, int C2, bool BF, int T0 = 4, int T1 = 4, int T2 = 4>
 void emb_fwd_grid(const EmbArgs &a, long tiles, float *G0, hipStream_t s) {
+  constexpr size_t lds = sizeof(float) * emb_fwd_lds_floats<C0, C1, C2>();
   static unsigned cap = 0;
-  if (cap == 0) cap = resident_blocks(k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>);
+  if (cap == 0) {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void *)k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    cap = resident_blocks(k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>, lds);
+  }
   const unsigned blocks = (unsigned)(tiles < (long)cap ? tiles : (long)cap);
-  hipLaunchKernelGGL((k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(256), 0, s, a,
-                     G0);
+  hipLaunchKernelGGL((k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(256), lds, s,
+                     a, G0);
 }
 
 template <int C0, int C1, int C2, bool BF, int T0 = 4, int T1 = 4, int T2 = 4>
 void emb_bwd_grid(const EmbArgs &a, long tiles, const float *dG0, float *gs, hipStream_t s) {
+  constexpr size_t lds = sizeof(float) * emb_bwd_lds_floats<C0, C1, C2>();
   static unsigned cap = 0;
-  if (cap == 0) cap = resident_blocks(k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>);
+  if (cap == 0) {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void *)k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    cap = resident_blocks(k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>, lds);
+  }
   const unsigned blocks = (unsigned)(tiles < (long)cap ? tiles : (long)cap);
-  hipLaunchKernelGGL((k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(256), 0, s, a,
-                     dG0, gs);
+  hipLaunchKernelGGL((k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(256), lds, s,
+                     a, dG0, gs);
 }
 
 // MFMA steps that the last 16-wide depth chunk of a contraction over real
