@@ -20,7 +20,6 @@ namespace dpa1 {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kNlistWaves = 4;     // waves per block in the neighbour kernel
 constexpr int kListCap = 128;      // == DP_MAX_SEL
 
 __device__ __forceinline__ void pair_vec(const double *__restrict__ x, int i, int j,
@@ -157,102 +156,171 @@ __device__ __forceinline__ int dim_offsets(const CellGrid &g, int dim, int c, in
   return n;
 }
 
-// One wavefront per centre atom k.  Local centres collect every atom within
-// rcut; ghost centres collect local atoms only (they are needed by the force
-// gather, never as energy centres).
-__global__ __launch_bounds__(kWave *kNlistWaves) void k_nlist(
-    const double *__restrict__ x, int nloc, int nall, CellGrid g, double rc2, int sel,
-    const int *__restrict__ atom_cell, const int *__restrict__ cell_start,
-    const int *__restrict__ cell_atoms, int *__restrict__ nlist, int *__restrict__ nnei,
-    DevFlags *flags) {
-  __shared__ int list[kNlistWaves][kListCap];
+// One workgroup per cell.  Every atom of a cell has the same 27 neighbour
+// cells, so the workgroup stages their candidates (atom index and FP64
+// coordinates) in LDS once and each wavefront then tests its centres (one
+// at a time) against the staged tile, 64 candidates per pass.  Local
+// centres collect every atom within rcut; ghost centres collect local atoms
+// only (they are needed by the force gather, never as energy centres).  A
+// neighbourhood with more candidates than the tile holds is scanned from
+// global memory instead (same ranges, same test).
+constexpr int kCellWaves = 8;      // wavefronts per cell workgroup
+constexpr int kTileCap = 1536;     // staged candidates (about 2.5x the protein density)
+constexpr int kMaxRanges = 27;
+
+// The pair test on FP64 coordinates: the recipe of pair_vec and norm2.
+__device__ __forceinline__ bool within(double xi0, double xi1, double xi2, double xj0, double xj1,
+                                       double xj2, const CellGrid &g, double rc2) {
+#pragma clang fp contract(off)
+  double d0 = xj0 - xi0, d1 = xj1 - xi1, d2 = xj2 - xi2;
+  if (g.periodic) {
+    d0 = d0 - g.L[0] * rint(d0 / g.L[0]);
+    d1 = d1 - g.L[1] * rint(d1 / g.L[1]);
+    d2 = d2 - g.L[2] * rint(d2 / g.L[2]);
+  }
+  return (d0 * d0 + d1 * d1) + d2 * d2 < rc2;
+}
+
+__global__ __launch_bounds__(kWave *kCellWaves) void k_nlist(
+    const double *__restrict__ x, int nloc, CellGrid g, double rc2, int sel,
+    const int *__restrict__ cell_start, const int *__restrict__ cell_atoms,
+    int *__restrict__ nlist, int *__restrict__ nnei, DevFlags *flags) {
+  __shared__ int tj[kTileCap];
+  __shared__ double tx[kTileCap], ty[kTileCap], tz[kTileCap];
+  __shared__ int list[kCellWaves][kListCap];
+  __shared__ int rb[kMaxRanges], roff[kMaxRanges + 1];
+  __shared__ int nr;
+  const int cell = blockIdx.x;
+  const int a0 = cell_start[cell], a1 = cell_start[cell + 1];
+  if (a0 == a1) return;  // empty cell: the whole workgroup leaves
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const int k = blockIdx.x * kNlistWaves + wave;
-  if (k >= nall) return;
-  const bool ghost = k >= nloc;
-  const int ck = atom_cell[k];
-  const int cx = ck % g.nc[0];
-  const int cy = (ck / g.nc[0]) % g.nc[1];
-  const int cz = ck / (g.nc[0] * g.nc[1]);
-  int ox[3], oy[3], oz[3];
-  const int nx = dim_offsets(g, 0, cx, ox);
-  const int ny = dim_offsets(g, 1, cy, oy);
-  const int nz = dim_offsets(g, 2, cz, oz);
-  int count = 0;
-  // candidates of the atom range [beg, end) of cell_atoms, 64 at a time
-  auto scan = [&](int beg, int end) {
-    for (int base = beg; base < end; base += kWave) {
-      const int idx = base + lane;
-      bool hit = false;
-      int j = -1;
-      if (idx < end) {
-        j = cell_atoms[idx];
-        if (j != k && (!ghost || j < nloc)) {
-          double d[3];
-          pair_vec(x, k, j, g, d);
-          hit = norm2(d) < rc2;
+  if (threadIdx.x == 0) {
+    // The cells of one (y, z) row are consecutive in the cell order, so their
+    // atoms are one contiguous range of cell_atoms unless the row wraps: the
+    // row's cells are visited in ascending index and merged while their
+    // atom ranges touch.
+    const int cx = cell % g.nc[0];
+    const int cy = (cell / g.nc[0]) % g.nc[1];
+    const int cz = cell / (g.nc[0] * g.nc[1]);
+    int ox[3], oy[3], oz[3];
+    const int nx = dim_offsets(g, 0, cx, ox);
+    const int ny = dim_offsets(g, 1, cy, oy);
+    const int nz = dim_offsets(g, 2, cz, oz);
+    int q = 0, tot = 0;
+    auto add = [&](int beg, int end) {
+      rb[q] = beg;
+      roff[q] = tot;
+      tot += end - beg;
+      ++q;
+    };
+    for (int a = 0; a < nz; ++a)
+      for (int b = 0; b < ny; ++b) {
+        const int row = (oz[a] * g.nc[1] + oy[b]) * g.nc[0];
+        int cs[3];
+        for (int c = 0; c < nx; ++c) cs[c] = row + ox[c];
+        if (nx > 1 && cs[0] > cs[1]) { const int t = cs[0]; cs[0] = cs[1]; cs[1] = t; }
+        if (nx > 2 && cs[1] > cs[2]) { const int t = cs[1]; cs[1] = cs[2]; cs[2] = t; }
+        if (nx > 1 && cs[0] > cs[1]) { const int t = cs[0]; cs[0] = cs[1]; cs[1] = t; }
+        int beg = cell_start[cs[0]], end = cell_start[cs[0] + 1];
+        for (int c = 1; c < nx; ++c) {
+          const int cb = cell_start[cs[c]], ce = cell_start[cs[c] + 1];
+          if (cb == end) {
+            end = ce;
+          } else {
+            add(beg, end);
+            beg = cb;
+            end = ce;
+          }
         }
+        add(beg, end);
       }
+    roff[q] = tot;
+    nr = q;
+  }
+  __syncthreads();
+  const int R = nr;
+  const int T = roff[R];
+  const bool staged = T <= kTileCap;
+  if (staged) {
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+      int q = 0;
+      while (t >= roff[q + 1]) ++q;  // ranges are few (at most 27)
+      const int j = cell_atoms[rb[q] + (t - roff[q])];
+      tj[t] = j;
+      tx[t] = x[3 * j + 0];
+      ty[t] = x[3 * j + 1];
+      tz[t] = x[3 * j + 2];
+    }
+  }
+  __syncthreads();
+  for (int ai = a0 + wave; ai < a1; ai += kCellWaves) {
+    const int k = cell_atoms[ai];
+    const bool ghost = k >= nloc;
+    const double xk0 = x[3 * k + 0], xk1 = x[3 * k + 1], xk2 = x[3 * k + 2];
+    int count = 0;
+    auto keep = [&](bool hit, int j) {
       const unsigned long long m = __ballot(hit);
       const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
       if (hit && pos < kListCap) list[wave][pos] = j;
       count += __popcll(m);
-    }
-  };
-  // The cells of one (y, z) row are consecutive in the cell order, so their
-  // atoms are one contiguous range of cell_atoms unless the row wraps: the
-  // row's cells are visited in ascending index and merged while their atom
-  // ranges touch (a few passes of 64 candidates per row instead of one per
-  // cell; the list is sorted afterwards, so the visiting order is free).
-  for (int a = 0; a < nz; ++a)
-    for (int b = 0; b < ny; ++b) {
-      const int row = (oz[a] * g.nc[1] + oy[b]) * g.nc[0];
-      int cs[3];
-      for (int c = 0; c < nx; ++c) cs[c] = row + ox[c];
-      // ascending (at most three entries)
-      if (nx > 1 && cs[0] > cs[1]) { const int t = cs[0]; cs[0] = cs[1]; cs[1] = t; }
-      if (nx > 2 && cs[1] > cs[2]) { const int t = cs[1]; cs[1] = cs[2]; cs[2] = t; }
-      if (nx > 1 && cs[0] > cs[1]) { const int t = cs[0]; cs[0] = cs[1]; cs[1] = t; }
-      int beg = cell_start[cs[0]], end = cell_start[cs[0] + 1];
-      for (int c = 1; c < nx; ++c) {
-        const int cb = cell_start[cs[c]], ce = cell_start[cs[c] + 1];
-        if (cb == end) {
-          end = ce;
-        } else {
-          scan(beg, end);
-          beg = cb;
-          end = ce;
+    };
+    if (staged) {
+      for (int base = 0; base < T; base += kWave) {
+        const int t = base + lane;
+        bool hit = false;
+        int j = -1;
+        if (t < T) {
+          j = tj[t];
+          if (j != k && (!ghost || j < nloc))
+            hit = within(xk0, xk1, xk2, tx[t], ty[t], tz[t], g, rc2);
+        }
+        keep(hit, j);
+      }
+    } else {
+      for (int q = 0; q < R; ++q) {
+        const int beg = rb[q], end = rb[q] + (roff[q + 1] - roff[q]);
+        for (int base = beg; base < end; base += kWave) {
+          const int idx = base + lane;
+          bool hit = false;
+          int j = -1;
+          if (idx < end) {
+            j = cell_atoms[idx];
+            if (j != k && (!ghost || j < nloc))
+              hit = within(xk0, xk1, xk2, x[3 * j + 0], x[3 * j + 1], x[3 * j + 2], g, rc2);
+          }
+          keep(hit, j);
         }
       }
-      scan(beg, end);
     }
-  const int n = count < sel ? count : sel;
-  if (count > sel) {
-    if (lane == 0) {
-      int old = atomicMin(&flags->overflow_atom, k);
-      if (old > k) atomicExch(&flags->overflow_count, count);
+    const int n = count < sel ? count : sel;
+    if (count > sel) {
+      if (lane == 0) {
+        int old = atomicMin(&flags->overflow_atom, k);
+        if (old > k) atomicExch(&flags->overflow_count, count);
+      }
     }
+    // rank sort of the (distinct) indices
+    int vals[2], ranks[2];
+    for (int h = 0; h < 2; ++h) {
+      const int p = lane + h * kWave;
+      vals[h] = p < n ? list[wave][p] : INT_MAX;
+      ranks[h] = 0;
+    }
+    for (int q = 0; q < n; ++q) {
+      const int v = list[wave][q];
+      ranks[0] += v < vals[0];
+      ranks[1] += v < vals[1];
+    }
+    int *row = nlist + (size_t)k * sel;
+    for (int h = 0; h < 2; ++h) {
+      const int p = lane + h * kWave;
+      if (p < n) row[ranks[h]] = vals[h];
+      else if (p < sel) row[p] = -1;
+    }
+    if (lane == 0) nnei[k] = n;
+    __builtin_amdgcn_wave_barrier();  // the wave's list is rewritten by its next centre
   }
-  // rank sort of the (distinct) indices
-  int vals[2], ranks[2];
-  for (int h = 0; h < 2; ++h) {
-    const int p = lane + h * kWave;
-    vals[h] = p < n ? list[wave][p] : INT_MAX;
-    ranks[h] = 0;
-  }
-  for (int q = 0; q < n; ++q) {
-    const int v = list[wave][q];
-    ranks[0] += v < vals[0];
-    ranks[1] += v < vals[1];
-  }
-  int *row = nlist + (size_t)k * sel;
-  for (int h = 0; h < 2; ++h) {
-    const int p = lane + h * kWave;
-    if (p < n) row[ranks[h]] = vals[h];
-    else if (p < sel) row[p] = -1;
-  }
-  if (lane == 0) nnei[k] = n;
 }
 
 // One thread per (centre, slot).  Geometry in FP64, stored as FP32.
@@ -353,9 +421,10 @@ void launch_nlist(const double *coords, int nloc, int nall, CellGrid grid, doubl
                   const int *atom_cell, const int *cell_start, const int *cell_atoms, int *nlist,
                   int *nnei, DevFlags *flags, hipStream_t s) {
   if (nall <= 0) return;
-  hipLaunchKernelGGL(k_nlist, dim3(nblk(nall, kNlistWaves)), dim3(kWave * kNlistWaves), 0, s,
-                     coords, nloc, nall, grid, rcut * rcut, sel, atom_cell, cell_start,
-                     cell_atoms, nlist, nnei, flags);
+  (void)atom_cell;
+  const int ncell = grid.nc[0] * grid.nc[1] * grid.nc[2];
+  hipLaunchKernelGGL(k_nlist, dim3(ncell), dim3(kWave * kCellWaves), 0, s, coords, nloc, grid,
+                     rcut * rcut, sel, cell_start, cell_atoms, nlist, nnei, flags);
 }
 
 void launch_env_embed1(const double *coords, const int32_t *types, CellGrid grid, int nloc,

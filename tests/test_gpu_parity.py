@@ -79,6 +79,40 @@ def test_nlist_bit_exact_192(model, oracle_model):
         assert np.all(nl[i, nn[i]:] == -1)
 
 
+def test_nlist_dense_neighbourhood_beyond_lds_tile(weights_path):
+    """1,728 atoms on a jittered 12^3 lattice in a periodic box 3.9 rc wide:
+    three cells per side, so the 27 cells around any cell hold every atom,
+    more candidates than the neighbour kernel stages in LDS (its scan of
+    global memory runs instead).  Every atom has 122 neighbours (the lattice
+    shells at 0.975 and 1.028 rc stay on their side under the jitter); lists
+    bit-exact against brute force."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_07276_amd import binding
+    rng = np.random.default_rng(5)
+    L = 3.9 * RC
+    grid = (np.arange(12) + 0.5) * (L / 12)
+    coords = np.stack(np.meshgrid(grid, grid, grid, indexing="ij"), -1).reshape(-1, 3)
+    coords = coords + rng.uniform(-0.02, 0.02, coords.shape)
+    n = len(coords)
+    types = rng.integers(0, 2, n).astype(np.int32)
+    box = np.diag([L, L, L])
+    say(f"case: dense lattice N={n}, box {L:.1f} A, sel 128, neighbour list")
+    m = binding.Model(weights_path, RC, 128)
+    try:
+        m.compute(coords, types, box, n, 0)
+        nl, nn = m.debug_nlist(n)
+    finally:
+        m.close()
+    ref = orc.neighbor_list(coords, box, RC, np.arange(n))
+    assert all(len(r) == 122 for r in ref)
+    for i in range(n):
+        assert nn[i] == len(ref[i])
+        assert np.array_equal(nl[i, :nn[i]], ref[i])
+        assert np.all(nl[i, nn[i]:] == -1)
+
+
 def test_parity_open_cluster_with_ghosts(model, oracle_model):
     # open boundaries: a cluster whose outer shell is passed as ghosts
     c = synth.open_cluster(150, 9.0, 5, seed=9)
