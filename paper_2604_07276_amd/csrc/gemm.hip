@@ -83,7 +83,12 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   // Used by the BF16 instances and the 16-row (per-centre) tiles; the FP32
   // 64-row tiles keep per-wavefront W streams (see the k loop).
   constexpr bool kShareW = BF != 0 || MT < 4;
-  constexpr int KC = BF ? 32 : 16;  // k depth of one staged chunk (BF16: one 16x16x32 step)
+  // k depth of one staged chunk: 32 in BF16 (one 16x16x32 step) and for the
+  // FP32 16-row tiles (the long-k fitting products: two 16-deep steps per
+  // barrier, the next chunk's loads twice as far ahead); 16 for FP32 32-row
+  // tiles (whose registers a 32-deep chunk would spill)
+  constexpr int KC = (BF != 0 || MT == 1) ? 32 : 16;
+  constexpr int H = KC / 16;        // 16-deep steps per chunk
   constexpr int kWS = KC + 4;       // LDS row stride
   __shared__ float wsh[kShareW ? 2 : 1][kShareW ? NT * 16 : 1][kWS];
   const int M = a.Mptr ? *a.Mptr : a.Mmax;
@@ -205,39 +210,54 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
     }
   } else {
 
-    // Double-buffered k loop: the operands of chunk k0 + 16 (the block's W
-    // rows, the wavefront's X rows) are loaded while chunk k0 is multiplied;
-    // the MFMAs of one k step go to independent accumulators back to back.
-    floatx4 xv[MT], xn[MT];
-    wload(0);
+    // Double-buffered k loop: the operands of chunk k0 + KC (the block's W
+    // rows, the wavefront's X rows) are loaded while chunk k0 is multiplied
+    // as H 16-deep steps (with H = 2 a second half past K, K being a
+    // multiple of 16, re-reads the first half of X and meets zero weights:
+    // its MFMAs add zeros); the MFMAs of one step go to independent
+    // accumulators back to back.
+    floatx4 xv[MT][H], xn[MT][H];
+    auto xload = [&](int k0, floatx4 (&x)[MT][H]) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) xv[mt] = ldx4<BF>(xrow[mt], 0);
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+          x[mt][h] = ldx4<BF>(xrow[mt], k0 + 16 * h < a.K ? k0 + 16 * h : k0);
+    };
+    wload(0);
+    xload(0, xv);
     wstore(0);
     __syncthreads();
     int b = 0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < a.K; k0 += 16) {
-      const bool more = k0 + 16 < a.K;  // uniform
+    for (int k0 = 0; k0 < a.K; k0 += KC) {
+      const bool more = k0 + KC < a.K;  // uniform
       if (more) {
-        wload(k0 + 16);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) xn[mt] = ldx4<BF>(xrow[mt], k0 + 16);
+        wload(k0 + KC);
+        xload(k0 + KC, xn);
       }
-      floatx4 wv[NT];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) wv[nt] = *(const floatx4 *)&wsh[b][nt * 16 + r][4 * g];
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int h = 0; h < H; ++h) {
+        floatx4 wv[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
+          wv[nt] = *(const floatx4 *)&wsh[b][nt * 16 + r][16 * h + 4 * g];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma4(wv[nt][t], xv[mt][t], acc[mt][nt]);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+              acc[mt][nt] = mfma4(wv[nt][t], xv[mt][h][t], acc[mt][nt]);
+      }
       if (more) wstore(b ^ 1);
-      __syncthreads();  // chunk k0 + 16 staged; buffer b free again
+      __syncthreads();  // chunk k0 + KC staged; buffer b free again
       b ^= 1;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) xv[mt] = xn[mt];
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int h = 0; h < H; ++h) xv[mt][h] = xn[mt][h];
     }
   }
   } else {
