@@ -134,6 +134,12 @@ def byte_model(nnei: np.ndarray, shape, bf16: bool = False) -> dict:
         "oproj_ln_fwd": (L * P * (t * d + f4 * (M + 2 * M + 1)), L),
         "oproj_bwd": (L * P * (f4 * M + t * d), L),
     }
+    # descriptor adjoint with the last layer's projection adjoint: per pair
+    # G, xhat, the geometry record's R~ and 1/std in, the residual gradient,
+    # dR~ and dO out; per centre dD and T in
+    if L > 0:
+        out["desc_oproj_bwd"] = (P * (f4 * (3 * M + 1) + 16.0 + 16.0 + t * d)
+                                 + len(nnei) * f4 * (M * shape["axis"] + 4 * M), 1)
     nn = nnei.astype(np.float64)
     for c, npad in enumerate((32, 64, 96, 128)):
         sel_c = (nnei > npad - 32) & (nnei <= npad)
@@ -179,10 +185,10 @@ def geometry_bytes(nnei: np.ndarray, sel: int, nall: int) -> dict:
 
 def kernel_sources(kernel: str) -> list:
     """Library sources that define a kernel's code and launch (the attention
-    kernels: attn.hip and the shared internal header; the attention-layer
+    and descriptor kernels: attn.hip and the shared headers; the attention-layer
     projections: gemm.hip and that header; others: every source)."""
     csrc = os.path.join(ROOT, "paper_2604_07276_amd", "csrc")
-    if kernel.startswith("attn_"):
+    if kernel.startswith(("attn_", "desc_")):
         return [os.path.join(csrc, "attn.hip"), os.path.join(csrc, "dpa1_internal.h"),
                 os.path.join(csrc, "ln_res.h")]
     if kernel.startswith(("qkv_", "oproj_")):
@@ -449,8 +455,9 @@ def main():
               file=sys.stderr)
         for name, (cnt, ms) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
             tf = ""
-            if name in flops:
-                tf = f"{flops[name][0] * args.steps / (ms * 1e-3) / 1e12:9.1f}"
+            if name in flops:  # per-launch work times the launches made
+                per = flops[name][0] / flops[name][1]
+                tf = f"{per * cnt / (ms * 1e-3) / 1e12:9.1f}"
             print(f"{name:<16}{cnt:>9}{ms / cnt:>10.4f}{ms / tot:>8.1%}{tf:>9}", file=sys.stderr)
         print(f"step: {ms_step:.3f} ms, {step_flops / 1e12:.4f} TFLOP algorithmic, "
               f"sum of kernel times {tot / args.steps:.3f} ms", file=sys.stderr)

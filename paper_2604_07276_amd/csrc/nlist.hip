@@ -2,9 +2,9 @@
 //
 // Full neighbour lists within the cutoff (Sec. II-A: cutoff lists make the
 // cost O(N); Sec. II-C: a DP descriptor needs the full list of every centre).
-// A cell grid with edge >= rcut bins the atoms; one wavefront per centre
-// scans the 27 surrounding cells, tests candidates in FP64 and compacts hits
-// with a ballot.  Lists are sorted by atom index so that every later stage
+// A cell grid with edge >= rcut bins the atoms; one workgroup per cell
+// stages the candidates of the 27 surrounding cells in LDS, and one
+// wavefront per centre tests them in FP64 and compacts hits with a ballot.  Lists are sorted by atom index so that every later stage
 // sees a deterministic neighbour order.
 //
 // Pair vectors follow one fixed FP64 recipe, with contraction disabled so
