@@ -311,6 +311,11 @@ def test_replication_2x2x1(model):
     ("student_dpse", dict(emb=(16, 32, 64), axis=8, n_attn=0, fit=(128, 128))),
     # widths 25 -> 50 -> 50: identity residual in the last embedding layer
     ("emb25-50-50_attn2", dict(emb=(25, 50, 50), n_attn=2, fit=(64, 64, 64))),
+    # widths 25 -> 50 -> 98: the fused embedding kernels with no residual in
+    # the last layer, and 98 real features of 112 in the kernels that take
+    # the last 16-wide chunk's real features in one step (QKV projection,
+    # forward with the projection, descriptor adjoint with dO)
+    ("emb25-50-98_attn2", dict(emb=(25, 50, 98), n_attn=2)),
     # no attention layer: the descriptor takes the embedding output directly
     ("attn0", dict(n_attn=0)),
 ])
