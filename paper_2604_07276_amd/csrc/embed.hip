@@ -45,7 +45,7 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi
 // instead of four: in step s lane group g carries depth 16 (KCH - 1) + 4 s + g
 // on both operands (W loaded at that depth, x taken from the lane that holds
 // it: lane r + 16 s, element g).
-template <int KCH, int NTILE, bool BF, int KT, int LDW = KCH * 16>
+template <int KCH, int NTILE, bool BF, int KT, int LDW = KCH * 16, int MT>
 __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
                                       const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
 #pragma unroll
@@ -140,7 +140,7 @@ struct EmbArgs {
 
 // Rows [row0, row0 + 16 MT) of h1 as the B operand of layer 2 (rows past P
 // read row 0 and are never stored).
-template <int C0>
+template <int C0, int MT>
 __device__ __forceinline__ void load_h1(const float *h1, int row0, int P, int r, int g,
                                         floatx4 (&x0)[MT][C0]) {
 #pragma unroll
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
 // acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k] with W given by its transpose
 // Wt[k][n] (row stride LDT, in LDS): the adjoint products read the forward's
 // staged operand.  Same operand values and MFMA order as layer() on W.
-template <int KCH, int NTILE, bool BF, int KT, int LDT>
+template <int KCH, int NTILE, bool BF, int KT, int LDT, int MT>
 __device__ __forceinline__ void layer_t(const float *Wt, int r, int g,
                                         const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
 #pragma unroll
@@ -331,9 +331,18 @@ __device__ __forceinline__ void layer_t(const float *Wt, int r, int g,
   }
 }
 
-template <int C0, int C1, int C2>
+// The adjoint's tiles.  FP32: one 16-row tile per wavefront, eight
+// wavefronts per workgroup, four wavefronts per SIMD in 128 registers
+// (0.54 -> 0.52 ms against two-tile wavefronts at two per SIMD).  BF16 keeps
+// two-tile wavefronts, four per workgroup (the one-tile form measured
+// 0.28 -> 0.31 ms there).
+constexpr int bwd_tiles(bool bf) { return bf ? 2 : 1; }  // 16-row tiles per wavefront
+constexpr int bwd_waves(bool bf) { return bf ? 4 : 8; }  // wavefronts per workgroup
+
+template <int C0, int C1, int C2, bool BF>
 constexpr int emb_bwd_lds_floats() {
-  return emb_fwd_lds_floats<C0, C1, C2>() + C0 * 16;
+  return bwd_waves(BF) * bwd_tiles(BF) * 16 * (C1 * 16 + 1) + C1 * 16 * (C0 * 16 + 4) +
+         C2 * 16 * (C1 * 16 + 4) + C1 * 16 + C2 * 16 + C0 * 16;
 }
 
 // Adjoint of layers 2-3 with their forward recomputed, persistent like the
@@ -344,19 +353,20 @@ constexpr int emb_bwd_lds_floats() {
 // wave's LDS rows by storing d_out[k] and then adding d_out[k + fin] in
 // place, so a row needs only the input width.
 template <int C0, int C1, int C2, bool BF, int T0, int T1, int T2>
-__global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__restrict__ dG0,
-                                                    float *__restrict__ gs) {
+__global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
+    EmbArgs a, const float *__restrict__ dG0, float *__restrict__ gs) {
+  constexpr int BT = bwd_tiles(BF), BW = bwd_waves(BF);
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   extern __shared__ float esm[];
-  float(*xs)[MT * 16][LD1 + 1] = (float(*)[MT * 16][LD1 + 1])esm;  // per wave: h1, then folds
-  float *w2s = esm + 4 * MT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
+  float(*xs)[BT * 16][LD1 + 1] = (float(*)[BT * 16][LD1 + 1])esm;  // per wave: h1, then folds
+  float *w2s = esm + BW * BT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
   float *w3s = w2s + LD1 * (LD0 + 4);          // [LD2][LD1 + 4]
   float *b2s = w3s + LD2 * (LD1 + 4);
   float *b3s = b2s + LD1;
   float *wss = b3s + LD2;
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int stride = gridDim.x * 4 * 16 * MT;
+  const int stride = gridDim.x * BW * 16 * BT;
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
   stage_vec<LD0>(a.ws, wss);
@@ -364,28 +374,28 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   stage_w<LD2, LD1>(a.W3t, w3s);
   __syncthreads();
   // per-lane indices taken afresh in every iteration, as in the forward
-  for (int row0 = (blockIdx.x * 4 + wave) * 16 * MT; row0 < P; row0 += stride) {
+  for (int row0 = (blockIdx.x * BW + wave) * 16 * BT; row0 < P; row0 += stride) {
   int lane_it = lane;
   asm volatile("" : "+v"(lane_it));
   const int r = lane_it & 15, g = lane_it >> 4;
   float(*xw)[LD1 + 1] = xs[wave];
   __builtin_amdgcn_wave_barrier();
   // ---- recompute the forward
-  floatx4 x0[MT][C0];
+  floatx4 x0[BT][C0];
   load_h1<C0>(a.h1, row0, P, r, g, x0);
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
     for (int c = 0; c < C0; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
-  floatx4 t1[MT][C1], x1[MT][C1];
+  floatx4 t1[BT][C1], x1[BT][C1];
   {
-    floatx4 acc1[MT][C1];
+    floatx4 acc1[BT][C1];
     layer<C0, C1, BF, T0, LD0 + 4>(w2s, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < C1; ++nt)
 #pragma unroll
@@ -397,12 +407,12 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
           x1[mt][nt][v] = n < a.n1 ? h : 0.f;
         }
   }
-  floatx4 d2[MT][C2];  // tanh output of layer 3, then dE/du3
+  floatx4 d2[BT][C2];  // tanh output of layer 3, then dE/du3
   {
-    floatx4 acc2[MT][C2];
+    floatx4 acc2[BT][C2];
     layer<C1, C2, BF, T1, LD1 + 4>(w3s, r, g, x1, acc2);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < C2; ++nt)
 #pragma unroll
@@ -415,7 +425,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   // ---- adjoint: du3 = dG0 (1 - t3^2); the wave's rows get dG0[k] + dG0[k + n1]
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
+  for (int mt = 0; mt < BT; ++mt) {
     const int row = row0 + mt * 16 + r;
     const int rr = row < P ? row : 0;
     floatx4 gv[C2];  // all loads of the tile row before any use
@@ -444,12 +454,12 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
   }
   __builtin_amdgcn_wave_barrier();
   // dh2 = du3 W3^T + res^T(dG0) ; du2 = dh2 (1 - t2^2)
-  floatx4 du2[MT][C1];
+  floatx4 du2[BT][C1];
   {
-    floatx4 acc[MT][C1];
+    floatx4 acc[BT][C1];
     layer_t<C2, C1, BF, T2, LD1 + 4>(w3s, r, g, d2, acc);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < C1; ++nt)
 #pragma unroll
@@ -465,7 +475,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
     // the wave's rows get dh2[k] + dh2[k + n0]
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < C0; ++nt)
 #pragma unroll
@@ -473,7 +483,7 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
     __builtin_amdgcn_wave_barrier();
     if (a.res2 == RES_DOUBLE) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < C1; ++nt)
 #pragma unroll
@@ -485,10 +495,10 @@ __global__ __launch_bounds__(256, 2) void k_emb_bwd(EmbArgs a, const float *__re
     __builtin_amdgcn_wave_barrier();
   }
   // dh1 = du2 W2^T + res^T(dh2) ; du1 = dh1 (1 - h1^2) ; gs = du1 . ws
-  floatx4 acc0[MT][C0];
+  floatx4 acc0[BT][C0];
   layer_t<C1, C0, BF, T1, LD0 + 4>(w2s, r, g, du2, acc0);
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
+  for (int mt = 0; mt < BT; ++mt) {
     float s = 0.f;
 #pragma unroll
     for (int nt = 0; nt < C0; ++nt)
@@ -523,9 +533,9 @@ namespace {
 
 // Blocks of kernel k that the device holds at once (the persistent grid).
 template <class K>
-unsigned resident_blocks(K k, size_t lds = 0) {
+unsigned resident_blocks(K k, size_t lds = 0, int threads = 256) {
   int nb = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess || nb <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, threads, lds) != hipSuccess || nb <= 0)
     nb = 2;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -550,18 +560,21 @@ void emb_fwd_grid(const EmbArgs &a, long tiles, float *G0, hipStream_t s) {
 }
 
 template <int C0, int C1, int C2, bool BF, int T0 = 4, int T1 = 4, int T2 = 4>
-void emb_bwd_grid(const EmbArgs &a, long tiles, const float *dG0, float *gs, hipStream_t s) {
-  constexpr size_t lds = sizeof(float) * emb_bwd_lds_floats<C0, C1, C2>();
+void emb_bwd_grid(const EmbArgs &a, long rows, const float *dG0, float *gs, hipStream_t s) {
+  constexpr size_t lds = sizeof(float) * emb_bwd_lds_floats<C0, C1, C2, BF>();
+  constexpr int threads = 64 * bwd_waves(BF);
+  constexpr long per_block = 16L * bwd_tiles(BF) * bwd_waves(BF);  // rows per block and round
+  const long tiles = (rows + per_block - 1) / per_block;
   static unsigned cap = 0;
   if (cap == 0) {
     if (lds > 65536)
       (void)hipFuncSetAttribute((const void *)k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    cap = resident_blocks(k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>, lds);
+    cap = resident_blocks(k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>, lds, threads);
   }
   const unsigned blocks = (unsigned)(tiles < (long)cap ? tiles : (long)cap);
-  hipLaunchKernelGGL((k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(256), lds, s,
-                     a, dG0, gs);
+  hipLaunchKernelGGL((k_emb_bwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(threads), lds,
+                     s, a, dG0, gs);
 }
 
 // MFMA steps that the last 16-wide depth chunk of a contraction over real
@@ -591,14 +604,14 @@ void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
 void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t s) {
   EmbArgs a{e.h1, e.W2t, e.b2, e.W3t, e.b3, e.W2b, e.W3b, e.ws, e.n0, e.n1, e.n2, e.res2, e.res3,
             e.Pptr};
-  const long tiles = ((long)e.Pmax + 64 * MT - 1) / (64 * MT);
-  if (tiles == 0) return;
+  const long rows = e.Pmax;
+  if (rows <= 0) return;
   const bool st = is_student_widths(pad16(e.n0), pad16(e.n1), pad16(e.n2));
-  if (st && e.bf16) emb_bwd_grid<1, 2, 4, true>(a, tiles, dG0, gs, s);
-  else if (st) emb_bwd_grid<1, 2, 4, false>(a, tiles, dG0, gs, s);
-  else if (e.bf16) emb_bwd_grid<2, 4, 7, true>(a, tiles, dG0, gs, s);
-  else if (short_tails(e)) emb_bwd_grid<2, 4, 7, false, 3, 1, 1>(a, tiles, dG0, gs, s);
-  else emb_bwd_grid<2, 4, 7, false>(a, tiles, dG0, gs, s);
+  if (st && e.bf16) emb_bwd_grid<1, 2, 4, true>(a, rows, dG0, gs, s);
+  else if (st) emb_bwd_grid<1, 2, 4, false>(a, rows, dG0, gs, s);
+  else if (e.bf16) emb_bwd_grid<2, 4, 7, true>(a, rows, dG0, gs, s);
+  else if (short_tails(e)) emb_bwd_grid<2, 4, 7, false, 3, 1, 1>(a, rows, dG0, gs, s);
+  else emb_bwd_grid<2, 4, 7, false>(a, rows, dG0, gs, s);
 }
 
 }  // namespace dpa1
