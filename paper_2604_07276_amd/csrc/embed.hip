@@ -18,7 +18,6 @@ namespace dpa1 {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-constexpr int MT = 2;  // 16-row tiles per wavefront
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -38,8 +37,8 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi
   return __builtin_shufflevector(to_bf16(lo), to_bf16(hi), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k]  (W row-major [NTILE*16][LDW],
-// in global memory or in LDS).
+// acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k] over the wavefront's MT 16-row
+// tiles (W row-major [NTILE*16][LDW], in global memory or in LDS).
 // KT < 4 (FP32 only): x and W hold data only in the first 4 KT columns of the
 // last 16-wide chunk (zeros past them), which then takes KT MFMA steps
 // instead of four: in step s lane group g carries depth 16 (KCH - 1) + 4 s + g
@@ -153,16 +152,16 @@ __device__ __forceinline__ void load_h1(const float *h1, int row0, int P, int r,
   }
 }
 
-// Persistent over row tiles (the grid holds what the device keeps resident,
-// two workgroups per CU), with W2^T and W3^T staged in LDS once per
-// workgroup (row stride padded by 4 floats).
-// T0, T1, T2: MFMA steps of the last depth chunk in contractions over the
-// widths n0, n1, n2 (4: the whole chunk; fewer when the real width leaves the
-// rest of the chunk zero, FP32 only).
-template <int C0, int C1, int C2>
+// Tiles of the forward as those of the adjoint below: FP32 one 16-row tile
+// per wavefront and eight wavefronts per workgroup, BF16 two-tile
+// wavefronts, four per workgroup.
+constexpr int fwd_tiles(bool bf) { return bf ? 2 : 1; }
+constexpr int fwd_waves(bool bf) { return bf ? 4 : 8; }
+
+template <int C0, int C1, int C2, bool BF>
 constexpr int emb_fwd_lds_floats() {
-  return 4 * MT * 16 * (C1 * 16 + 1) + C1 * 16 * (C0 * 16 + 4) + C2 * 16 * (C1 * 16 + 4) +
-         C1 * 16 + C2 * 16;
+  return fwd_waves(BF) * fwd_tiles(BF) * 16 * (C1 * 16 + 1) + C1 * 16 * (C0 * 16 + 4) +
+         C2 * 16 * (C1 * 16 + 4) + C1 * 16 + C2 * 16;
 }
 
 template <int N, int K>
@@ -173,26 +172,34 @@ __device__ __forceinline__ void stage_w(const float *__restrict__ W, float *dst)
   }
 }
 
+// Persistent over row tiles (the grid holds what the device keeps resident,
+// two workgroups per CU), with W2^T and W3^T staged in LDS once per
+// workgroup (row stride padded by 4 floats).
+// T0, T1, T2: MFMA steps of the last depth chunk in contractions over the
+// widths n0, n1, n2 (4: the whole chunk; fewer when the real width leaves the
+// rest of the chunk zero, FP32 only).
 template <int C0, int C1, int C2, bool BF, int T0, int T1, int T2>
-__global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict__ G0) {
+__global__ __launch_bounds__(64 * fwd_waves(BF), BF ? 2 : 4) void k_emb_fwd(
+    EmbArgs a, float *__restrict__ G0) {
+  constexpr int BT = fwd_tiles(BF), BW = fwd_waves(BF);
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   extern __shared__ float esm[];
-  float(*xs)[MT * 16][LD1 + 1] = (float(*)[MT * 16][LD1 + 1])esm;  // per wave: h1, then h2 rows
-  float *w2s = esm + 4 * MT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
+  float(*xs)[BT * 16][LD1 + 1] = (float(*)[BT * 16][LD1 + 1])esm;  // per wave: h1, then h2 rows
+  float *w2s = esm + BW * BT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
   float *w3s = w2s + LD1 * (LD0 + 4);          // [LD2][LD1 + 4]
   float *b2s = w3s + LD2 * (LD1 + 4);
   float *b3s = b2s + LD1;
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int stride = gridDim.x * 4 * 16 * MT;
-  int row0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  const int stride = gridDim.x * BW * 16 * BT;
+  int row0 = (blockIdx.x * BW + wave) * 16 * BT;
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
   stage_w<LD1, LD0>(a.W2t, w2s);
   stage_w<LD2, LD1>(a.W3t, w3s);
   __syncthreads();
   // the next tile's h1 rows are loaded while the current tile is multiplied
-  floatx4 xn[MT][C0];
+  floatx4 xn[BT][C0];
   if (row0 < P) load_h1<C0>(a.h1, row0, P, lane & 15, lane >> 4, xn);
   for (; row0 < P; row0 += stride) {
     // per-lane indices are taken afresh in every iteration from a value the
@@ -202,25 +209,25 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
     asm volatile("" : "+v"(lane_it));
     const int r = lane_it & 15, g = lane_it >> 4;
     float(*xw)[LD1 + 1] = xs[wave];
-    floatx4 x0[MT][C0];
+    floatx4 x0[BT][C0];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int c = 0; c < C0; ++c) x0[mt][c] = xn[mt][c];
     if (row0 + stride < P) load_h1<C0>(a.h1, row0 + stride, P, r, g, xn);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int c = 0; c < C0; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
-    floatx4 acc1[MT][C1];
+    floatx4 acc1[BT][C1];
     layer<C0, C1, BF, T0, LD0 + 4>(w2s, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
-    floatx4 x1[MT][C1];
+    floatx4 x1[BT][C1];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < C1; ++nt)
 #pragma unroll
@@ -232,16 +239,16 @@ __global__ __launch_bounds__(256, 2) void k_emb_fwd(EmbArgs a, float *__restrict
         }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < C1; ++nt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
-    floatx4 acc2[MT][C2];
+    floatx4 acc2[BT][C2];
     layer<C1, C2, BF, T1, LD1 + 4>(w3s, r, g, x1, acc2);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
+    for (int mt = 0; mt < BT; ++mt) {
       const int row = row0 + mt * 16 + r;
       if (row >= P) continue;
 #pragma unroll
@@ -545,18 +552,21 @@ unsigned resident_blocks(K k, size_t lds = 0, int threads = 256) {
 }
 
 template <int C0, int C1, int C2, bool BF, int T0 = 4, int T1 = 4, int T2 = 4>
-void emb_fwd_grid(const EmbArgs &a, long tiles, float *G0, hipStream_t s) {
-  constexpr size_t lds = sizeof(float) * emb_fwd_lds_floats<C0, C1, C2>();
+void emb_fwd_grid(const EmbArgs &a, long rows, float *G0, hipStream_t s) {
+  constexpr size_t lds = sizeof(float) * emb_fwd_lds_floats<C0, C1, C2, BF>();
+  constexpr int threads = 64 * fwd_waves(BF);
+  constexpr long per_block = 16L * fwd_tiles(BF) * fwd_waves(BF);  // rows per block and round
+  const long tiles = (rows + per_block - 1) / per_block;
   static unsigned cap = 0;
   if (cap == 0) {
     if (lds > 65536)
       (void)hipFuncSetAttribute((const void *)k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    cap = resident_blocks(k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>, lds);
+    cap = resident_blocks(k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>, lds, threads);
   }
   const unsigned blocks = (unsigned)(tiles < (long)cap ? tiles : (long)cap);
-  hipLaunchKernelGGL((k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(256), lds, s,
-                     a, G0);
+  hipLaunchKernelGGL((k_emb_fwd<C0, C1, C2, BF, T0, T1, T2>), dim3(blocks), dim3(threads), lds,
+                     s, a, G0);
 }
 
 template <int C0, int C1, int C2, bool BF, int T0 = 4, int T1 = 4, int T2 = 4>
@@ -591,14 +601,14 @@ bool short_tails(const EmbLaunch &e) {
 void launch_emb_fwd(const EmbLaunch &e, float *G0, hipStream_t s) {
   EmbArgs a{e.h1, e.W2t, e.b2, e.W3t, e.b3, e.W2b, e.W3b, e.ws, e.n0, e.n1, e.n2, e.res2, e.res3,
             e.Pptr};
-  const long tiles = ((long)e.Pmax + 64 * MT - 1) / (64 * MT);
-  if (tiles == 0) return;
+  const long rows = e.Pmax;
+  if (rows <= 0) return;
   const bool st = is_student_widths(pad16(e.n0), pad16(e.n1), pad16(e.n2));
-  if (st && e.bf16) emb_fwd_grid<1, 2, 4, true>(a, tiles, G0, s);
-  else if (st) emb_fwd_grid<1, 2, 4, false>(a, tiles, G0, s);
-  else if (e.bf16) emb_fwd_grid<2, 4, 7, true>(a, tiles, G0, s);
-  else if (short_tails(e)) emb_fwd_grid<2, 4, 7, false, 3, 1, 1>(a, tiles, G0, s);
-  else emb_fwd_grid<2, 4, 7, false>(a, tiles, G0, s);
+  if (st && e.bf16) emb_fwd_grid<1, 2, 4, true>(a, rows, G0, s);
+  else if (st) emb_fwd_grid<1, 2, 4, false>(a, rows, G0, s);
+  else if (e.bf16) emb_fwd_grid<2, 4, 7, true>(a, rows, G0, s);
+  else if (short_tails(e)) emb_fwd_grid<2, 4, 7, false, 3, 1, 1>(a, rows, G0, s);
+  else emb_fwd_grid<2, 4, 7, false>(a, rows, G0, s);
 }
 
 void launch_emb_bwd(const EmbLaunch &e, const float *dG0, float *gs, hipStream_t s) {
