@@ -504,6 +504,9 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   // dh1 = du2 W2^T + res^T(dh2) ; du1 = dh1 (1 - h1^2) ; gs = du1 . ws
   floatx4 acc0[BT][C0];
   layer_t<C1, C0, BF, T1, LD0 + 4>(w2s, r, g, du2, acc0);
+  // one-tile wavefronts read their h1 rows again (from L2) rather than hold
+  // them in registers through the adjoint, which spilled at 128 registers
+  if constexpr (BT == 1) load_h1<C0>(a.h1, row0, P, r, g, x0);
 #pragma unroll
   for (int mt = 0; mt < BT; ++mt) {
     float s = 0.f;
