@@ -664,8 +664,8 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   RUN("cell_bin", launch_cell_bin(d_coords, nall, grid, w.atom_cell, w.cell_count, s));
   RUN("cell_scan", launch_scan(w.cell_count, grid.ncell, w.cell_start, s));
   RUN("cell_fill", launch_cell_fill(w.atom_cell, nall, w.cell_start, w.cell_fill, w.cell_atoms, s));
-  RUN("nlist", launch_nlist(d_coords, nloc, nall, grid, m->rcut, sel, w.atom_cell, w.cell_start,
-                            w.cell_atoms, w.nlist, w.nnei, m->flags, s));
+  RUN("nlist", launch_nlist(d_coords, nloc, nall, grid, m->rcut, sel, w.cell_start, w.cell_atoms,
+                            w.nlist, w.nnei, m->flags, s));
   RUN("pair_scan", launch_scan(w.nnei, nloc, w.pair_off, s));
   if (m->cap_pairs < 0 || m->want_pairs > m->cap_pairs || m->cap_pairs_nloc != m->cap_nloc) {
     // lay the pair arena out from this step's pair count (the only blocking

@@ -59,8 +59,8 @@ void launch_scan(const int *in, int n, int *out_excl, hipStream_t s);  // out[n]
 void launch_cell_fill(const int *atom_cell, int nall, const int *cell_start, int *cell_fill,
                       int *cell_atoms, hipStream_t s);
 void launch_nlist(const double *coords, int nloc, int nall, CellGrid grid, double rcut,
-                  int sel, const int *atom_cell, const int *cell_start, const int *cell_atoms,
-                  int *nlist, int *nnei, DevFlags *flags, hipStream_t s);
+                  int sel, const int *cell_start, const int *cell_atoms, int *nlist, int *nnei,
+                  DevFlags *flags, hipStream_t s);
 // Per pair: geometry record and the first embedding layer
 // h1 = tanh(type_table[t_j][t_i] + ws * s), 25 -> stride 32.
 void launch_env_embed1(const double *coords, const int32_t *types, CellGrid grid, int nloc,

@@ -418,10 +418,9 @@ void launch_cell_fill(const int *atom_cell, int nall, const int *cell_start, int
 }
 
 void launch_nlist(const double *coords, int nloc, int nall, CellGrid grid, double rcut, int sel,
-                  const int *atom_cell, const int *cell_start, const int *cell_atoms, int *nlist,
-                  int *nnei, DevFlags *flags, hipStream_t s) {
+                  const int *cell_start, const int *cell_atoms, int *nlist, int *nnei,
+                  DevFlags *flags, hipStream_t s) {
   if (nall <= 0) return;
-  (void)atom_cell;
   const int ncell = grid.nc[0] * grid.nc[1] * grid.nc[2];
   hipLaunchKernelGGL(k_nlist, dim3(ncell), dim3(kWave * kCellWaves), 0, s, coords, nloc, grid,
                      rcut * rcut, sel, cell_start, cell_atoms, nlist, nnei, flags);
