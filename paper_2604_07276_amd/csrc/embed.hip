@@ -11,6 +11,8 @@
 // lookups leaves the registers.  The adjoint recomputes h2 and the tanh
 // outputs from h1 instead of storing them, and ends with the scalar
 // dE/ds = sum_o dE/du1[o] * ws[o] per pair.
+#include <type_traits>
+
 #include "dpa1_internal.h"
 
 namespace dpa1 {
@@ -44,8 +46,8 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const floatx4 &lo, const floatx4 &hi
 // instead of four: in step s lane group g carries depth 16 (KCH - 1) + 4 s + g
 // on both operands (W loaded at that depth, x taken from the lane that holds
 // it: lane r + 16 s, element g).
-template <int KCH, int NTILE, bool BF, int KT, int LDW = KCH * 16, int MT>
-__device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
+template <int KCH, int NTILE, bool BF, int KT, int LDW = KCH * 16, int MT, typename WT>
+__device__ __forceinline__ void layer(const WT *__restrict__ W, int r, int g,
                                       const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -85,10 +87,17 @@ __device__ __forceinline__ void layer(const float *__restrict__ W, int r, int g,
       for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(x[mt][c], pair ? x[mt][pair ? c + 1 : c] : z);
 #pragma unroll
       for (int nt = 0; nt < NTILE; ++nt) {
-        const float *wp = W + (size_t)(nt * 16 + r) * LDW + 16 * c + 4 * g;
-        const floatx4 w0 = *(const floatx4 *)wp;
-        const floatx4 w1 = pair ? *(const floatx4 *)(wp + 16) : z;
-        const bf16x8 wb = to_bf16x8(w0, w1);
+        const WT *wp = W + (size_t)(nt * 16 + r) * LDW + 16 * c + 4 * g;
+        bf16x8 wb;
+        if constexpr (std::is_same<WT, __bf16>::value) {  // staged in BF16 already
+          const bf16x4 w0 = *(const bf16x4 *)wp;
+          const bf16x4 w1 = pair ? *(const bf16x4 *)(wp + 16) : to_bf16(z);
+          wb = __builtin_shufflevector(w0, w1, 0, 1, 2, 3, 4, 5, 6, 7);
+        } else {
+          const floatx4 w0 = *(const floatx4 *)wp;
+          const floatx4 w1 = pair ? *(const floatx4 *)(wp + 16) : z;
+          wb = to_bf16x8(w0, w1);
+        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, xb[mt], acc[mt][nt], 0, 0, 0);
@@ -159,17 +168,35 @@ constexpr int fwd_tiles(bool bf) { return bf ? 2 : 1; }
 constexpr int fwd_waves(bool bf) { return bf ? 4 : 8; }
 
 template <int C0, int C1, int C2, bool BF>
-constexpr int emb_fwd_lds_floats() {
-  return fwd_waves(BF) * fwd_tiles(BF) * 16 * (C1 * 16 + 1) + C1 * 16 * (C0 * 16 + 4) +
-         C2 * 16 * (C1 * 16 + 4) + C1 * 16 + C2 * 16;
-}
+constexpr int emb_fwd_lds_floats();
 
-template <int N, int K>
-__device__ __forceinline__ void stage_w(const float *__restrict__ W, float *dst) {
+// W [N][K] into LDS with row stride LDD: FP32, or BF16 (rounded to nearest
+// even once here instead of at every use; the same values)
+template <int N, int K, int LDD, typename WT>
+__device__ __forceinline__ void stage_w(const float *__restrict__ W, WT *dst) {
   for (int idx = threadIdx.x; idx < N * (K / 4); idx += blockDim.x) {
     const int row = idx / (K / 4), c4 = idx % (K / 4);
-    *(float4 *)(dst + row * (K + 4) + 4 * c4) = *(const float4 *)(W + (size_t)row * K + 4 * c4);
+    const floatx4 v = *(const floatx4 *)(W + (size_t)row * K + 4 * c4);
+    if constexpr (std::is_same<WT, __bf16>::value)
+      *(bf16x4 *)(dst + row * LDD + 4 * c4) = to_bf16(v);
+    else
+      *(floatx4 *)(dst + row * LDD + 4 * c4) = v;
   }
+}
+
+// LDS row strides (elements) of the staged W2^T [LD1][LD0] and W3^T [LD2][LD1]
+// and their size in floats: FP32 rows padded by 4, BF16 rows by 8 (16-byte
+// aligned rows either way)
+constexpr int w_ld(int k, bool bf) { return bf ? k + 8 : k + 4; }
+constexpr int w_floats(int c0, int c1, int c2, bool bf) {
+  return bf ? (c1 * 16 * w_ld(c0 * 16, true) + c2 * 16 * w_ld(c1 * 16, true)) / 2
+            : c1 * 16 * w_ld(c0 * 16, false) + c2 * 16 * w_ld(c1 * 16, false);
+}
+
+template <int C0, int C1, int C2, bool BF>
+constexpr int emb_fwd_lds_floats() {
+  return fwd_waves(BF) * fwd_tiles(BF) * 16 * (C1 * 16 + 1) + w_floats(C0, C1, C2, BF) +
+         C1 * 16 + C2 * 16;
 }
 
 // Persistent over row tiles (the grid holds what the device keeps resident,
@@ -185,9 +212,11 @@ __global__ __launch_bounds__(64 * fwd_waves(BF), BF ? 2 : 4) void k_emb_fwd(
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   extern __shared__ float esm[];
   float(*xs)[BT * 16][LD1 + 1] = (float(*)[BT * 16][LD1 + 1])esm;  // per wave: h1, then h2 rows
-  float *w2s = esm + BW * BT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
-  float *w3s = w2s + LD1 * (LD0 + 4);          // [LD2][LD1 + 4]
-  float *b2s = w3s + LD2 * (LD1 + 4);
+  using WT = typename std::conditional<BF, __bf16, float>::type;
+  constexpr int LW2 = w_ld(LD0, BF), LW3 = w_ld(LD1, BF);
+  WT *w2s = (WT *)(esm + BW * BT * 16 * (LD1 + 1));  // [LD1][LW2]
+  WT *w3s = w2s + LD1 * LW2;                          // [LD2][LW3]
+  float *b2s = esm + BW * BT * 16 * (LD1 + 1) + w_floats(C0, C1, C2, BF);
   float *b3s = b2s + LD1;
   const int P = *a.Pptr;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -195,8 +224,8 @@ __global__ __launch_bounds__(64 * fwd_waves(BF), BF ? 2 : 4) void k_emb_fwd(
   int row0 = (blockIdx.x * BW + wave) * 16 * BT;
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
-  stage_w<LD1, LD0>(a.W2t, w2s);
-  stage_w<LD2, LD1>(a.W3t, w3s);
+  stage_w<LD1, LD0, LW2>(a.W2t, w2s);
+  stage_w<LD2, LD1, LW3>(a.W3t, w3s);
   __syncthreads();
   // the next tile's h1 rows are loaded while the current tile is multiplied
   floatx4 xn[BT][C0];
@@ -223,7 +252,7 @@ __global__ __launch_bounds__(64 * fwd_waves(BF), BF ? 2 : 4) void k_emb_fwd(
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][16 * c + 4 * g + v] = x0[mt][c][v];
     floatx4 acc1[BT][C1];
-    layer<C0, C1, BF, T0, LD0 + 4>(w2s, r, g, x0, acc1);
+    layer<C0, C1, BF, T0, LW2>(w2s, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
     floatx4 x1[BT][C1];
 #pragma unroll
@@ -245,7 +274,7 @@ __global__ __launch_bounds__(64 * fwd_waves(BF), BF ? 2 : 4) void k_emb_fwd(
 #pragma unroll
         for (int v = 0; v < 4; ++v) xw[mt * 16 + r][nt * 16 + 4 * g + v] = x1[mt][nt][v];
     floatx4 acc2[BT][C2];
-    layer<C1, C2, BF, T1, LD1 + 4>(w3s, r, g, x1, acc2);
+    layer<C1, C2, BF, T1, LW3>(w3s, r, g, x1, acc2);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < BT; ++mt) {
@@ -270,8 +299,8 @@ __global__ __launch_bounds__(64 * fwd_waves(BF), BF ? 2 : 4) void k_emb_fwd(
 // acc[mt][nt] = sum_k W[nt*16 + r][k] x[mt][k] with W given by its transpose
 // Wt[k][n] (row stride LDT, in LDS): the adjoint products read the forward's
 // staged operand.  Same operand values and MFMA order as layer() on W.
-template <int KCH, int NTILE, bool BF, int KT, int LDT, int MT>
-__device__ __forceinline__ void layer_t(const float *Wt, int r, int g,
+template <int KCH, int NTILE, bool BF, int KT, int LDT, int MT, typename WT>
+__device__ __forceinline__ void layer_t(const WT *Wt, int r, int g,
                                         const floatx4 (&x)[MT][KCH], floatx4 (&acc)[MT][NTILE]) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -310,14 +339,23 @@ __device__ __forceinline__ void layer_t(const float *Wt, int r, int g,
       for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(x[mt][c], pair ? x[mt][pair ? c + 1 : c] : z);
 #pragma unroll
       for (int nt = 0; nt < NTILE; ++nt) {
-        const float *wp = Wt + (16 * c + 4 * g) * LDT + nt * 16 + r;
-        floatx4 w0, w1;
+        const WT *wp = Wt + (16 * c + 4 * g) * LDT + nt * 16 + r;
+        bf16x8 wb;
+        if constexpr (std::is_same<WT, __bf16>::value) {  // staged in BF16 already
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          w0[v] = wp[v * LDT];
-          w1[v] = pair ? wp[(16 + v) * LDT] : 0.f;
+          for (int v = 0; v < 4; ++v) {
+            wb[v] = wp[v * LDT];
+            wb[4 + v] = pair ? wp[(16 + v) * LDT] : (__bf16)0.f;
+          }
+        } else {
+          floatx4 w0, w1;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            w0[v] = wp[v * LDT];
+            w1[v] = pair ? wp[(16 + v) * LDT] : 0.f;
+          }
+          wb = to_bf16x8(w0, w1);
         }
-        const bf16x8 wb = to_bf16x8(w0, w1);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, xb[mt], acc[mt][nt], 0, 0, 0);
@@ -348,8 +386,8 @@ constexpr int bwd_waves(bool bf) { return bf ? 4 : 8; }  // wavefronts per workg
 
 template <int C0, int C1, int C2, bool BF>
 constexpr int emb_bwd_lds_floats() {
-  return bwd_waves(BF) * bwd_tiles(BF) * 16 * (C1 * 16 + 1) + C1 * 16 * (C0 * 16 + 4) +
-         C2 * 16 * (C1 * 16 + 4) + C1 * 16 + C2 * 16 + C0 * 16;
+  return bwd_waves(BF) * bwd_tiles(BF) * 16 * (C1 * 16 + 1) + w_floats(C0, C1, C2, BF) +
+         C1 * 16 + C2 * 16 + C0 * 16;
 }
 
 // Adjoint of layers 2-3 with their forward recomputed, persistent like the
@@ -366,9 +404,11 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   constexpr int LD0 = C0 * 16, LD1 = C1 * 16, LD2 = C2 * 16;
   extern __shared__ float esm[];
   float(*xs)[BT * 16][LD1 + 1] = (float(*)[BT * 16][LD1 + 1])esm;  // per wave: h1, then folds
-  float *w2s = esm + BW * BT * 16 * (LD1 + 1);  // [LD1][LD0 + 4]
-  float *w3s = w2s + LD1 * (LD0 + 4);          // [LD2][LD1 + 4]
-  float *b2s = w3s + LD2 * (LD1 + 4);
+  using WT = typename std::conditional<BF, __bf16, float>::type;
+  constexpr int LW2 = w_ld(LD0, BF), LW3 = w_ld(LD1, BF);
+  WT *w2s = (WT *)(esm + BW * BT * 16 * (LD1 + 1));  // [LD1][LW2]
+  WT *w3s = w2s + LD1 * LW2;                          // [LD2][LW3]
+  float *b2s = esm + BW * BT * 16 * (LD1 + 1) + w_floats(C0, C1, C2, BF);
   float *b3s = b2s + LD1;
   float *wss = b3s + LD2;
   const int P = *a.Pptr;
@@ -377,8 +417,8 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   stage_vec<LD1>(a.b2, b2s);
   stage_vec<LD2>(a.b3, b3s);
   stage_vec<LD0>(a.ws, wss);
-  stage_w<LD1, LD0>(a.W2t, w2s);
-  stage_w<LD2, LD1>(a.W3t, w3s);
+  stage_w<LD1, LD0, LW2>(a.W2t, w2s);
+  stage_w<LD2, LD1, LW3>(a.W3t, w3s);
   __syncthreads();
   // per-lane indices taken afresh in every iteration, as in the forward
   for (int row0 = (blockIdx.x * BW + wave) * 16 * BT; row0 < P; row0 += stride) {
@@ -399,7 +439,7 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   floatx4 t1[BT][C1], x1[BT][C1];
   {
     floatx4 acc1[BT][C1];
-    layer<C0, C1, BF, T0, LD0 + 4>(w2s, r, g, x0, acc1);
+    layer<C0, C1, BF, T0, LW2>(w2s, r, g, x0, acc1);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int mt = 0; mt < BT; ++mt)
@@ -417,7 +457,7 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   floatx4 d2[BT][C2];  // tanh output of layer 3, then dE/du3
   {
     floatx4 acc2[BT][C2];
-    layer<C1, C2, BF, T1, LD1 + 4>(w3s, r, g, x1, acc2);
+    layer<C1, C2, BF, T1, LW3>(w3s, r, g, x1, acc2);
 #pragma unroll
     for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
@@ -464,7 +504,7 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   floatx4 du2[BT][C1];
   {
     floatx4 acc[BT][C1];
-    layer_t<C2, C1, BF, T2, LD1 + 4>(w3s, r, g, d2, acc);
+    layer_t<C2, C1, BF, T2, LW3>(w3s, r, g, d2, acc);
 #pragma unroll
     for (int mt = 0; mt < BT; ++mt)
 #pragma unroll
@@ -503,7 +543,7 @@ __global__ __launch_bounds__(64 * bwd_waves(BF), BF ? 2 : 4) void k_emb_bwd(
   }
   // dh1 = du2 W2^T + res^T(dh2) ; du1 = dh1 (1 - h1^2) ; gs = du1 . ws
   floatx4 acc0[BT][C0];
-  layer_t<C1, C0, BF, T1, LD0 + 4>(w2s, r, g, du2, acc0);
+  layer_t<C1, C0, BF, T1, LW2>(w2s, r, g, du2, acc0);
   // one-tile wavefronts read their h1 rows again (from L2) rather than hold
   // them in registers through the adjoint, which spilled at 128 registers
   if constexpr (BT == 1) load_h1<C0>(a.h1, row0, P, r, g, x0);
