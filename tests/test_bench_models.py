@@ -83,3 +83,16 @@ def test_bf16_byte_model_halves_only_the_bf16_stored_tensors():
         assert b16[f"attn_fwd_n{c}"][0] < b32[f"attn_fwd_n{c}"][0] or b32[f"attn_fwd_n{c}"][0] == 0
     assert bench.byte_model(nn, SHAPE)["qkv_bwd"][0] == b32["qkv_bwd"][0]
     assert M == 100
+
+
+def test_descriptor_adjoint_bytes_count_its_operands_once():
+    nn = _nnei(5)
+    P, nloc = float(nn.sum()), len(nn)
+    M, d, axis = SHAPE["M"], SHAPE["dattn"], SHAPE["axis"]
+    for bf16, t in ((False, 4.0), (True, 2.0)):
+        b, launches = bench.byte_model(nn, SHAPE, bf16=bf16)["desc_oproj_bwd"]
+        # G, xhat, 1/std and R~ in; the residual gradient, dR~ and dO out; dD and T per centre
+        want = P * (4.0 * (2 * M + 1) + 16.0 + 4.0 * M + 16.0 + t * d) + nloc * 4.0 * (M * axis + 4 * M)
+        assert launches == 1
+        assert abs(b - want) <= 1e-9 * want
+
