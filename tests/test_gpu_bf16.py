@@ -66,6 +66,40 @@ def test_bf16_parity_192_atoms(model, oracle_model):
     assert rmse > 1e-6
 
 
+def test_bf16_parity_98_features(tmp_path):
+    """BF16 mode on a model with 98 embedding features (widths 25 -> 50 -> 98):
+    the BF16 kernels that take the last 16-wide feature chunk with two real
+    features (QKV projection, forward with the projection, descriptor adjoint
+    with dO) and the fused embedding kernels without a last-layer residual,
+    against the FP64 oracle at the same bars."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_07276_amd import binding
+    p = str(tmp_path / "emb98.bin")
+    synth.make_weights(p, seed=3, shape=synth.ModelShape(emb=(25, 50, 98), n_attn=2))
+    om = orc.load_model(p)
+    s = synth.parity_system(1)
+    say("case: BF16 mode, 98 embedding features, 192-atom system vs the FP64 oracle")
+    r = orc.compute(om, s.coords, s.types, s.box, 192, 0, RC, SEL)
+    m = binding.Model(p, RC, SEL)
+    try:
+        m.set_precision(binding.PREC_BF16)
+        E, F, V, _ = m.compute(s.coords, s.types, s.box, 192, 0)
+    finally:
+        m.close()
+    dF = F - r.forces
+    rmse = np.sqrt((dF ** 2).mean())
+    dE = abs(E - r.energy) / 192
+    say(f"[bf16 emb98] dE/N={dE:.2e} force RMSE={rmse:.2e} max={np.abs(dF).max():.2e} "
+        f"(|F|rms={np.sqrt((r.forces ** 2).mean()):.2e})")
+    assert dE <= E_TOL
+    assert rmse <= F_RMSE
+    assert np.abs(dF).max() <= 0.1
+    assert np.abs(V - r.virial).max() / 192 <= E_TOL
+    assert rmse > 1e-6
+
+
 def test_bf16_protein_15668(model, oracle_model):
     """Whole 15,668-atom frame in BF16 against the FP32 path (itself within
     1e-4 eV/A of the oracle), and e_i of 400 random centres against the oracle."""
