@@ -756,8 +756,15 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   {
     const Linear &L = m->fitl[0];
     GemmArgs a{w.dmat, m->ldD, L.Wt, m->ldD, L.ldout, L.fout, nullptr, nloc, m->bf16};
-    RUN("fit_fwd", gemm_tanh_res(a, m->fb0, d_types, L.ldout, nullptr, 0, RES_NONE, 0, w.z[0],
-                                 L.ldout, w.tf[0], L.ldout, s));
+    // few centres (a small domain): the long-k first layer split over k, with
+    // the attention adjoint's dQKV buffer (unused until the adjoint) as scratch
+    const size_t scratch = (size_t)(m->cap_pairs + 64) * 3 * std::max(m->dattn, 16);
+    RUN("fit_fwd", {
+      if (!gemm_tanh_res_split(a, m->fb0, d_types, L.ldout, w.z[0], L.ldout, w.tf[0], L.ldout,
+                               w.dqkv, m->cap_pairs >= 0 ? scratch : 0, s))
+        gemm_tanh_res(a, m->fb0, d_types, L.ldout, nullptr, 0, RES_NONE, 0, w.z[0], L.ldout,
+                      w.tf[0], L.ldout, s);
+    });
   }
   for (int l = 1; l < nf; ++l) {
     const Linear &L = m->fitl[l];

@@ -85,6 +85,7 @@ struct GemmArgs {
   int bf16;       // 1: BF16 matrix-core operands (FP32 accumulate), 0: FP32
   int xbf16;      // with bf16: X is stored in BF16 (row stride ldx in elements)
   int kreal;      // 0, or the depth up to which X and W hold data (zeros past it)
+  int kslice;     // 0, or split k: grid slice z covers depths [z kslice, (z + 1) kslice)
 };
 
 enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_FOLD = 4 };
@@ -94,6 +95,15 @@ enum ResMode { RES_NONE = 0, RES_IDENT = 1, RES_DOUBLE = 2, RES_BCAST = 3, RES_F
 void gemm_tanh_res(const GemmArgs &a, const float *bias, const int32_t *row_type, int bias_ld,
                    const float *res, int ldr, int res_mode, int res_fin, float *y, int ldy,
                    float *tout, int ldt, hipStream_t s);
+// The same product split over k for few rows and a long k (the first fitting
+// layer of a small domain): slices of the k range run as separate
+// workgroups into partial sums in scratch, one pass adds them in slice
+// order and applies the epilogue.  Returns false, launching nothing, when
+// the shape does not call for it or scratch (floats) is too small; the
+// caller then runs gemm_tanh_res.
+bool gemm_tanh_res_split(const GemmArgs &a, const float *bias, const int32_t *row_type,
+                         int bias_ld, float *y, int ldy, float *tout, int ldt, float *scratch,
+                         size_t scratch_floats, hipStream_t s);
 // y = acc + b (b may be null); ybf16: y stored in BF16
 void gemm_linear(const GemmArgs &a, const float *bias, float *y, int ldy, hipStream_t s,
                  int ybf16 = 0);

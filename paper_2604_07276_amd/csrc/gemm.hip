@@ -99,6 +99,10 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
   stage_cols<Epi, NT>(epi, nt0, a.Npad, cs);
   __syncthreads();
   const int ntt = a.Npad / 16;
+  // k range of this workgroup: all of K, or with split k (shared-W paths
+  // only, kslice a multiple of the chunk depth) slice blockIdx.z
+  const int kbeg = a.kslice ? (int)blockIdx.z * a.kslice : 0;
+  const int kend = a.kslice ? min(a.K, kbeg + a.kslice) : a.K;
   // W staging: thread tid moves float4 q = tid + 256 j of the chunk, row
   // q / QPR of the block's W^T rows, k quad q % QPR (column tiles past the
   // last one stage a duplicate of tile 0; their outputs are never stored).
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
         // a quad of the second half past K (16-deep tail) reads the first
         // half's address and stages zeros
         const int q = tid + 256 * j < NQ ? tid + 256 * j : 0;  // as in wsrc
-        const bool ok = KC == 16 || k + 4 * (q % QPR) < a.K;
+        const bool ok = KC == 16 || k + 4 * (q % QPR) < kend;
         const float4 v = *(const float4 *)(wsrc[j] + (ok ? k : k - 16));
         wst[j] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
       }
@@ -175,19 +179,19 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         xn[mt][0] = ldx4<BF>(xrow[mt], k0);
-        xn[mt][1] = ldx4<BF>(xrow[mt], k0 + 16 < a.K ? k0 + 16 : k0);
+        xn[mt][1] = ldx4<BF>(xrow[mt], k0 + 16 < kend ? k0 + 16 : k0);
       }
     };
-    wload(0);
-    xload(0);
+    wload(kbeg);
+    xload(kbeg);
     wstore(0);
     __syncthreads();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) xb[mt] = to_bf16x8(xn[mt][0], xn[mt][1]);
     int b = 0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < a.K; k0 += KC) {
-      const bool more = k0 + KC < a.K;  // uniform
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+      const bool more = k0 + KC < kend;  // uniform
       if (more) {
         wload(k0 + KC);
         xload(k0 + KC);
@@ -222,16 +226,16 @@ __global__ __launch_bounds__(256, MT >= 4 ? 2 : 3) void k_gemm(GemmArgs a, Epi e
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int h = 0; h < H; ++h)
-          x[mt][h] = ldx4<BF>(xrow[mt], k0 + 16 * h < a.K ? k0 + 16 * h : k0);
+          x[mt][h] = ldx4<BF>(xrow[mt], k0 + 16 * h < kend ? k0 + 16 * h : k0);
     };
-    wload(0);
-    xload(0, xv);
+    wload(kbeg);
+    xload(kbeg, xv);
     wstore(0);
     __syncthreads();
     int b = 0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < a.K; k0 += KC) {
-      const bool more = k0 + KC < a.K;  // uniform
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+      const bool more = k0 + KC < kend;  // uniform
       if (more) {
         wload(k0 + KC);
         xload(k0 + KC, xn);
@@ -742,6 +746,32 @@ struct EpiLinear {
   }
 };
 
+// Split k: the raw partial sums of slice blockIdx.z, y + z * slice.
+struct EpiPartial {
+  static constexpr int kLds = 0;
+  static constexpr int kCols = 1;
+  float *y;
+  int ldy;
+  size_t slice;
+  __device__ __forceinline__ const float *col(int) const { return nullptr; }
+  template <int MT, int NT>
+  __device__ __forceinline__ void apply(floatx4 (&acc)[MT][NT], int row0, int nt0, int ntt,
+                                        int lane, int M, const float *) const {
+    const int r = lane & 15, g = lane >> 4;
+    float *yz = y + blockIdx.z * slice;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = row0 + mt * 16 + r;
+      if (row >= M) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt0 + nt >= ntt) continue;
+        *(floatx4 *)(yz + (size_t)row * ldy + (nt0 + nt) * 16 + 4 * g) = acc[mt][nt];
+      }
+    }
+  }
+};
+
 // y = tanh(acc + b) + res ; the bias is per column, or per row type when
 // row_type is set (bias [ntypes][bias_ld], read from global memory).
 struct EpiTanhRes {
@@ -1215,6 +1245,33 @@ void launch_lds(const GemmArgs &a, const Epi &e, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm_lds<MT, NT, KCH, Epi, 0, 4>), dim3(gx, gy), dim3(256), lds, s, a, e);
 }
 
+// Split k, second pass: each lane adds its tile values over the slices in
+// slice order and applies the product's own epilogue to the sums.
+template <int NT, class Epi>
+__global__ __launch_bounds__(256) void k_splitk_finish(const float *__restrict__ part, int nslice,
+                                                     size_t slice, int ldp, int M, int Npad,
+                                                     Epi epi) {
+  __shared__ float cs[Epi::kCols * NT * 16];
+  const int nt0 = blockIdx.y * NT;
+  stage_cols<Epi, NT>(epi, nt0, Npad, cs);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int row0 = (blockIdx.x * 4 + wave) * 16;
+  if (row0 >= M) return;  // no barrier follows
+  const int ntt = Npad / 16;
+  const size_t rb = (size_t)(row0 + r < M ? row0 + r : 0) * ldp;
+  floatx4 acc[1][NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int tile = nt0 + nt < ntt ? nt0 + nt : 0;
+    acc[0][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int z = 0; z < nslice; ++z)
+      acc[0][nt] += *(const floatx4 *)(part + z * slice + rb + tile * 16 + 4 * g);
+  }
+  epi.template apply<1, NT>(acc, row0, nt0, ntt, lane, M, cs);
+}
+
 // Rows per wave: two 16-row tiles for the large pair-batched products,
 // one for the centre-batched fitting net (more blocks for fewer rows).
 template <class Epi>
@@ -1269,6 +1326,35 @@ void gemm_tanh_res(const GemmArgs &a, const float *bias, const int32_t *row_type
                    float *tout, int ldt, hipStream_t s) {
   EpiTanhRes e{bias, row_type, bias_ld, res, ldr, res_mode, res_fin, y, ldy, tout, ldt, a.Nreal};
   run(a, e, false, s);
+}
+
+bool gemm_tanh_res_split(const GemmArgs &a, const float *bias, const int32_t *row_type,
+                         int bias_ld, float *y, int ldy, float *tout, int ldt, float *scratch,
+                         size_t scratch_floats, hipStream_t s) {
+  // few rows: fewer than 64 row blocks of 64, so the unsplit product would
+  // occupy a fraction of the CUs for the whole k loop
+  constexpr int kMaxRows = 4096, kSlices = 8, NT = 4;
+  const int M = a.Mmax;
+  if (a.Mptr || M <= 0 || M >= kMaxRows || a.K < 512 || (a.bf16 && a.xbf16) || !scratch)
+    return false;
+  const int kslice = ((a.K + kSlices - 1) / kSlices + 31) / 32 * 32;  // whole 32-deep chunks
+  const int nslice = (a.K + kslice - 1) / kslice;
+  const size_t slice = (size_t)M * a.Npad;
+  if ((size_t)nslice * slice > scratch_floats) return false;
+  GemmArgs as = a;
+  as.kslice = kslice;
+  as.kreal = 0;
+  const EpiPartial ep{scratch, a.Npad, slice};
+  const int ntt = a.Npad / 16;
+  const dim3 grid((unsigned)((M + 63) / 64), (unsigned)((ntt + NT - 1) / NT), (unsigned)nslice);
+  if (a.bf16)
+    hipLaunchKernelGGL((k_gemm<1, NT, EpiPartial, 1>), grid, dim3(256), 0, s, as, ep);
+  else
+    hipLaunchKernelGGL((k_gemm<1, NT, EpiPartial, 0>), grid, dim3(256), 0, s, as, ep);
+  const EpiTanhRes e{bias, row_type, bias_ld, nullptr, 0, RES_NONE, 0, y, ldy, tout, ldt, a.Nreal};
+  hipLaunchKernelGGL((k_splitk_finish<NT, EpiTanhRes>), dim3(grid.x, grid.y), dim3(256), 0, s,
+                     scratch, nslice, slice, a.Npad, M, a.Npad, e);
+  return true;
 }
 
 void gemm_ln_res(const GemmArgs &a, const float *bias, const float *gamma, const float *beta,
