@@ -559,14 +559,24 @@ __global__ void k_fill_int(int *p, int n, int v) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
 }
-__global__ void k_init_flags(DevFlags *f, int *ccount) {
-  if (threadIdx.x == 0) {
-    f->overflow_atom = INT_MAX;
-    f->overflow_count = 0;
-    f->bad_type_atom = INT_MAX;
-    f->pair_overflow = 0;
+// Start of a step: the flags and attention class counts (block 0) and the
+// per-cell atom counters of the binning (all blocks), in one launch.
+__global__ void k_init_step(DevFlags *f, int *ccount, int *cell_count, int *cell_fill,
+                            int ncell) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      f->overflow_atom = INT_MAX;
+      f->overflow_count = 0;
+      f->bad_type_atom = INT_MAX;
+      f->pair_overflow = 0;
+    }
+    if (threadIdx.x < 8) ccount[threadIdx.x] = 0;
   }
-  if (threadIdx.x < 8) ccount[threadIdx.x] = 0;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ncell) {
+    cell_count[k] = 0;
+    cell_fill[k] = 0;
+  }
 }
 // Capacity check of the pair arena (one block): a step with more neighbour
 // pairs than the arena holds records its count and gets no pair work at all
@@ -652,15 +662,10 @@ int enqueue_forward(dp_model *m, const double *d_coords, const int32_t *d_types,
   const int *Pptr = w.pair_off + nloc;
   const int ne = (int)m->emb.size(), na = m->n_attn, nf = (int)m->fit.size();
 
-  RUN("init", hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, m->flags, w.ccount));
+  RUN("init", hipLaunchKernelGGL(k_init_step, dim3((grid.ncell + 255) / 256), dim3(256), 0, s,
+                                 m->flags, w.ccount, w.cell_count, w.cell_fill, grid.ncell));
   RUN("check_types", launch_check_types(d_types, nall, m->ntypes, m->flags, w.types_safe, s));
   d_types = w.types_safe;
-  RUN("cell_clear", {
-    hipLaunchKernelGGL(k_fill_int, dim3((grid.ncell + 255) / 256), dim3(256), 0, s,
-                       w.cell_count, grid.ncell, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3((grid.ncell + 255) / 256), dim3(256), 0, s, w.cell_fill,
-                       grid.ncell, 0);
-  });
   RUN("cell_bin", launch_cell_bin(d_coords, nall, grid, w.atom_cell, w.cell_count, s));
   RUN("cell_scan", launch_scan(w.cell_count, grid.ncell, w.cell_start, s));
   RUN("cell_fill", launch_cell_fill(w.atom_cell, nall, w.cell_start, w.cell_fill, w.cell_atoms, s));
